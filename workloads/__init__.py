@@ -1,0 +1,276 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module builds particle sets (positions, velocities, potential, kind,
+wall normals) and a plain parameter dictionary.  It holds none of the
+solver's arithmetic: both the CPU oracle and the HIP library consume what it
+returns, each converting the dictionary into its own parameter struct.
+
+Every case is a dict:
+    params : dict of physical / numerical parameters (see ``base_params``)
+    x, u   : (n, dim) float64      positions, velocities
+    phi    : (n,) float64          auxiliary potential
+    kind   : (n,) uint8            0 fluid, 1 fixed wall dummy
+    normal : (n, dim) float64      unit wall normal (dummies; zero for fluid)
+    mass   : None                  (each side derives m = rho(phi) dx^d)
+    t      : float                 initial time
+    meta   : dict                  description and sizes
+
+Geometry: particles sit on the lattice ((i+1/2) dx, (j+1/2) dx[, (k+1/2) dx]);
+walls are ``layers`` lattice layers of dummies outside the container.  The
+initial potential is the hydrostatic solution phi = G.x + H |G| (zero at the
+still-water level H), velocity zero.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+G_EARTH = 9.81
+
+
+def base_params(dim, dx, *, h_factor=1.3, c0=None, depth=1.0, gravity=None, rho0=1000.0,
+                nu=1e-4, cfl=0.2, delta=0.1, pst_R=0.2, pst_n=4.0, delta_sph=False, pst=False,
+                tic=False, fs_project=False, cont_uncorr=False, fs_mode="none", precision="fp64",
+                forcing_amp=(0.0, 0.0, 0.0), forcing_omega=0.0, domain_lo=None, domain_hi=None,
+                features=False):
+    if gravity is None:
+        gravity = [0.0, -G_EARTH, 0.0] if dim == 2 else [0.0, 0.0, -G_EARTH]
+    if c0 is None:
+        c0 = 10.0 * math.sqrt(G_EARTH * depth)
+    h = h_factor * dx
+    return {
+        "dim": dim, "dx": dx, "h": h, "c0": float(c0), "rho0": rho0, "nu": nu, "cfl": cfl,
+        "delta": delta, "pst_R": pst_R, "pst_n": pst_n,
+        "lambda_tic": 0.75, "lambda_fs_lo": 0.2, "lambda_fs_hi": 0.75, "lambda_singular": 1e-6,
+        "gravity": list(gravity), "forcing_amp": list(forcing_amp), "forcing_omega": float(forcing_omega),
+        "domain_lo": list(domain_lo) if domain_lo is not None else [0.0] * 3,
+        "domain_hi": list(domain_hi) if domain_hi is not None else [0.0] * 3,
+        "cell_size": 2.0 * h,
+        "delta_sph": bool(delta_sph), "pst": bool(pst), "tic": bool(tic),
+        "fs_project": bool(fs_project), "cont_uncorr": bool(cont_uncorr),
+        "fs_mode": fs_mode, "precision": precision, "features": bool(features),
+    }
+
+
+def _lattice(lo_idx, hi_idx, dx):
+    axes = [(np.arange(a, b) + 0.5) * dx for a, b in zip(lo_idx, hi_idx)]
+    grids = np.meshgrid(*axes, indexing="ij")
+    return np.stack([g.ravel() for g in grids], axis=1)
+
+
+def _assemble(params, xf, xd, nd, H, meta):
+    dim = params["dim"]
+    x = np.concatenate([xf, xd], axis=0).astype(np.float64)
+    n = x.shape[0]
+    kind = np.concatenate([np.zeros(len(xf), np.uint8), np.ones(len(xd), np.uint8)])
+    normal = np.zeros((n, dim))
+    normal[len(xf):] = nd
+    G = np.asarray(params["gravity"][:dim], dtype=np.float64)
+    gmag = float(np.linalg.norm(params["gravity"]))
+    phi = x @ G + H * gmag
+    meta = dict(meta)
+    meta.update({"n_fluid": int(len(xf)), "n_dummy": int(len(xd)), "H": H})
+    return {"params": params, "x": x, "u": np.zeros((n, dim)), "phi": phi, "kind": kind,
+            "normal": normal, "mass": None, "t": 0.0, "meta": meta}
+
+
+def _box_walls(dim, dx, n_cells, layers, open_top_cells=None):
+    """Dummy lattice points in a `layers`-thick shell around the box
+    [0, n_cells*dx] (axis dim-1 vertical).  With open_top_cells the vertical
+    shell stops at that many cells (no lid)."""
+    lo = [-layers] * dim
+    hi = [n + layers for n in n_cells]
+    if open_top_cells is not None:
+        hi[dim - 1] = open_top_cells
+    pts = _lattice(lo, hi, dx)
+    box_hi = np.array(n_cells, dtype=np.float64) * dx
+    inside = np.all((pts > 0.0) & (pts < box_hi), axis=1)
+    pts = pts[~inside]
+    nrm = np.zeros_like(pts)
+    for a in range(dim):
+        nrm[:, a] += (pts[:, a] < 0.0).astype(np.float64)
+        nrm[:, a] -= (pts[:, a] > box_hi[a]).astype(np.float64)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return pts, nrm
+
+
+def tank2d(dx=0.01, width=1.0, depth=0.5, wall_height=0.6, layers=3, **kw):
+    """2D hydrostatic tank with a flat bottom (1.0 m x 0.5 m water at dx = 0.01:
+    5,000 fluid particles, 678 dummies)."""
+    nx, ny, nw = round(width / dx), round(depth / dx), round(wall_height / dx)
+    kw.setdefault("depth", depth)
+    ceiling = wall_height + 0.25 * wall_height
+    params = base_params(2, dx, domain_lo=[-layers * dx, -layers * dx, 0.0],
+                         domain_hi=[width + layers * dx, ceiling, 0.0], **kw)
+    xf = _lattice([0, 0], [nx, ny], dx)
+    xd, nd = _box_walls(2, dx, [nx, nw], layers, open_top_cells=nw)
+    return _assemble(params, xf, xd, nd, depth,
+                     {"name": "tank2d", "desc": f"2D hydrostatic tank {width}x{depth} m, dx={dx}"})
+
+
+def bump2d(shape="gauss", dx=0.002, width=2.0, depth=0.5, amp=0.1, sigma=0.1, bump_width=0.4,
+           wall_height=None, layers=3, **kw):
+    """2D hydrostatic water layer over a bottom bump.  shape 'gauss':
+    b(x) = amp exp(-(x - W/2)^2 / (2 sigma^2)); 'rect': a block of height amp and
+    width bump_width; 'tri': a triangle of height amp and base bump_width."""
+    if wall_height is None:
+        wall_height = depth + 0.1 * depth
+    nx, nw = round(width / dx), round(wall_height / dx)
+    xc = 0.5 * width
+    kw.setdefault("depth", depth)
+    ceiling = wall_height * 1.25
+    params = base_params(2, dx, domain_lo=[-layers * dx, -layers * dx, 0.0],
+                         domain_hi=[width + layers * dx, ceiling, 0.0], **kw)
+
+    def bottom(x):
+        if shape == "gauss":
+            return amp * np.exp(-((x - xc) ** 2) / (2.0 * sigma ** 2))
+        if shape == "tri":
+            return np.maximum(0.0, amp * (1.0 - np.abs(x - xc) / (0.5 * bump_width)))
+        return np.where(np.abs(x - xc) <= 0.5 * bump_width, amp, 0.0)
+
+    def bottom_slope(x):
+        if shape == "gauss":
+            return -(x - xc) / sigma ** 2 * bottom(x)
+        if shape == "tri":
+            inside = np.abs(x - xc) < 0.5 * bump_width
+            return np.where(inside, -np.sign(x - xc) * amp / (0.5 * bump_width), 0.0)
+        return np.zeros_like(x)
+
+    pts = _lattice([0, 0], [nx, round(depth / dx)], dx)
+    b = bottom(pts[:, 0])
+    xf = pts[pts[:, 1] > b]
+    # dummies: the box shell plus lattice points inside the bump within `layers` cells of its surface
+    xd_box, nd_box = _box_walls(2, dx, [nx, nw], layers, open_top_cells=nw)
+    solid = pts[pts[:, 1] <= b]
+    keep = []
+    nrm = []
+    for p in solid:
+        xb = p[0]
+        if shape == "rect":
+            top_gap = amp - p[1]
+            side_gap = 0.5 * bump_width - abs(xb - xc)
+            if min(top_gap, side_gap) >= layers * dx:
+                continue
+            keep.append(p)
+            if top_gap <= side_gap:
+                nrm.append([0.0, 1.0])
+            else:
+                nrm.append([math.copysign(1.0, xb - xc), 0.0])
+        else:
+            bb = float(bottom(np.array([xb]))[0])
+            if bb - p[1] >= layers * dx:
+                continue
+            s = float(bottom_slope(np.array([xb]))[0])
+            v = np.array([-s, 1.0])
+            keep.append(p)
+            nrm.append(v / np.linalg.norm(v))
+    if keep:
+        xd = np.concatenate([xd_box, np.array(keep)], axis=0)
+        nd = np.concatenate([nd_box, np.array(nrm)], axis=0)
+    else:
+        xd, nd = xd_box, nd_box
+    return _assemble(params, xf, xd, nd, depth,
+                     {"name": f"bump2d-{shape}",
+                      "desc": f"2D {width}x{depth} m layer over a {shape} bump (amp {amp}), dx={dx}"})
+
+
+def box3d(dx, tank, fluid_hi, layers=3, name="box3d", desc="", **kw):
+    """3D closed box [0, tank] (lid included) with a fluid block
+    [0, fluid_hi] at rest; gravity along -z."""
+    n_cells = [round(t / dx) for t in tank]
+    nf = [round(f / dx) for f in fluid_hi]
+    kw.setdefault("depth", fluid_hi[2])
+    params = base_params(3, dx, domain_lo=[-layers * dx] * 3,
+                         domain_hi=[t + layers * dx for t in tank], **kw)
+    xf = _lattice([0, 0, 0], nf, dx)
+    xd, nd = _box_walls(3, dx, n_cells, layers)
+    return _assemble(params, xf, xd, nd, fluid_hi[2], {"name": name, "desc": desc})
+
+
+def dambreak3d(dx=0.01, tank=(3.22, 1.0, 1.0), column=(1.2, 1.0, 0.55), **kw):
+    """3D dam break: column at rest against the x = 0 wall of a closed tank
+    (660,000 fluid + 465,408 dummies at dx = 0.01)."""
+    kw.setdefault("c0", 30.0)
+    kw.setdefault("delta_sph", True)
+    kw.setdefault("pst", True)
+    kw.setdefault("tic", True)
+    kw.setdefault("fs_project", True)
+    kw.setdefault("cont_uncorr", True)
+    kw.setdefault("fs_mode", "exact")
+    return box3d(dx, tank, column, name="dambreak3d",
+                 desc=f"3D dam break, tank {tank}, column {column}, dx={dx}", **kw)
+
+
+def slosh_omega(length=1.0, depth=0.28, factor=1.2):
+    """Forcing frequency for a period `factor` times the first natural sloshing
+    period (linear theory: w1^2 = g k tanh(k d), k = pi / L)."""
+    k = math.pi / length
+    w1 = math.sqrt(G_EARTH * k * math.tanh(k * depth))
+    return w1 / factor
+
+
+def slosh3d(dx=0.002, tank=(1.0, 0.5, 0.56), depth=0.28, amp=0.005, **kw):
+    """3D sloshing tank forced horizontally in its own frame: G(t) = (A w^2
+    sin wt, 0, -g).  At dx = 0.002: 17,500,000 fluid + 2,047,296 dummies."""
+    kw.setdefault("delta_sph", True)
+    kw.setdefault("pst", True)
+    kw.setdefault("tic", True)
+    kw.setdefault("fs_project", True)
+    kw.setdefault("cont_uncorr", True)
+    kw.setdefault("fs_mode", "exact")
+    w = slosh_omega(tank[0], depth)
+    kw.setdefault("forcing_amp", (amp, 0.0, 0.0))
+    kw.setdefault("forcing_omega", w)
+    return box3d(dx, tank, (tank[0], tank[1], depth), name="slosh3d",
+                 desc=f"3D sloshing tank {tank}, depth {depth}, forcing A={amp} m, dx={dx}", **kw)
+
+
+def jitter(case, sigma=0.1, seed=0):
+    """Copy of `case` with fluid positions displaced by N(0, (sigma dx)^2)."""
+    c = dict(case)
+    rng = np.random.default_rng(seed)
+    x = case["x"].copy()
+    f = case["kind"] == 0
+    x[f] += rng.normal(0.0, sigma * case["params"]["dx"], size=x[f].shape)
+    c["x"] = x
+    return c
+
+
+def random_velocity(case, amp=0.1, seed=1):
+    c = dict(case)
+    rng = np.random.default_rng(seed)
+    u = case["u"].copy()
+    f = case["kind"] == 0
+    u[f] = rng.normal(0.0, amp, size=u[f].shape)
+    c["u"] = u
+    return c
+
+
+def random_potential(case, amp=1.0, seed=2):
+    c = dict(case)
+    rng = np.random.default_rng(seed)
+    c["phi"] = case["phi"] + amp * rng.normal(0.0, 1.0, size=case["phi"].shape)
+    return c
+
+
+def with_params(case, **kw):
+    c = dict(case)
+    p = dict(case["params"])
+    p.update(kw)
+    c["params"] = p
+    return c
+
+
+def cloud(n, dim, box=1.0, h=0.05, seed=0):
+    """n uniform random fluid points in [0, box]^dim (no walls)."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, box, size=(n, dim))
+    dx = h / 1.3
+    params = base_params(dim, dx, domain_lo=[0.0] * 3, domain_hi=[box] * 3, depth=box)
+    params["h"] = h
+    params["cell_size"] = 2.0 * h
+    case = _assemble(params, x, np.zeros((0, dim)), np.zeros((0, dim)), box,
+                     {"name": "cloud", "desc": f"{n} random points in [0,{box}]^{dim}"})
+    return case
