@@ -1,0 +1,324 @@
+// Internal declarations of the gfx950 WCSPH library: device-side parameter
+// blocks, the particle layout in HBM, small device math shared by the kernels
+// (kernel function, cell geometry, the cell-row walker of Algorithm 1, the
+// closed-form symmetric eigenvalues and the small linear solves).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "wbsph.h"
+
+namespace wb {
+
+constexpr int kBlock = 256;   // threads per block for streaming kernels
+constexpr int kNFeat = 16;    // classifier features per particle
+constexpr int kMaxReach = 3;  // cells searched each side: ceil(2h / R) <= 3
+
+// error bits accumulated on the device
+enum : uint32_t {
+  kErrDomain = 1u,
+  kErrNonFinite = 2u,
+  kErrCapacity = 4u,
+};
+
+// per-particle flag bits (fluid, sorted order)
+enum : uint32_t {
+  kFlagCons = 1u,       // conservative (TIC / singular) branch used
+  kFlagFS = 2u,         // free surface
+  kFlagCand = 4u,       // 0.2 < lambda <= 0.75: decided by scan or MLP
+  kFlagSingular = 8u,   // lambda_min <= lambda_singular
+  kFlagByScan = 16u,    // decided by the scan-region pass
+  kFlagByMLP = 32u,     // decided by the classifier
+};
+
+// Background grid (Sec. 3): N_a = floor((hi - lo) / R) + 1 cells per axis.
+struct Grid {
+  double lo[3];
+  double hi[3];
+  double R;
+  double invR;   // not used for cell indices (IEEE division is), only for pruning
+  int32_t N[3];
+  int32_t reach; // cells searched on each side, ceil(2h / R)
+  int64_t ncell;
+};
+
+// Physical / numerical constants as the kernels need them.
+struct Phys {
+  int32_t dim;
+  uint32_t flags;
+  int32_t fs_mode;
+  int32_t pad_;
+  double h, inv_h, two_h, two_h2;  // two_h2 = (2h)*(2h)
+  double c0, rho0, inv_c02, dx;
+  double alpha;    // Wendland normalisation 7/(4 pi h^2) or 21/(16 pi h^3)
+  double kfac;     // 5 alpha / h^2:  grad_i W_ij = kfac t^3 (x_j - x_i)
+  double w0inv;    // 1 / W(dx / h)
+  double wself;    // W(0)
+  double delta, pst_R, pst_n;
+  double lambda_tic, lambda_lo, lambda_hi, lambda_sing;
+  double grav[3], famp[3], fomega;
+  double cfl, nu, gmax;   // gmax = max_t |G(t)|
+};
+
+// Device-resident scalars (one instance in the workspace).
+struct Scalars {
+  double t;          // time at the start of the current step
+  double dt;         // current step
+  double t_rhs;      // time of the right-hand side being evaluated
+  double umax;       // sqrt of umax2 for the current right-hand side
+  unsigned long long umax2_bits;  // atomic max of |U|^2 (non-negative double bits)
+  unsigned long long pairs;       // sum of fluid neighbour counts of the last RHS
+  uint32_t err;
+  uint32_t n_cand;   // candidates listed by the pair pass
+  uint32_t n_scan;   // candidates sent to the scan pass
+  uint32_t n_fs, n_cons, n_sing, n_mlp;
+  uint32_t pad_;
+  double steps;
+};
+
+// Fluid state, FP64 path, sorted by (cell, original index).
+struct FluidF64 {
+  double *x[3], *u[3], *phi, *m;
+  double *x0[3], *u0[3], *phi0;  // stage-0 copies (SSP-RK2 second stage)
+  uint32_t *id;                  // original index
+};
+
+// Fluid state, mixed path: int cell (packed) + FP32 offset in [0, R),
+// FP32 velocity, FP64 potential; Kahan compensations and the stage-1
+// increments used by the incremental form of the second stage.
+struct FluidMixed {
+  uint32_t *cell;      // ix | iy << 11 | iz << 22
+  float *o[3], *oc[3]; // offset and its Kahan compensation
+  float *u[3], *uc[3];
+  double *phi;
+  float *m;
+  float *dx1[3], *du1[3];  // stage-1 increments dt*(U+dU), dt*a
+  double *dphi1;
+  uint32_t *id;
+};
+
+// Per-fluid outputs of one right-hand side (sorted order).
+struct Rates {
+  double *acc[3], *dphi, *dus[3], *lam[3], *nrm[3];
+  uint32_t *flags;
+  uint32_t *nnb;
+  float *feat;    // nf * 16 (all particles, SPH_F_FEATURES) or candidate rows
+  float *logit;   // nf
+};
+
+// ------------------------------------------------------------ device math
+
+__device__ __forceinline__ void body_force(const Phys &P, double t, double G[3]) {
+  double s = sin(P.fomega * t);
+  double w2 = P.fomega * P.fomega;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) G[a] = P.grav[a] + P.famp[a] * w2 * s;
+}
+
+// Cell coordinate along one axis, Eq. (ixyz): floor((x - lo) / R) with an
+// IEEE subtraction and division (no contraction), as the cell index must be
+// reproducible bit for bit.
+__device__ __forceinline__ int cell_coord(double x, double lo, double R) {
+  return (int)floor((x - lo) / R);
+}
+
+// |r|^2 summed in axis order without contraction (the neighbour test of
+// Algorithm 1 decides set membership, so it is evaluated exactly as written).
+template <int DIM>
+__device__ __forceinline__ double dist2_exact(double rx, double ry, double rz) {
+#pragma clang fp contract(off)
+  double s = rx * rx;
+  s = s + ry * ry;
+  if (DIM == 3) s = s + rz * rz;
+  return s;
+}
+
+// Closed-form eigenvalues of a symmetric 2x2 / 3x3 matrix (Sec. 3),
+// ascending.  S = (xx, yy, zz, xy, xz, yz).
+template <int DIM>
+__device__ __forceinline__ void eig_sym(const double S[6], double lam[3]) {
+  if (DIM == 2) {
+    double m = 0.5 * (S[0] + S[1]), d = 0.5 * (S[0] - S[1]);
+    double r = sqrt(d * d + S[3] * S[3]);
+    lam[0] = m - r;
+    lam[1] = m + r;
+    lam[2] = 0.0;
+    return;
+  }
+  const double a00 = S[0], a11 = S[1], a22 = S[2], a01 = S[3], a02 = S[4], a12 = S[5];
+  double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  if (p1 == 0.0) {
+    double e0 = fmin(a00, fmin(a11, a22)), e2 = fmax(a00, fmax(a11, a22));
+    lam[0] = e0;
+    lam[2] = e2;
+    lam[1] = a00 + a11 + a22 - e0 - e2;
+    return;
+  }
+  double q = (a00 + a11 + a22) * (1.0 / 3.0);
+  double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+  double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * p1;
+  double p = sqrt(p2 * (1.0 / 6.0));
+  double ip = 1.0 / p;
+  double B00 = b00 * ip, B11 = b11 * ip, B22 = b22 * ip, B01 = a01 * ip, B02 = a02 * ip, B12 = a12 * ip;
+  double det = B00 * (B11 * B22 - B12 * B12) - B01 * (B01 * B22 - B12 * B02) + B02 * (B01 * B12 - B11 * B02);
+  double r = fmin(1.0, fmax(-1.0, 0.5 * det));
+  double ang = acos(r) * (1.0 / 3.0);
+  double hi = q + 2.0 * p * cos(ang);
+  double lo = q + 2.0 * p * cos(ang + 2.0943951023931954923);  // + 2 pi / 3
+  lam[0] = lo;
+  lam[2] = hi;
+  lam[1] = 3.0 * q - hi - lo;
+}
+
+// Inverse of a symmetric matrix S = (xx, yy, zz, xy, xz, yz) as the same
+// packed form; returns the determinant.
+template <int DIM>
+__device__ __forceinline__ double inv_sym(const double S[6], double I[6]) {
+  if (DIM == 2) {
+    double det = S[0] * S[1] - S[3] * S[3];
+    double id = 1.0 / det;
+    I[0] = S[1] * id;
+    I[1] = S[0] * id;
+    I[3] = -S[3] * id;
+    I[2] = I[4] = I[5] = 0.0;
+    return det;
+  }
+  double c00 = S[1] * S[2] - S[5] * S[5];
+  double c11 = S[0] * S[2] - S[4] * S[4];
+  double c22 = S[0] * S[1] - S[3] * S[3];
+  double c01 = S[4] * S[5] - S[3] * S[2];
+  double c02 = S[3] * S[5] - S[4] * S[1];
+  double c12 = S[3] * S[4] - S[0] * S[5];
+  double det = S[0] * c00 + S[3] * c01 + S[4] * c02;
+  double id = 1.0 / det;
+  I[0] = c00 * id;
+  I[1] = c11 * id;
+  I[2] = c22 * id;
+  I[3] = c01 * id;
+  I[4] = c02 * id;
+  I[5] = c12 * id;
+  return det;
+}
+
+template <int DIM>
+__device__ __forceinline__ void sym_mul(const double I[6], const double v[3], double y[3]) {
+  if (DIM == 2) {
+    y[0] = I[0] * v[0] + I[3] * v[1];
+    y[1] = I[3] * v[0] + I[1] * v[1];
+    y[2] = 0.0;
+  } else {
+    y[0] = I[0] * v[0] + I[3] * v[1] + I[4] * v[2];
+    y[1] = I[3] * v[0] + I[1] * v[1] + I[5] * v[2];
+    y[2] = I[4] * v[0] + I[5] * v[1] + I[2] * v[2];
+  }
+}
+
+// ------------------------------------------------------- cell-row walker
+//
+// Algorithm 1 visits the 3^d cells around the particle's cell.  Cells along x
+// are consecutive in HashID order, so each (y, z) offset is one contiguous
+// run of particles: one "row".  With cells smaller than 2h the walker visits
+// (2 reach + 1)^(d-1) rows; a row whose (y, z) slab is farther than 2h from
+// the particle is skipped and the x span is cut to the particle's reach.  The
+// cuts are conservative (slightly widened), the exact test is done per pair.
+struct RowWalker {
+  int32_t row;       // next row index in [0, nrows)
+  int32_t nrows;
+  int32_t seg;       // 0: fluid part of the current row, 1: dummy part
+  uint32_t cur, end; // current run [cur, end) in record index space
+  int32_t cx, cy, cz;
+  uint32_t dlo, dhi; // dummy run of the current row (absolute record index)
+};
+
+template <int DIM>
+__device__ __forceinline__ void walker_init(RowWalker &w, const Grid &g, double x, double y, double z) {
+  w.cx = cell_coord(x, g.lo[0], g.R);
+  w.cy = cell_coord(y, g.lo[1], g.R);
+  w.cz = DIM == 3 ? cell_coord(z, g.lo[2], g.R) : 0;
+  int side = 2 * g.reach + 1;
+  w.nrows = DIM == 3 ? side * side : side;
+  w.row = 0;
+  w.seg = 1;
+  w.cur = w.end = 0;
+  w.dlo = w.dhi = 0;
+}
+
+// Advances to the next non-empty run; returns false when the walk is over.
+// cs_f / cs_d: cell start arrays (ncell + 1) of the fluid and dummy records;
+// dummy records live at index nf + k.
+template <int DIM>
+__device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const uint32_t *__restrict__ cs_f,
+                                            const uint32_t *__restrict__ cs_d, uint32_t nf, double x, double y,
+                                            double z, double two_h) {
+  for (;;) {
+    if (w.seg == 0) {  // fluid part done: emit the dummy part of the same row
+      w.seg = 1;
+      if (w.dlo < w.dhi) {
+        w.cur = w.dlo;
+        w.end = w.dhi;
+        return true;
+      }
+      continue;
+    }
+    if (w.row >= w.nrows) return false;
+    int side = 2 * g.reach + 1;
+    int r = w.row++;
+    int dy = (DIM == 3 ? r % side : r) - g.reach;
+    int dz = DIM == 3 ? r / side - g.reach : 0;
+    int iy = w.cy + dy, iz = w.cz + dz;
+    if (iy < 0 || iy >= g.N[1]) continue;
+    if (DIM == 3 && (iz < 0 || iz >= g.N[2])) continue;
+    // distance from the particle to the row's (y, z) slab, slightly reduced
+    double ey = 0.0, ez = 0.0;
+    if (dy > 0) ey = (g.lo[1] + (double)iy * g.R) - y;
+    if (dy < 0) ey = y - (g.lo[1] + (double)(iy + 1) * g.R);
+    if (DIM == 3) {
+      if (dz > 0) ez = (g.lo[2] + (double)iz * g.R) - z;
+      if (dz < 0) ez = z - (g.lo[2] + (double)(iz + 1) * g.R);
+    }
+    ey = fmax(0.0, ey - 1e-12 * g.R);
+    ez = fmax(0.0, ez - 1e-12 * g.R);
+    double rem = two_h * two_h - ey * ey - ez * ez;
+    if (rem < 0.0) continue;
+    double reach = sqrt(rem) * (1.0 + 1e-12) + 1e-12 * g.R;
+    int x0 = cell_coord(x - reach, g.lo[0], g.R);
+    int x1 = cell_coord(x + reach, g.lo[0], g.R);
+    x0 = max(x0, max(w.cx - g.reach, 0));
+    x1 = min(x1, min(w.cx + g.reach, g.N[0] - 1));
+    if (x0 > x1) continue;
+    int64_t base = (int64_t)iy * g.N[0] + (int64_t)iz * g.N[0] * g.N[1];
+    uint32_t flo = cs_f[base + x0], fhi = cs_f[base + x1 + 1];
+    w.dlo = nf + cs_d[base + x0];
+    w.dhi = nf + cs_d[base + x1 + 1];
+    w.seg = 0;
+    if (flo < fhi) {
+      w.cur = flo;
+      w.end = fhi;
+      return true;
+    }
+  }
+}
+
+// ---------------------------------------------------------- launch helpers
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// Host launchers implemented in the kernel translation units.  All take the
+// stream to enqueue on and return hipSuccess or the launch error.
+struct Ctx;  // host context (api.hip)
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
+// exclusive scan of n u32 values into out (out may alias in); total written
+// to out[n]; tmp needs scan_tmp_words(n) words.
+size_t scan_tmp_words(int64_t n);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+
+}  // namespace wb

@@ -1,0 +1,405 @@
+// Time integration and bookkeeping kernels:
+//   - fluid max |U| (atomic max on the bit pattern of a non-negative double,
+//     order independent, hence deterministic) and the time-step rule of
+//     Sec. 2.3 evaluated on the device, so a step never waits for the host;
+//   - the two SSP-RK2 stage updates (Sec. 2.3), FP64 path;
+//   - gathers from HashID order back to the caller's particle order;
+//   - the input split by particle kind at set-up.
+#include "common.h"
+#include "kernels.h"
+
+namespace wb {
+
+// --------------------------------------------------------------- max |U|
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_umax(const T *__restrict__ u0, const T *__restrict__ u1,
+                                              const T *__restrict__ u2, int64_t n, Scalars *sc) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double a = (double)u0[i], b = (double)u1[i], c = DIM == 3 ? (double)u2[i] : 0.0;
+    m = fmax(m, a * a + b * b + c * c);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    atomicMax(&sc->umax2_bits, (unsigned long long)__double_as_longlong(b));
+  }
+}
+
+__global__ void k_reset_umax(Scalars *sc) { sc->umax2_bits = 0ull; }
+
+hipError_t launch_umax(int dim, const double *const u[3], const float *const uf[3], int64_t nf, Scalars *sc,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_umax, dim3(1), dim3(1), 0, s, sc);
+  if (nf > 0) {
+    unsigned blocks = grid_for(nf);
+    if (blocks > 1024) blocks = 1024;
+    if (u) {
+      if (dim == 2)
+        hipLaunchKernelGGL((k_umax<double, 2>), dim3(blocks), dim3(256), 0, s, u[0], u[1], u[1], nf, sc);
+      else
+        hipLaunchKernelGGL((k_umax<double, 3>), dim3(blocks), dim3(256), 0, s, u[0], u[1], u[2], nf, sc);
+    } else {
+      if (dim == 2)
+        hipLaunchKernelGGL((k_umax<float, 2>), dim3(blocks), dim3(256), 0, s, uf[0], uf[1], uf[1], nf, sc);
+      else
+        hipLaunchKernelGGL((k_umax<float, 3>), dim3(blocks), dim3(256), 0, s, uf[0], uf[1], uf[2], nf, sc);
+    }
+  }
+  return hipGetLastError();
+}
+
+// dt = CFL min(dx/(C0 + |U|max), dx^2/(2 nu), sqrt(2 dx/|G|max)) at the start
+// of a step (Sec. 2.3); the first right-hand side is evaluated at t.
+__global__ void k_dt(Phys P, Scalars *sc, double dt_override) {
+  double umax = sqrt(__longlong_as_double((long long)sc->umax2_bits));
+  double dt = P.dx / (P.c0 + umax);
+  if (P.nu > 0.0) dt = fmin(dt, P.dx * P.dx / (2.0 * P.nu));
+  if (P.gmax > 0.0) dt = fmin(dt, sqrt(2.0 * P.dx / P.gmax));
+  dt *= P.cfl;
+  sc->dt = dt_override > 0.0 ? dt_override : dt;
+  sc->umax = umax;
+  sc->t_rhs = sc->t;
+}
+
+hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(1), 0, s, P, sc, dt_override);
+  return hipGetLastError();
+}
+
+// Stage bookkeeping: U_max of the stage and the time of its right-hand side
+// (stage 1 at t, stage 2 at t + dt); statistics counters restart.
+__global__ void k_stage_time(Scalars *sc, int stage) {
+  sc->umax = sqrt(__longlong_as_double((long long)sc->umax2_bits));
+  sc->t_rhs = stage == 2 ? sc->t + sc->dt : sc->t;
+  sc->n_cand = 0;
+  sc->n_scan = 0;
+  sc->n_fs = 0;
+  sc->n_cons = 0;
+  sc->n_sing = 0;
+  sc->n_mlp = 0;
+  sc->pairs = 0ull;
+}
+
+hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage_time, dim3(1), dim3(1), 0, s, sc, stage);
+  return hipGetLastError();
+}
+
+__global__ void k_advance_time(Scalars *sc) {
+  sc->t = sc->t + sc->dt;
+  sc->steps += 1.0;
+}
+
+hipError_t launch_advance_time(Scalars *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(1), 0, s, sc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ SSP-RK2, FP64
+// Stage 1: phi1 = phi + dt Dphi, U1 = U + dt a, x1 = x + dt (U + dU).
+// Stage 2: q = 1/2 q0 + 1/2 (q1 + dt rate(q1)) for phi, U and x.
+// Written without contraction, as the equations are printed.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_stage_f64(FluidF64 f, Rates r, int64_t n, const Scalars *__restrict__ sc,
+                                                   int stage) {
+#pragma clang fp contract(off)
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double dt = sc->dt;
+  if (stage == 1) {
+    double ph = f.phi[i];
+    f.phi0[i] = ph;
+    f.phi[i] = ph + dt * r.dphi[i];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      double x = f.x[a][i], u = f.u[a][i];
+      f.x0[a][i] = x;
+      f.u0[a][i] = u;
+      f.u[a][i] = u + dt * r.acc[a][i];
+      f.x[a][i] = x + dt * (u + r.dus[a][i]);
+    }
+  } else {
+    f.phi[i] = 0.5 * f.phi0[i] + 0.5 * (f.phi[i] + dt * r.dphi[i]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      double u1 = f.u[a][i];
+      f.u[a][i] = 0.5 * f.u0[a][i] + 0.5 * (u1 + dt * r.acc[a][i]);
+      f.x[a][i] = 0.5 * f.x0[a][i] + 0.5 * (f.x[a][i] + dt * (u1 + r.dus[a][i]));
+    }
+  }
+}
+
+hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, const Scalars *sc,
+                            int stage, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_stage_f64<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, f, r, nf, sc, stage);
+  else
+    hipLaunchKernelGGL(k_stage_f64<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, f, r, nf, sc, stage);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- gathers
+
+__global__ void k_gather_f64(const double *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
+                             double *__restrict__ dst, int stride, int comp) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[(int64_t)id[k] * stride + comp] = src[k];
+}
+
+__global__ void k_gather_f32_as_f64(const float *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
+                                    double *__restrict__ dst, int stride, int comp) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[(int64_t)id[k] * stride + comp] = (double)src[k];
+}
+
+__global__ void k_gather_rec(const double4 *__restrict__ rec, const uint32_t *__restrict__ id, int64_t n,
+                             double *__restrict__ dst, int stride, int comp, int ncomp) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double4 v = rec[k];
+  double c[4] = {v.x, v.y, v.z, v.w};
+  for (int a = 0; a < ncomp; ++a) dst[(int64_t)id[k] * stride + a] = c[comp + a];
+}
+
+__global__ void k_gather_u32_bits(const uint32_t *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
+                                  int32_t *__restrict__ dst, uint32_t mask, int shift) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[id[k]] = (int32_t)((src[k] & mask) >> shift);
+}
+
+__global__ void k_gather_i32(const int32_t *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
+                             int32_t *__restrict__ dst, int stride, int comp) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[(int64_t)id[k] * stride + comp] = src[k];
+}
+
+__global__ void k_gather_rows_f32(const float *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
+                                  int width, float *__restrict__ dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  for (int c = 0; c < width; ++c) dst[(int64_t)id[k] * width + c] = src[k * width + c];
+}
+
+__global__ void k_fill_f64(double *p, double v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f32(float *p, float v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <int DIM>
+__global__ void k_cells_of(Grid g, const double *__restrict__ x, const double *__restrict__ y,
+                           const double *__restrict__ z, const uint32_t *__restrict__ id, int64_t n,
+                           int32_t *__restrict__ dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int64_t o = (int64_t)id[k] * 3;
+  dst[o + 0] = cell_coord(x[k], g.lo[0], g.R);
+  dst[o + 1] = cell_coord(y[k], g.lo[1], g.R);
+  dst[o + 2] = DIM == 3 ? cell_coord(z[k], g.lo[2], g.R) : 0;
+}
+
+// which: 0 rho = rho0 exp(phi/C0^2); 1 p = C0^2 (rho - rho0)  (Eq. eos-water)
+__global__ void k_rho_p(Phys P, const double *__restrict__ phi, const uint32_t *__restrict__ id, int64_t n,
+                        double *__restrict__ dst, int which) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double rho = P.rho0 * exp(phi[k] * P.inv_c02);
+  dst[id[k]] = which == 0 ? rho : P.c0 * P.c0 * (rho - P.rho0);
+}
+
+__global__ void k_rho_p_rec(Phys P, const double4 *__restrict__ rec, const uint32_t *__restrict__ id, int64_t n,
+                            double *__restrict__ dst, int which) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double rho = P.rho0 * exp(rec[k].w * P.inv_c02);
+  dst[id[k]] = which == 0 ? rho : P.c0 * P.c0 * (rho - P.rho0);
+}
+
+hipError_t launch_gather_f64(const double *src, const uint32_t *id, int64_t n, double *dst, int stride, int comp,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_f32_as_f64(const float *src, const uint32_t *id, int64_t n, double *dst, int stride,
+                                    int comp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_f32_as_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rec(const double4 *rec, const uint32_t *id, int64_t n, double *dst, int stride, int comp,
+                             int ncomp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rec, dim3(grid_for(n)), dim3(kBlock), 0, s, rec, id, n, dst, stride, comp, ncomp);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_u32_bits(const uint32_t *src, const uint32_t *id, int64_t n, int32_t *dst, uint32_t mask,
+                                  int shift, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_u32_bits, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, mask, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_i32(const int32_t *src, const uint32_t *id, int64_t n, int32_t *dst, int stride, int comp,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows_f32(const float *src, const uint32_t *id, int64_t n, int width, float *dst,
+                                  hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, width, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cells_of(const Grid &g, int dim, const double *const x[3], const uint32_t *id, int64_t n,
+                           int32_t *dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_cells_of<2>, dim3(grid_for(n)), dim3(kBlock), 0, s, g, x[0], x[1], x[1], id, n, dst);
+  else
+    hipLaunchKernelGGL(k_cells_of<3>, dim3(grid_for(n)), dim3(kBlock), 0, s, g, x[0], x[1], x[2], id, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho_p(const Phys &P, const double *phi, const uint32_t *id, int64_t n, double *dst, int which,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rho_p, dim3(grid_for(n)), dim3(kBlock), 0, s, P, phi, id, n, dst, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho_p_rec(const Phys &P, const double4 *rec, const uint32_t *id, int64_t n, double *dst,
+                            int which, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rho_p_rec, dim3(grid_for(n)), dim3(kBlock), 0, s, P, rec, id, n, dst, which);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ set-up
+
+__global__ void k_kind_flags(const uint8_t *__restrict__ kind, int64_t n, uint32_t *__restrict__ isf,
+                             uint32_t *__restrict__ isd) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  isf[i] = kind[i] == 0 ? 1u : 0u;
+  isd[i] = kind[i] == 1 ? 1u : 0u;
+}
+
+hipError_t launch_kind_flags(const uint8_t *kind, int64_t n, uint32_t *isf, uint32_t *isd, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kind_flags, dim3(grid_for(n)), dim3(kBlock), 0, s, kind, n, isf, isd);
+  return hipGetLastError();
+}
+
+// Writes fluid rows into f (in original relative order) and dummy rows into
+// d; mass == NULL -> m = rho0 exp(phi / C0^2) dx^dim.
+__global__ void k_split(Phys P, int64_t n, const double *__restrict__ x, const double *__restrict__ u,
+                        const double *__restrict__ phi, const double *__restrict__ mass,
+                        const uint8_t *__restrict__ kind, const double *__restrict__ nrm,
+                        const uint32_t *__restrict__ frank, const uint32_t *__restrict__ drank, FluidF64 f,
+                        Dummies d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int dim = P.dim;
+  double vol = dim == 2 ? P.dx * P.dx : P.dx * P.dx * P.dx;
+  double m = mass ? mass[i] : P.rho0 * exp(phi[i] * P.inv_c02) * vol;
+  if (kind[i] == 0) {
+    uint32_t k = frank[i];
+    for (int a = 0; a < dim; ++a) {
+      f.x[a][k] = x[i * dim + a];
+      f.u[a][k] = u[i * dim + a];
+    }
+    f.phi[k] = phi[i];
+    f.m[k] = m;
+    f.id[k] = (uint32_t)i;
+  } else {
+    uint32_t k = drank[i];
+    for (int a = 0; a < dim; ++a) {
+      d.x[a][k] = x[i * dim + a];
+      d.n[a][k] = nrm[i * dim + a];
+    }
+    d.phi_in[k] = phi[i];
+    d.m[k] = m;
+    d.id[k] = (uint32_t)i;
+  }
+}
+
+hipError_t launch_split(const Phys &P, int64_t n, const double *x, const double *u, const double *phi,
+                        const double *mass, const uint8_t *kind, const double *nrm, const uint32_t *frank,
+                        const uint32_t *drank, FluidF64 f, Dummies d, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(kBlock), 0, s, P, n, x, u, phi, mass, kind, nrm, frank, drank,
+                     f, d);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_dummies(const uint32_t *__restrict__ perm, int64_t nd, Dummies src, Dummies dst, int dim) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nd) return;
+  uint32_t o = perm[k];
+  for (int a = 0; a < dim; ++a) {
+    dst.x[a][k] = src.x[a][o];
+    dst.n[a][k] = src.n[a][o];
+  }
+  dst.m[k] = src.m[o];
+  dst.phi_in[k] = src.phi_in[o];
+  dst.id[k] = src.id[o];
+  dst.src[k] = -1;
+}
+
+hipError_t launch_gather_dummies(const uint32_t *perm, int64_t nd, Dummies src, Dummies dst, int dim, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_dummies, dim3(grid_for(nd)), dim3(kBlock), 0, s, perm, nd, src, dst, dim);
+  return hipGetLastError();
+}
+
+// Non-finite state check (velocity and potential); positions are checked by
+// the hash kernel.
+template <int DIM>
+__global__ void k_check_state(FluidF64 f, int64_t n, Scalars *sc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool ok = isfinite(f.phi[i]);
+  for (int a = 0; a < DIM; ++a) ok = ok && isfinite(f.u[a][i]);
+  if (!ok) atomicOr(&sc->err, kErrNonFinite);
+}
+
+hipError_t launch_check_state(int dim, const FluidF64 &f, int64_t nf, Scalars *sc, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_check_state<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, f, nf, sc);
+  else
+    hipLaunchKernelGGL(k_check_state<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, f, nf, sc);
+  return hipGetLastError();
+}
+
+}  // namespace wb

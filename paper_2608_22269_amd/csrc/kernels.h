@@ -1,0 +1,82 @@
+// Host launchers of the device kernels, grouped by translation unit.
+#pragma once
+
+#include "common.h"
+
+namespace wb {
+
+struct SortScratch {
+  uint32_t *key, *slot, *count, *scan_tmp;
+};
+
+// grid.hip
+hipError_t launch_sort_keys(const Grid &g, int dim, const double *x, const double *y, const double *z,
+                            const uint32_t *packed_cell, int64_t n, const uint32_t *id, SortScratch &ss,
+                            uint32_t *start, uint32_t *perm, Scalars *sc, hipStream_t s);
+hipError_t launch_reorder_f64(const Phys &P, const uint32_t *perm, int64_t n, const FluidF64 &src,
+                              const FluidF64 &dst, double4 *rec0, double4 *rec1, int with_stage0, hipStream_t s);
+
+// Dummy wall particles (static, sorted once by cell).
+struct Dummies {
+  double *x[3], *n[3], *m, *phi_in;
+  uint32_t *id;
+  int32_t *src;  // sorted fluid index of the mirror source, -1 if inactive
+};
+
+// pair.hip
+hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const double4 *rec0,
+                             const double4 *rec1, double4 *drec0, double4 *drec1, const uint32_t *cs_f,
+                             uint32_t nf, const Scalars *sc, hipStream_t s, const uint32_t *fid);
+hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
+                           const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
+                           uint32_t *cand, bool features, hipStream_t s);
+hipError_t launch_scan_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
+                           const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
+                           const Rates &out, Scalars *sc, hipStream_t s);
+hipError_t launch_nb_count_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
+                               const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, uint32_t *cnt, hipStream_t s);
+hipError_t launch_nb_fill_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
+                              const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, const uint32_t *did,
+                              const uint32_t *off, uint32_t r0, uint32_t r1, int32_t *ids, hipStream_t s);
+hipError_t launch_sort_rows(const uint32_t *off, int64_t r0, int64_t r1, int32_t *ids, hipStream_t s);
+
+// integrate.hip
+hipError_t launch_umax(int dim, const double *const u[3], const float *const uf[3], int64_t nf, Scalars *sc,
+                       hipStream_t s);
+hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t s);
+hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s);
+hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, const Scalars *sc,
+                            int stage, hipStream_t s);
+hipError_t launch_advance_time(Scalars *sc, hipStream_t s);
+hipError_t launch_gather_f64(const double *src, const uint32_t *id, int64_t n, double *dst, int stride, int comp,
+                             hipStream_t s);
+hipError_t launch_gather_f32_as_f64(const float *src, const uint32_t *id, int64_t n, double *dst, int stride,
+                                    int comp, hipStream_t s);
+hipError_t launch_gather_rec(const double4 *rec, const uint32_t *id, int64_t n, double *dst, int stride,
+                             int comp, int ncomp, hipStream_t s);
+hipError_t launch_gather_u32_bits(const uint32_t *src, const uint32_t *id, int64_t n, int32_t *dst,
+                                  uint32_t mask, int shift, hipStream_t s);
+hipError_t launch_gather_i32(const int32_t *src, const uint32_t *id, int64_t n, int32_t *dst, int stride,
+                             int comp, hipStream_t s);
+hipError_t launch_gather_rows_f32(const float *src, const uint32_t *id, int64_t n, int width, float *dst,
+                                  hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+hipError_t launch_cells_of(const Grid &g, int dim, const double *const x[3], const uint32_t *id, int64_t n,
+                           int32_t *dst, hipStream_t s);
+hipError_t launch_rho_p(const Phys &P, const double *phi, const uint32_t *id, int64_t n, double *dst, int which,
+                        hipStream_t s);
+hipError_t launch_rho_p_rec(const Phys &P, const double4 *rec, const uint32_t *id, int64_t n, double *dst,
+                            int which, hipStream_t s);
+
+// Setup: split the caller's particles by kind.
+hipError_t launch_split(const Phys &P, int64_t n, const double *x, const double *u, const double *phi,
+                        const double *mass, const uint8_t *kind, const double *nrm, const uint32_t *fluid_rank,
+                        const uint32_t *dummy_rank, FluidF64 f, Dummies d, hipStream_t s);
+hipError_t launch_kind_flags(const uint8_t *kind, int64_t n, uint32_t *is_fluid, uint32_t *is_dummy,
+                             hipStream_t s);
+hipError_t launch_gather_dummies(const uint32_t *perm, int64_t nd, Dummies src, Dummies dst, int dim,
+                                 hipStream_t s);
+hipError_t launch_check_state(int dim, const FluidF64 &f, int64_t nf, Scalars *sc, hipStream_t s);
+
+}  // namespace wb

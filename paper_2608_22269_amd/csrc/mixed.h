@@ -1,0 +1,42 @@
+// Mixed-precision path: positions as an integer cell plus an FP32 offset
+// inside the cell, FP32 pair evaluation, FP64 accumulation of the
+// correction matrix and of the potential-gradient sums.
+#pragma once
+
+#include "common.h"
+#include "kernels.h"
+
+namespace wb {
+
+// Neighbour-facing records of the mixed path (fluid rows then dummy rows):
+// r0 = (offset x, y, z, packed cell as float bits), r1 = (u, v, w, V) in FP32,
+// phi in FP64.
+struct MixedRec {
+  float4 *r0, *r1;
+  double *phi;
+};
+
+hipError_t launch_to_mixed(const Phys &P, const Grid &g, const FluidF64 &src, int64_t nf, const FluidMixed &dst,
+                           Scalars *sc, hipStream_t s);
+hipError_t launch_reorder_mixed(const Phys &P, const Grid &g, const uint32_t *perm, int64_t nf,
+                                const FluidMixed &src, const FluidMixed &dst, const MixedRec &rec, int with_stage0,
+                                hipStream_t s);
+hipError_t launch_mirror_mixed(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const MixedRec &rec,
+                               const uint32_t *cs_f, uint32_t nf, const Scalars *sc, hipStream_t s,
+                               const uint32_t *fid);
+hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
+                             const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
+                             bool features, hipStream_t s);
+hipError_t launch_scan_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
+                             const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
+                             const Rates &out, Scalars *sc, hipStream_t s);
+hipError_t launch_stage_mixed(const Phys &P, const Grid &g, const FluidMixed &f, const Rates &r, int64_t nf,
+                              const Scalars *sc, int stage, hipStream_t s);
+// state fields of the fluid rows (x, u, phi, rho, p, mass, cell) in original order
+hipError_t launch_fields_mixed(const Phys &P, const Grid &g, const FluidMixed &f, int64_t nf, int field, void *dst,
+                               hipStream_t s);
+// dummy rows of u, phi, rho, p from the mixed records
+hipError_t launch_dummy_fields_mixed(const Phys &P, const MixedRec &rec, int64_t nf, const uint32_t *did, int64_t nd,
+                                     int field, void *dst, hipStream_t s);
+
+}  // namespace wb

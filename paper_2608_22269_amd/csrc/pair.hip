@@ -1,0 +1,568 @@
+// Particle interaction stage, FP64 path (Sec. 2 and Sec. 3):
+//   - dummy-wall mirror (Sec. 2.4, Eq. phiBn and the slip velocity);
+//   - the fused pair pass: every sum of Eq. (sph) in one neighbour pass --
+//     L (Eq. renorm), the Riemann sum of Eqs. (parGrad)/(lfsover) kept on the
+//     right of L^T (the correction moved out of the sum, Sec. 3), the
+//     conservative sum (TIC), the velocity-gradient tensor of the continuity
+//     equation, the delta-SPH sum and the shifting sum -- followed by an
+//     epilogue with the closed-form eigenvalues, the small solves and the
+//     free-surface pre-classification;
+//   - the scan-region pass over free-surface candidates;
+//   - neighbour-list export for parity checks.
+//
+// Work mapping.  One lane per fluid particle, particles in HashID order.  A
+// lane first walks the cell rows of Algorithm 1 and compacts the in-range
+// candidates into its own column of an LDS list (32 entries), then runs the
+// dense pair body over that list; it alternates until its walk ends.  Lanes of
+// one wave belong to the same or neighbouring cells, so their walks touch the
+// same records in lockstep (coalesced loads) and the expensive body runs on
+// real neighbours only instead of every candidate of the 3^d cells.
+#include "common.h"
+#include "kernels.h"
+
+namespace wb {
+
+constexpr int kList = 32;  // LDS list entries per lane
+
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
+  // wave-aggregated atomic append; returns the slot of this lane (valid if pred)
+  unsigned long long mask = __ballot(pred);
+  uint32_t base = 0;
+  if (mask) {
+    int leader = __ffsll((long long)mask) - 1;
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+  }
+  return base + (uint32_t)__popcll(mask & __lanemask_lt());
+}
+
+__device__ __forceinline__ void wave_count(uint32_t *counter, bool pred) {
+  unsigned long long mask = __ballot(pred);
+  if (mask && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)mask) - 1))
+    atomicAdd(counter, (uint32_t)__popcll(mask));
+}
+
+// ------------------------------------------------------------------ mirror
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, int64_t nd,
+                                                    const double4 *__restrict__ rec0,
+                                                    const double4 *__restrict__ rec1, double4 *__restrict__ drec0,
+                                                    double4 *__restrict__ drec1, const uint32_t *__restrict__ cs_f,
+                                                    uint32_t nf, const Scalars *__restrict__ sc,
+                                                    const uint32_t *__restrict__ fid) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nd) return;
+  double xd = d.x[0][k], yd = d.x[1][k], zd = DIM == 3 ? d.x[2][k] : 0.0;
+  RowWalker w;
+  walker_init<DIM>(w, g, xd, yd, zd);
+  int64_t best = -1;
+  uint32_t best_id = 0;
+  double best_r2 = 0.0;
+  // fluid runs only (the dummy cell-start array is not needed: pass cs_f twice
+  // and stop at the first dummy run)
+  while (walker_next<DIM>(w, g, cs_f, cs_f, nf, xd, yd, zd, P.two_h)) {
+    if (w.cur >= nf) continue;
+    for (uint32_t j = w.cur; j < w.end; ++j) {
+      double4 b = rec0[j];
+      double r2 = dist2_exact<DIM>(b.x - xd, b.y - yd, b.z - zd);
+      if (r2 <= P.two_h2) {
+        uint32_t jid = fid[j];
+        if (best < 0 || r2 < best_r2 || (r2 == best_r2 && jid < best_id)) {
+          best = j;
+          best_r2 = r2;
+          best_id = jid;
+        }
+      }
+    }
+  }
+  d.src[k] = (int32_t)best;
+  if (best < 0) {
+    drec0[k] = make_double4(xd, yd, zd, d.phi_in[k]);
+    drec1[k] = make_double4(0.0, 0.0, 0.0, 0.0);  // inactive: in no fluid's support
+    return;
+  }
+  double G[3];
+  body_force(P, sc->t_rhs, G);
+  double4 f0 = rec0[best], f1 = rec1[best];
+  // phi_d = phi_f + G.(x_d - x_f)        (Eq. phiBn)
+  double gp = G[0] * (xd - f0.x) + G[1] * (yd - f0.y);
+  if (DIM == 3) gp += G[2] * (zd - f0.z);
+  double phid = f0.w + gp;
+  // slip: U_d = U_f - (U_f . n_d) n_d
+  double nx = d.n[0][k], ny = d.n[1][k], nz = DIM == 3 ? d.n[2][k] : 0.0;
+  double un = f1.x * nx + f1.y * ny + f1.z * nz;
+  double V = d.m[k] / (P.rho0 * exp(phid * P.inv_c02));
+  drec0[k] = make_double4(xd, yd, zd, phid);
+  drec1[k] = make_double4(f1.x - un * nx, f1.y - un * ny, DIM == 3 ? f1.z - un * nz : 0.0, V);
+}
+
+// ----------------------------------------------------------- pair pass
+
+template <int DIM, bool FEAT>
+__global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
+                                                  const double4 *__restrict__ rec1, const uint32_t *__restrict__ cs_f,
+                                                  const uint32_t *__restrict__ cs_d, uint32_t nf, Scalars *sc,
+                                                  Rates out, uint32_t *__restrict__ cand) {
+  __shared__ uint32_t list[kList][kBlock];
+  const int tid = threadIdx.x;
+  const uint32_t i = blockIdx.x * kBlock + tid;
+  const bool active = i < nf;
+
+  double4 a0 = make_double4(0.0, 0.0, 0.0, 0.0), a1 = a0;
+  if (active) {
+    a0 = rec0[i];
+    a1 = rec1[i];
+  }
+  RowWalker w;
+  walker_init<DIM>(w, g, a0.x, a0.y, a0.z);
+  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf, a0.x, a0.y, a0.z, P.two_h);
+
+  double L[6] = {0, 0, 0, 0, 0, 0};
+  double gs[3] = {0, 0, 0}, SR[3] = {0, 0, 0}, SC[3] = {0, 0, 0}, Ps[3] = {0, 0, 0};
+  double N[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double Ds = 0.0;
+  double S0 = 0.0, m1[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0}, qmin = 2.0;
+  uint32_t nnb = 0, ndum = 0;
+  bool coincident = false;
+  const bool pst4 = P.pst_n == 4.0;
+
+  for (;;) {
+    // phase 1: compact in-range candidates into this lane's LDS column
+    int cnt = 0;
+    while (!done && cnt < kList) {
+      uint32_t j = w.cur;
+      if (j != i) {
+        double4 b = rec0[j];
+        double r2 = dist2_exact<DIM>(b.x - a0.x, b.y - a0.y, b.z - a0.z);
+        if (r2 <= P.two_h2) {
+          list[cnt][tid] = j;
+          ++cnt;
+        }
+      }
+      if (++w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf, a0.x, a0.y, a0.z, P.two_h);
+    }
+    // phase 2: dense pair body over the list
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t j = list[k][tid];
+      const double4 b0 = rec0[j], b1 = rec1[j];
+      const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
+      const double r2 = dist2_exact<DIM>(rx, ry, rz);
+      coincident |= (r2 == 0.0);
+      const double is = rsqrt(r2);
+      const double s = r2 * is;
+      const double q = s * P.inv_h;
+      const double t = 1.0 - 0.5 * q;
+      const double t2 = t * t, t3 = t2 * t;
+      const double wv = P.kfac * t3 * b1.w;  // |grad W| / |r| times V_j
+      const double gx = wv * rx, gy = wv * ry, gz = wv * rz;
+      // L = sum r (x) grad W V  (symmetric for the radial kernel)
+      L[0] += rx * gx;
+      L[1] += ry * gy;
+      L[3] += rx * gy;
+      if (DIM == 3) {
+        L[2] += rz * gz;
+        L[4] += rx * gz;
+        L[5] += ry * gz;
+      }
+      gs[0] += gx;
+      gs[1] += gy;
+      if (DIM == 3) gs[2] += gz;
+      const double dph = b0.w - a0.w;
+      const double dux = b1.x - a1.x, duy = b1.y - a1.y, duz = DIM == 3 ? b1.z - a1.z : 0.0;
+      const double dun = (dux * rx + duy * ry + duz * rz) * is;
+      const double c2 = dph - P.c0 * dun;  // 2 (phi*_ij - phi_i)
+      const double cs = b0.w + a0.w;        // conservative form
+      SR[0] += c2 * gx;
+      SR[1] += c2 * gy;
+      SC[0] += cs * gx;
+      SC[1] += cs * gy;
+      if (DIM == 3) {
+        SR[2] += c2 * gz;
+        SC[2] += cs * gz;
+      }
+      // N_ab = sum (U_j - U_i)_a (grad W V)_b
+      N[0] += dux * gx;
+      N[1] += dux * gy;
+      N[3] += duy * gx;
+      N[4] += duy * gy;
+      if (DIM == 3) {
+        N[2] += dux * gz;
+        N[5] += duy * gz;
+        N[6] += duz * gx;
+        N[7] += duz * gy;
+        N[8] += duz * gz;
+      }
+      Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
+      const double W = P.alpha * t2 * t2 * (2.0 * q + 1.0);
+      const double wr = W * P.w0inv;
+      const double wrn = pst4 ? (wr * wr) * (wr * wr) : pow(wr, P.pst_n);
+      const double pw = 1.0 + P.pst_R * wrn;
+      Ps[0] += pw * gx;
+      Ps[1] += pw * gy;
+      if (DIM == 3) Ps[2] += pw * gz;
+      if (FEAT) {
+        const double WV = W * b1.w;
+        S0 += WV;
+        m1[0] += WV * rx;
+        m1[1] += WV * ry;
+        m2[0] += WV * rx * rx;
+        m2[1] += WV * ry * ry;
+        m2[3] += WV * rx * ry;
+        if (DIM == 3) {
+          m1[2] += WV * rz;
+          m2[2] += WV * rz * rz;
+          m2[4] += WV * rx * rz;
+          m2[5] += WV * ry * rz;
+        }
+        qmin = fmin(qmin, q);
+        ndum += (j >= nf) ? 1u : 0u;
+      }
+    }
+    nnb += cnt;
+    if (done) break;
+  }
+
+  // ------------------------------------------------------------- epilogue
+  const uint32_t flags = P.flags;
+  double lam[3];
+  eig_sym<DIM>(L, lam);
+  const double lmin = lam[0];
+  const bool singular = lmin <= P.lambda_sing;
+  const bool tic = (flags & SPH_F_TIC) && lmin < P.lambda_tic;
+  const bool cons = singular || tic;
+  double I[6] = {0, 0, 0, 0, 0, 0};
+  if (!singular) inv_sym<DIM>(L, I);
+  double G[3];
+  body_force(P, sc->t_rhs, G);
+  // momentum: a = -L^-T S_R + G  or  -S_C + G
+  double grad[3];
+  if (cons) {
+    grad[0] = SC[0];
+    grad[1] = SC[1];
+    grad[2] = SC[2];
+  } else {
+    sym_mul<DIM>(I, SR, grad);
+  }
+  // continuity: -C0^2 tr(L^-1 N) (+ delta-SPH)
+  double div;
+  if (singular || (tic && (flags & SPH_F_CONT_UNCORR))) {
+    div = N[0] + N[4] + (DIM == 3 ? N[8] : 0.0);
+  } else if (DIM == 2) {
+    div = I[0] * N[0] + I[3] * N[1] + I[3] * N[3] + I[1] * N[4];
+  } else {
+    div = I[0] * N[0] + I[3] * N[1] + I[4] * N[2] + I[3] * N[3] + I[1] * N[4] + I[5] * N[5] + I[4] * N[6] +
+          I[5] * N[7] + I[2] * N[8];
+  }
+  double dphi = -P.c0 * P.c0 * div;
+  if (flags & SPH_F_DELTA) dphi += P.delta * P.h * P.c0 * (2.0 * Ds);
+  // free-surface normal n = -L^-T g / |.|
+  double ng[3];
+  if (singular) {
+    ng[0] = -gs[0];
+    ng[1] = -gs[1];
+    ng[2] = -gs[2];
+  } else {
+    sym_mul<DIM>(I, gs, ng);
+    ng[0] = -ng[0];
+    ng[1] = -ng[1];
+    ng[2] = -ng[2];
+  }
+  const double nn = sqrt(ng[0] * ng[0] + ng[1] * ng[1] + (DIM == 3 ? ng[2] * ng[2] : 0.0));
+  double nrm[3] = {0.0, 0.0, 0.0};
+  if (nn > 0.0) {
+    nrm[0] = ng[0] / nn;
+    nrm[1] = ng[1] / nn;
+    if (DIM == 3) nrm[2] = ng[2] / nn;
+  }
+  // shifting: dU* = -2 h U_max P, clamped to U_max / 2
+  double dus[3] = {0.0, 0.0, 0.0};
+  const double umax = sc->umax;
+  if (flags & SPH_F_PST) {
+    double ds[3] = {-2.0 * P.h * umax * Ps[0], -2.0 * P.h * umax * Ps[1], -2.0 * P.h * umax * Ps[2]};
+    double dn = sqrt(ds[0] * ds[0] + ds[1] * ds[1] + (DIM == 3 ? ds[2] * ds[2] : 0.0));
+    if (dn > 0.0) {
+      double mag = dn < 0.5 * umax ? dn : 0.5 * umax;
+      dus[0] = mag * ds[0] / dn;
+      dus[1] = mag * ds[1] / dn;
+      if (DIM == 3) dus[2] = mag * ds[2] / dn;
+    }
+  }
+  // free-surface pre-classification by lambda_min
+  uint32_t fl = (cons ? kFlagCons : 0u) | (singular ? kFlagSingular : 0u);
+  bool is_cand = false;
+  if (P.fs_mode != SPH_FS_NONE) {
+    bool fs = false;
+    if (lmin <= P.lambda_lo) fs = true;
+    else if (lmin > P.lambda_hi) fs = false;
+    else if (nn == 0.0) fs = true;
+    else is_cand = true;
+    if (fs) {
+      fl |= kFlagFS;
+      if ((flags & SPH_F_FS_PROJECT) && (flags & SPH_F_PST)) {
+        double d = dus[0] * nrm[0] + dus[1] * nrm[1] + dus[2] * nrm[2];
+        dus[0] -= d * nrm[0];
+        dus[1] -= d * nrm[1];
+        dus[2] -= d * nrm[2];
+      }
+    }
+    if (is_cand) fl |= kFlagCand;
+  }
+  if (active) {
+    for (int a = 0; a < DIM; ++a) {
+      out.acc[a][i] = -grad[a] + G[a];
+      out.dus[a][i] = dus[a];
+      out.nrm[a][i] = nrm[a];
+    }
+    out.dphi[i] = dphi;
+    out.lam[0][i] = lam[0];
+    out.lam[1][i] = lam[1];
+    out.lam[2][i] = lam[2];
+    out.flags[i] = fl;
+    out.nnb[i] = nnb;
+    if (coincident) atomicOr(&sc->err, kErrNonFinite);
+    if (FEAT) {
+      float *f = out.feat + (size_t)i * kNFeat;
+      const double S0s = S0 + P.wself * a1.w;
+      double m1n = 0, m1sq = 0, nm2n = 0, trm2 = 0, gn2 = 0, pn2 = 0, ngr = 0, gg2 = 0;
+      const double M2[3][3] = {{m2[0], m2[3], m2[4]}, {m2[3], m2[1], m2[5]}, {m2[4], m2[5], m2[2]}};
+      for (int a = 0; a < DIM; ++a) {
+        m1n += nrm[a] * m1[a];
+        m1sq += m1[a] * m1[a];
+        trm2 += M2[a][a];
+        gn2 += gs[a] * gs[a];
+        pn2 += Ps[a] * Ps[a];
+        ngr += nrm[a] * G[a];
+        gg2 += G[a] * G[a];
+        for (int b = 0; b < DIM; ++b) nm2n += nrm[a] * M2[a][b] * nrm[b];
+      }
+      double detL = DIM == 2 ? L[0] * L[1] - L[3] * L[3]
+                             : L[0] * (L[1] * L[2] - L[5] * L[5]) - L[3] * (L[3] * L[2] - L[5] * L[4]) +
+                                   L[4] * (L[3] * L[5] - L[1] * L[4]);
+      f[0] = (float)lam[0];
+      f[1] = (float)lam[1];
+      f[2] = (float)(DIM == 3 ? lam[2] : lam[1]);
+      f[3] = (float)detL;
+      f[4] = (float)S0s;
+      f[5] = (float)nnb;
+      f[6] = (float)(sqrt(gn2) * P.h);
+      f[7] = (float)(S0s > 0.0 ? m1n / (S0s * P.h) : 0.0);
+      f[8] = (float)(S0s > 0.0 ? sqrt(m1sq) / (S0s * P.h) : 0.0);
+      f[9] = (float)(S0s > 0.0 ? nm2n / (S0s * P.h * P.h) : 0.0);
+      f[10] = (float)(S0s > 0.0 ? (trm2 - nm2n) / (S0s * P.h * P.h) : 0.0);
+      f[11] = (float)(nn * P.h);
+      f[12] = (float)(gg2 > 0.0 ? ngr / sqrt(gg2) : 0.0);
+      f[13] = (float)(nnb > 0 ? (double)ndum / (double)nnb : 0.0);
+      f[14] = (float)qmin;
+      f[15] = (float)(sqrt(pn2) * P.h);
+    }
+  }
+  // candidate list and statistics (wave-aggregated atomics)
+  const bool cand_l = active && is_cand;
+  uint32_t slot = wave_append(&sc->n_cand, cand_l);
+  if (cand_l) cand[slot] = i;
+  wave_count(&sc->n_fs, active && (fl & kFlagFS));
+  wave_count(&sc->n_cons, active && cons);
+  wave_count(&sc->n_sing, active && singular);
+  // ordered-pair count
+  unsigned long long pc = active ? nnb : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
+  if ((threadIdx.x & 63) == 0 && pc) atomicAdd(&sc->pairs, pc);
+}
+
+hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
+                           const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
+                           uint32_t *cand, bool features, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  dim3 gr(grid_for(nf)), bl(kBlock);
+  if (P.dim == 2) {
+    if (features)
+      hipLaunchKernelGGL((k_pair_f64<2, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+    else
+      hipLaunchKernelGGL((k_pair_f64<2, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+  } else {
+    if (features)
+      hipLaunchKernelGGL((k_pair_f64<3, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+    else
+      hipLaunchKernelGGL((k_pair_f64<3, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+  }
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- scan-region pass
+
+// Candidates (lambda_lo < lambda <= lambda_hi) are on the free surface unless
+// a neighbour lies in the umbrella-shaped region around T = x_i + h n: beyond
+// sqrt(2) h from i within h of T, or closer than sqrt(2) h to i with
+// |n.(x_j - T)| + |tangential part| < h.  Grid-stride over the device-counted
+// list, so the launch does not depend on the count.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_scan_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
+                                                  const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
+                                                  uint32_t nf, const uint32_t *__restrict__ list,
+                                                  const uint32_t *__restrict__ count, Rates out, Scalars *sc) {
+  const uint32_t total = *count;
+  const double two_h2_scan = 2.0 * P.h * P.h;
+  const double h2 = P.h * P.h;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+    const uint32_t i = list[k];
+    const double4 a = rec0[i];
+    const double n0 = out.nrm[0][i], n1 = out.nrm[1][i], n2 = DIM == 3 ? out.nrm[2][i] : 0.0;
+    const double T0 = a.x + P.h * n0, T1 = a.y + P.h * n1, T2 = DIM == 3 ? a.z + P.h * n2 : 0.0;
+    RowWalker w;
+    walker_init<DIM>(w, g, a.x, a.y, a.z);
+    bool covered = false;
+    while (!covered && walker_next<DIM>(w, g, cs_f, cs_d, nf, a.x, a.y, a.z, P.two_h)) {
+      for (uint32_t j = w.cur; j < w.end && !covered; ++j) {
+        if (j == i) continue;
+        const double4 b = rec0[j];
+        const double s2 = dist2_exact<DIM>(b.x - a.x, b.y - a.y, b.z - a.z);
+        if (s2 > P.two_h2) continue;
+        const double d0 = b.x - T0, d1 = b.y - T1, d2 = DIM == 3 ? b.z - T2 : 0.0;
+        if (s2 >= two_h2_scan) {
+          covered = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
+        } else {
+          const double dn = n0 * d0 + n1 * d1 + n2 * d2;
+          const double e0 = d0 - dn * n0, e1 = d1 - dn * n1, e2 = d2 - dn * n2;
+          covered = fabs(dn) + sqrt(e0 * e0 + e1 * e1 + e2 * e2) < P.h;
+        }
+      }
+    }
+    uint32_t fl = out.flags[i] | kFlagByScan;
+    if (!covered) {
+      fl |= kFlagFS;
+      if ((P.flags & SPH_F_FS_PROJECT) && (P.flags & SPH_F_PST)) {
+        double u0 = out.dus[0][i], u1 = out.dus[1][i], u2 = DIM == 3 ? out.dus[2][i] : 0.0;
+        double d = u0 * n0 + u1 * n1 + u2 * n2;
+        out.dus[0][i] = u0 - d * n0;
+        out.dus[1][i] = u1 - d * n1;
+        if (DIM == 3) out.dus[2][i] = u2 - d * n2;
+      }
+      atomicAdd(&sc->n_fs, 1u);
+    }
+    out.flags[i] = fl;
+  }
+}
+
+hipError_t launch_scan_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
+                           const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
+                           const Rates &out, Scalars *sc, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  unsigned blocks = grid_for(nf);
+  if (blocks > 2048) blocks = 2048;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_scan_f64<2>, dim3(blocks), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, list, count, out,
+                       sc);
+  else
+    hipLaunchKernelGGL(k_scan_f64<3>, dim3(blocks), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, list, count, out,
+                       sc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- neighbour export
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_nb_count(Phys P, Grid g, const double4 *__restrict__ rec0,
+                                                  const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
+                                                  uint32_t nf, const uint32_t *__restrict__ fid,
+                                                  uint32_t *__restrict__ cnt) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  double4 a = rec0[i];
+  RowWalker w;
+  walker_init<DIM>(w, g, a.x, a.y, a.z);
+  uint32_t c = 0;
+  while (walker_next<DIM>(w, g, cs_f, cs_d, nf, a.x, a.y, a.z, P.two_h)) {
+    for (uint32_t j = w.cur; j < w.end; ++j) {
+      if (j == i) continue;
+      double4 b = rec0[j];
+      if (dist2_exact<DIM>(b.x - a.x, b.y - a.y, b.z - a.z) <= P.two_h2) ++c;
+    }
+  }
+  cnt[fid[i]] = c;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_nb_fill(Phys P, Grid g, const double4 *__restrict__ rec0,
+                                                 const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
+                                                 uint32_t nf, const uint32_t *__restrict__ fid,
+                                                 const uint32_t *__restrict__ did, const uint32_t *__restrict__ off,
+                                                 uint32_t r0, uint32_t r1, int32_t *__restrict__ ids) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  const uint32_t row = fid[i];
+  if (row < r0 || row >= r1) return;
+  double4 a = rec0[i];
+  RowWalker w;
+  walker_init<DIM>(w, g, a.x, a.y, a.z);
+  uint32_t o = off[row];
+  while (walker_next<DIM>(w, g, cs_f, cs_d, nf, a.x, a.y, a.z, P.two_h)) {
+    for (uint32_t j = w.cur; j < w.end; ++j) {
+      if (j == i) continue;
+      double4 b = rec0[j];
+      if (dist2_exact<DIM>(b.x - a.x, b.y - a.y, b.z - a.z) <= P.two_h2)
+        ids[o++] = (int32_t)(j < nf ? fid[j] : did[j - nf]);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sort_rows(const uint32_t *__restrict__ off, int64_t r0, int64_t r1,
+                                                   int32_t *__restrict__ ids) {
+  int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= r1) return;
+  uint32_t b = off[r], e = off[r + 1];
+  for (uint32_t k = b + 1; k < e; ++k) {
+    int32_t v = ids[k];
+    uint32_t m = k;
+    while (m > b && ids[m - 1] > v) {
+      ids[m] = ids[m - 1];
+      --m;
+    }
+    ids[m] = v;
+  }
+}
+
+hipError_t launch_nb_count_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
+                               const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, uint32_t *cnt, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_nb_count<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, fid, cnt);
+  else
+    hipLaunchKernelGGL(k_nb_count<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, fid, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_fill_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
+                              const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, const uint32_t *did,
+                              const uint32_t *off, uint32_t r0, uint32_t r1, int32_t *ids, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_nb_fill<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, fid, did, off,
+                       r0, r1, ids);
+  else
+    hipLaunchKernelGGL(k_nb_fill<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, fid, did, off,
+                       r0, r1, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_rows(const uint32_t *off, int64_t r0, int64_t r1, int32_t *ids, hipStream_t s) {
+  if (r1 <= r0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_rows, dim3(grid_for(r1 - r0)), dim3(kBlock), 0, s, off, r0, r1, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const double4 *rec0,
+                             const double4 *rec1, double4 *drec0, double4 *drec1, const uint32_t *cs_f,
+                             uint32_t nf, const Scalars *sc, hipStream_t s, const uint32_t *fid) {
+  if (nd == 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_mirror_f64<2>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec0, rec1, drec0, drec1,
+                       cs_f, nf, sc, fid);
+  else
+    hipLaunchKernelGGL(k_mirror_f64<3>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec0, rec1, drec0, drec1,
+                       cs_f, nf, sc, fid);
+  return hipGetLastError();
+}
+
+}  // namespace wb

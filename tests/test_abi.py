@@ -1,0 +1,88 @@
+"""The C-ABI library loads on a machine without a GPU, exports every symbol
+include/wbsph.h declares, and rejects bad inputs on the host before any
+device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2608_22269_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "wbsph.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(L.exported_symbols()) == names
+
+
+def test_validate_and_workspace(L):
+    lib = L.lib()
+    c = wl.tank2d()
+    p = L.params_from_dict(c["params"])
+    assert lib.sph_validate(C.byref(p)) == L.SPH_OK
+    assert lib.sph_workspace_bytes(C.byref(p), 5000, 678) > 0
+    for field, val in (("dim", 4), ("h", -1.0), ("cfl", 0.0), ("precision", 7), ("fs_mode", 9)):
+        q = L.params_from_dict(c["params"])
+        setattr(q, field, val)
+        assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+        assert lib.sph_workspace_bytes(C.byref(q), 10, 10) == 0
+    q = L.params_from_dict(c["params"])
+    q.cell_size = 0.5 * q.h  # reach 4 > 3
+    assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+
+
+def _init(L, case, x=None, u=None, phi=None, kind=None, normal=None, ws=256, ws_bytes=1 << 40):
+    lib = L.lib()
+    p = L.params_from_dict(case["params"])
+    x = case["x"] if x is None else x
+    u = case["u"] if u is None else u
+    phi = case["phi"] if phi is None else phi
+    kind = case["kind"] if kind is None else kind
+    normal = case["normal"] if normal is None else normal
+    pp = lambda a: a.ctypes.data_as(C.c_void_p)
+    ctx = C.c_void_p()
+    return lib.sph_init(C.byref(p), len(kind), pp(x), pp(u), pp(phi), None, pp(kind), pp(normal), 0,
+                        C.c_void_p(ws), ws_bytes, None, C.byref(ctx))
+
+
+def test_host_validation_before_any_launch(L):
+    c = wl.tank2d(dx=0.05)
+    x = c["x"].copy()
+    x[2, 1] = 50.0
+    assert _init(L, c, x=x) == L.SPH_EDOMAIN
+    u = c["u"].copy()
+    u[0, 0] = np.nan
+    assert _init(L, c, u=u) == L.SPH_ENONFINITE
+    k = c["kind"].copy()
+    k[0] = 5
+    assert _init(L, c, kind=k) == L.SPH_EINVAL
+    nrm = c["normal"].copy()
+    nrm[-1] = [0.3, 0.3]
+    assert _init(L, c, normal=nrm) == L.SPH_EINVAL
+    # misaligned workspace
+    assert _init(L, c, ws=300) == L.SPH_EWORKSPACE
+
+
+def test_status_strings(L):
+    for code in range(-8, 1):
+        assert L.status_string(code)
