@@ -516,7 +516,7 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   FluidF64 f0;
   std::memset(&f0, 0, sizeof(f0));
   if (!c->mixed) {
-    f0 = c->alt;
+    f0 = c->cur;  // the first rebuild sorts cur into alt and swaps
   } else {
     for (int a = 0; a < dim; ++a) {
       f0.x[a] = (double *)take(sizeof(double) * nf);
@@ -674,11 +674,12 @@ sph_status sph_stats(sph_ctx *c, double out[16]) {
 namespace {
 
 __global__ void k_mirror_src_ids(const int32_t *__restrict__ src, const uint32_t *__restrict__ did,
-                                 const uint32_t *__restrict__ fid, int64_t nd, int32_t *__restrict__ dst) {
+                                 const uint32_t *__restrict__ fid, int64_t nd, int32_t *__restrict__ dst,
+                                 uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nd) return;
   int32_t s = src[k];
-  dst[did[k]] = s >= 0 ? (int32_t)fid[s] : -1;
+  if (did[k] < nout) dst[did[k]] = s >= 0 ? (int32_t)fid[s] : -1;
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
@@ -687,9 +688,9 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
 }
 
 __global__ void k_path_of(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ id, int64_t n,
-                          int32_t *__restrict__ dst) {
+                          int32_t *__restrict__ dst, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= n || id[k] >= nout) return;
   uint32_t f = flags[k];
   dst[id[k]] = (f & kFlagByMLP) ? 2 : (f & kFlagByScan) ? 1 : 0;
 }
@@ -750,19 +751,19 @@ extern "C" sph_status sph_fields(sph_ctx *c, int32_t field, void *out, int32_t o
   } else {
     switch (field) {
       case SPH_FIELD_X:
-        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->cur.x[a], fid, nf, dd, dim, a, s);
+        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->cur.x[a], fid, nf, dd, dim, a, s, (uint32_t)c->n);
         break;
       case SPH_FIELD_U:
-        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->cur.u[a], fid, nf, dd, dim, a, s);
+        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->cur.u[a], fid, nf, dd, dim, a, s, (uint32_t)c->n);
         break;
-      case SPH_FIELD_PHI: e = launch_gather_f64(c->cur.phi, fid, nf, dd, 1, 0, s); break;
-      case SPH_FIELD_MASS: e = launch_gather_f64(c->cur.m, fid, nf, dd, 1, 0, s); break;
+      case SPH_FIELD_PHI: e = launch_gather_f64(c->cur.phi, fid, nf, dd, 1, 0, s, (uint32_t)c->n); break;
+      case SPH_FIELD_MASS: e = launch_gather_f64(c->cur.m, fid, nf, dd, 1, 0, s, (uint32_t)c->n); break;
       case SPH_FIELD_RHO: case SPH_FIELD_P:
-        e = launch_rho_p(c->P, c->cur.phi, fid, nf, dd, field == SPH_FIELD_RHO ? 0 : 1, s);
+        e = launch_rho_p(c->P, c->cur.phi, fid, nf, dd, field == SPH_FIELD_RHO ? 0 : 1, s, (uint32_t)c->n);
         break;
       case SPH_FIELD_CELL: {
         const double *xx[3] = {c->cur.x[0], c->cur.x[1], c->cur.x[2]};
-        e = launch_cells_of(c->g, dim, xx, fid, nf, di, s);
+        e = launch_cells_of(c->g, dim, xx, fid, nf, di, s, (uint32_t)c->n);
         break;
       }
       default: break;
@@ -772,29 +773,30 @@ extern "C" sph_status sph_fields(sph_ctx *c, int32_t field, void *out, int32_t o
   if (e == hipSuccess) {
     switch (field) {
       case SPH_FIELD_X:
-        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->dm.x[a], c->dm.id, nd, dd, dim, a, s);
+        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->dm.x[a], c->dm.id, nd, dd, dim, a, s, (uint32_t)c->n);
         break;
-      case SPH_FIELD_MASS: e = launch_gather_f64(c->dm.m, c->dm.id, nd, dd, 1, 0, s); break;
+      case SPH_FIELD_MASS: e = launch_gather_f64(c->dm.m, c->dm.id, nd, dd, 1, 0, s, (uint32_t)c->n); break;
       case SPH_FIELD_CELL: {
         const double *xx[3] = {c->dm.x[0], c->dm.x[1], c->dm.x[2]};
-        e = launch_cells_of(c->g, dim, xx, c->dm.id, nd, di, s);
+        e = launch_cells_of(c->g, dim, xx, c->dm.id, nd, di, s, (uint32_t)c->n);
         break;
       }
       case SPH_FIELD_U:
-        if (!c->mixed) e = launch_gather_rec(c->rec1 + nf, c->dm.id, nd, dd, dim, 0, dim, s);
+        if (!c->mixed) e = launch_gather_rec(c->rec1 + nf, c->dm.id, nd, dd, dim, 0, dim, s, (uint32_t)c->n);
         else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s);
         break;
       case SPH_FIELD_PHI:
-        if (!c->mixed) e = launch_gather_rec(c->rec0 + nf, c->dm.id, nd, dd, 1, 3, 1, s);
+        if (!c->mixed) e = launch_gather_rec(c->rec0 + nf, c->dm.id, nd, dd, 1, 3, 1, s, (uint32_t)c->n);
         else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s);
         break;
       case SPH_FIELD_RHO: case SPH_FIELD_P:
-        if (!c->mixed) e = launch_rho_p_rec(c->P, c->rec0 + nf, c->dm.id, nd, dd, field == SPH_FIELD_RHO ? 0 : 1, s);
+        if (!c->mixed) e = launch_rho_p_rec(c->P, c->rec0 + nf, c->dm.id, nd, dd, field == SPH_FIELD_RHO ? 0 : 1, s, (uint32_t)c->n);
         else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s);
         break;
       case SPH_FIELD_MIRROR_SRC:
         if (nd > 0)
-          hipLaunchKernelGGL(k_mirror_src_ids, dim3(grid_for(nd)), dim3(kBlock), 0, s, c->dm.src, c->dm.id, fid, nd, di);
+          hipLaunchKernelGGL(k_mirror_src_ids, dim3(grid_for(nd)), dim3(kBlock), 0, s, c->dm.src, c->dm.id, fid, nd, di,
+                             (uint32_t)c->n);
         break;
       default: break;
     }
@@ -803,25 +805,25 @@ extern "C" sph_status sph_fields(sph_ctx *c, int32_t field, void *out, int32_t o
   if (e == hipSuccess && rate_field) {
     switch (field) {
       case SPH_FIELD_DUDT:
-        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->r.acc[a], fid, nf, dd, dim, a, s);
+        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->r.acc[a], fid, nf, dd, dim, a, s, (uint32_t)c->n);
         break;
       case SPH_FIELD_DELTA_U:
-        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->r.dus[a], fid, nf, dd, dim, a, s);
+        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->r.dus[a], fid, nf, dd, dim, a, s, (uint32_t)c->n);
         break;
       case SPH_FIELD_NORMAL:
-        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->r.nrm[a], fid, nf, dd, dim, a, s);
+        for (int a = 0; a < dim && e == hipSuccess; ++a) e = launch_gather_f64(c->r.nrm[a], fid, nf, dd, dim, a, s, (uint32_t)c->n);
         break;
       case SPH_FIELD_LAMBDA:
-        for (int a = 0; a < 3 && e == hipSuccess; ++a) e = launch_gather_f64(c->r.lam[a], fid, nf, dd, 3, a, s);
+        for (int a = 0; a < 3 && e == hipSuccess; ++a) e = launch_gather_f64(c->r.lam[a], fid, nf, dd, 3, a, s, (uint32_t)c->n);
         break;
-      case SPH_FIELD_DPHIDT: e = launch_gather_f64(c->r.dphi, fid, nf, dd, 1, 0, s); break;
-      case SPH_FIELD_FS: e = launch_gather_u32_bits(c->r.flags, fid, nf, di, kFlagFS, 1, s); break;
-      case SPH_FIELD_TIC: e = launch_gather_u32_bits(c->r.flags, fid, nf, di, kFlagCons, 0, s); break;
-      case SPH_FIELD_NNB: e = launch_gather_u32_bits(c->r.nnb, fid, nf, di, 0xffffffffu, 0, s); break;
-      case SPH_FIELD_FEATURES: e = launch_gather_rows_f32(c->r.feat, fid, nf, kNFeat, (float *)dst, s); break;
-      case SPH_FIELD_LOGIT: e = launch_gather_u32_bits((const uint32_t *)c->r.logit, fid, nf, di, 0xffffffffu, 0, s); break;
+      case SPH_FIELD_DPHIDT: e = launch_gather_f64(c->r.dphi, fid, nf, dd, 1, 0, s, (uint32_t)c->n); break;
+      case SPH_FIELD_FS: e = launch_gather_u32_bits(c->r.flags, fid, nf, di, kFlagFS, 1, s, (uint32_t)c->n); break;
+      case SPH_FIELD_TIC: e = launch_gather_u32_bits(c->r.flags, fid, nf, di, kFlagCons, 0, s, (uint32_t)c->n); break;
+      case SPH_FIELD_NNB: e = launch_gather_u32_bits(c->r.nnb, fid, nf, di, 0xffffffffu, 0, s, (uint32_t)c->n); break;
+      case SPH_FIELD_FEATURES: e = launch_gather_rows_f32(c->r.feat, fid, nf, kNFeat, (float *)dst, s, (uint32_t)c->n); break;
+      case SPH_FIELD_LOGIT: e = launch_gather_u32_bits((const uint32_t *)c->r.logit, fid, nf, di, 0xffffffffu, 0, s, (uint32_t)c->n); break;
       case SPH_FIELD_FS_PATH:
-        if (nf > 0) hipLaunchKernelGGL(k_path_of, dim3(grid_for(nf)), dim3(kBlock), 0, s, c->r.flags, fid, nf, di);
+        if (nf > 0) hipLaunchKernelGGL(k_path_of, dim3(grid_for(nf)), dim3(kBlock), 0, s, c->r.flags, fid, nf, di, (uint32_t)c->n);
         break;
       default: break;
     }
@@ -866,7 +868,7 @@ extern "C" sph_status sph_neighbors(sph_ctx *c, int64_t *offsets, int32_t *ids, 
   uint32_t *off = cnt + (n + 1);
   hipError_t e = launch_fill_u32(cnt, 0u, n + 1, s);
   if (e == hipSuccess)
-    e = launch_nb_count_f64(c->P, c->g, c->rec0, c->cs_f, c->cs_d, (uint32_t)nf, c->cur.id, cnt, s);
+    e = launch_nb_count_f64(c->P, c->g, c->rec0, c->cs_f, c->cs_d, (uint32_t)nf, c->cur.id, cnt, s, (uint32_t)n);
   if (e == hipSuccess) e = launch_exclusive_scan(cnt, off, n, c->ss.scan_tmp, s);
   std::vector<uint32_t> hoff((size_t)n + 1);
   if (e == hipSuccess) e = hipMemcpyAsync(hoff.data(), off, sizeof(uint32_t) * (n + 1), hipMemcpyDeviceToHost, s);

@@ -192,6 +192,9 @@ __global__ void __launch_bounds__(256) k_canon(const uint32_t *__restrict__ star
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   uint32_t b = start[c], e = start[c + 1];
+  // a cell this full only occurs with particles parked after a domain error;
+  // keep arrival order there rather than spend quadratic time
+  if (e - b > 1024u) return;
   for (uint32_t k = b + 1; k < e; ++k) {
     uint32_t v = perm[k];
     uint32_t vid = id[v];

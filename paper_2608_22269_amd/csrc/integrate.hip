@@ -148,42 +148,42 @@ hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, in
 // ---------------------------------------------------------------- gathers
 
 __global__ void k_gather_f64(const double *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
-                             double *__restrict__ dst, int stride, int comp) {
+                             double *__restrict__ dst, int stride, int comp, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) dst[(int64_t)id[k] * stride + comp] = src[k];
+  if (k < n && id[k] < nout) dst[(int64_t)id[k] * stride + comp] = src[k];
 }
 
 __global__ void k_gather_f32_as_f64(const float *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
-                                    double *__restrict__ dst, int stride, int comp) {
+                                    double *__restrict__ dst, int stride, int comp, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) dst[(int64_t)id[k] * stride + comp] = (double)src[k];
+  if (k < n && id[k] < nout) dst[(int64_t)id[k] * stride + comp] = (double)src[k];
 }
 
 __global__ void k_gather_rec(const double4 *__restrict__ rec, const uint32_t *__restrict__ id, int64_t n,
-                             double *__restrict__ dst, int stride, int comp, int ncomp) {
+                             double *__restrict__ dst, int stride, int comp, int ncomp, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= n || id[k] >= nout) return;
   double4 v = rec[k];
   double c[4] = {v.x, v.y, v.z, v.w};
   for (int a = 0; a < ncomp; ++a) dst[(int64_t)id[k] * stride + a] = c[comp + a];
 }
 
 __global__ void k_gather_u32_bits(const uint32_t *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
-                                  int32_t *__restrict__ dst, uint32_t mask, int shift) {
+                                  int32_t *__restrict__ dst, uint32_t mask, int shift, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) dst[id[k]] = (int32_t)((src[k] & mask) >> shift);
+  if (k < n && id[k] < nout) dst[id[k]] = (int32_t)((src[k] & mask) >> shift);
 }
 
 __global__ void k_gather_i32(const int32_t *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
-                             int32_t *__restrict__ dst, int stride, int comp) {
+                             int32_t *__restrict__ dst, int stride, int comp, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) dst[(int64_t)id[k] * stride + comp] = src[k];
+  if (k < n && id[k] < nout) dst[(int64_t)id[k] * stride + comp] = src[k];
 }
 
 __global__ void k_gather_rows_f32(const float *__restrict__ src, const uint32_t *__restrict__ id, int64_t n,
-                                  int width, float *__restrict__ dst) {
+                                  int width, float *__restrict__ dst, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= n || id[k] >= nout) return;
   for (int c = 0; c < width; ++c) dst[(int64_t)id[k] * width + c] = src[k * width + c];
 }
 
@@ -200,9 +200,9 @@ __global__ void k_fill_f32(float *p, float v, int64_t n) {
 template <int DIM>
 __global__ void k_cells_of(Grid g, const double *__restrict__ x, const double *__restrict__ y,
                            const double *__restrict__ z, const uint32_t *__restrict__ id, int64_t n,
-                           int32_t *__restrict__ dst) {
+                           int32_t *__restrict__ dst, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= n || id[k] >= nout) return;
   int64_t o = (int64_t)id[k] * 3;
   dst[o + 0] = cell_coord(x[k], g.lo[0], g.R);
   dst[o + 1] = cell_coord(y[k], g.lo[1], g.R);
@@ -211,60 +211,60 @@ __global__ void k_cells_of(Grid g, const double *__restrict__ x, const double *_
 
 // which: 0 rho = rho0 exp(phi/C0^2); 1 p = C0^2 (rho - rho0)  (Eq. eos-water)
 __global__ void k_rho_p(Phys P, const double *__restrict__ phi, const uint32_t *__restrict__ id, int64_t n,
-                        double *__restrict__ dst, int which) {
+                        double *__restrict__ dst, int which, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= n || id[k] >= nout) return;
   double rho = P.rho0 * exp(phi[k] * P.inv_c02);
   dst[id[k]] = which == 0 ? rho : P.c0 * P.c0 * (rho - P.rho0);
 }
 
 __global__ void k_rho_p_rec(Phys P, const double4 *__restrict__ rec, const uint32_t *__restrict__ id, int64_t n,
-                            double *__restrict__ dst, int which) {
+                            double *__restrict__ dst, int which, uint32_t nout) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= n || id[k] >= nout) return;
   double rho = P.rho0 * exp(rec[k].w * P.inv_c02);
   dst[id[k]] = which == 0 ? rho : P.c0 * P.c0 * (rho - P.rho0);
 }
 
 hipError_t launch_gather_f64(const double *src, const uint32_t *id, int64_t n, double *dst, int stride, int comp,
-                             hipStream_t s) {
+                             hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp);
+  hipLaunchKernelGGL(k_gather_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp, nout);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_f32_as_f64(const float *src, const uint32_t *id, int64_t n, double *dst, int stride,
-                                    int comp, hipStream_t s) {
+                                    int comp, hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_f32_as_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp);
+  hipLaunchKernelGGL(k_gather_f32_as_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp, nout);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_rec(const double4 *rec, const uint32_t *id, int64_t n, double *dst, int stride, int comp,
-                             int ncomp, hipStream_t s) {
+                             int ncomp, hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_rec, dim3(grid_for(n)), dim3(kBlock), 0, s, rec, id, n, dst, stride, comp, ncomp);
+  hipLaunchKernelGGL(k_gather_rec, dim3(grid_for(n)), dim3(kBlock), 0, s, rec, id, n, dst, stride, comp, ncomp, nout);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_u32_bits(const uint32_t *src, const uint32_t *id, int64_t n, int32_t *dst, uint32_t mask,
-                                  int shift, hipStream_t s) {
+                                  int shift, hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_u32_bits, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, mask, shift);
+  hipLaunchKernelGGL(k_gather_u32_bits, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, mask, shift, nout);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_i32(const int32_t *src, const uint32_t *id, int64_t n, int32_t *dst, int stride, int comp,
-                             hipStream_t s) {
+                             hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp);
+  hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, dst, stride, comp, nout);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_rows_f32(const float *src, const uint32_t *id, int64_t n, int width, float *dst,
-                                  hipStream_t s) {
+                                  hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_rows_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, width, dst);
+  hipLaunchKernelGGL(k_gather_rows_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, src, id, n, width, dst, nout);
   return hipGetLastError();
 }
 
@@ -281,26 +281,26 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_cells_of(const Grid &g, int dim, const double *const x[3], const uint32_t *id, int64_t n,
-                           int32_t *dst, hipStream_t s) {
+                           int32_t *dst, hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
   if (dim == 2)
-    hipLaunchKernelGGL(k_cells_of<2>, dim3(grid_for(n)), dim3(kBlock), 0, s, g, x[0], x[1], x[1], id, n, dst);
+    hipLaunchKernelGGL(k_cells_of<2>, dim3(grid_for(n)), dim3(kBlock), 0, s, g, x[0], x[1], x[1], id, n, dst, nout);
   else
-    hipLaunchKernelGGL(k_cells_of<3>, dim3(grid_for(n)), dim3(kBlock), 0, s, g, x[0], x[1], x[2], id, n, dst);
+    hipLaunchKernelGGL(k_cells_of<3>, dim3(grid_for(n)), dim3(kBlock), 0, s, g, x[0], x[1], x[2], id, n, dst, nout);
   return hipGetLastError();
 }
 
 hipError_t launch_rho_p(const Phys &P, const double *phi, const uint32_t *id, int64_t n, double *dst, int which,
-                        hipStream_t s) {
+                        hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rho_p, dim3(grid_for(n)), dim3(kBlock), 0, s, P, phi, id, n, dst, which);
+  hipLaunchKernelGGL(k_rho_p, dim3(grid_for(n)), dim3(kBlock), 0, s, P, phi, id, n, dst, which, nout);
   return hipGetLastError();
 }
 
 hipError_t launch_rho_p_rec(const Phys &P, const double4 *rec, const uint32_t *id, int64_t n, double *dst,
-                            int which, hipStream_t s) {
+                            int which, hipStream_t s, uint32_t nout) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rho_p_rec, dim3(grid_for(n)), dim3(kBlock), 0, s, P, rec, id, n, dst, which);
+  hipLaunchKernelGGL(k_rho_p_rec, dim3(grid_for(n)), dim3(kBlock), 0, s, P, rec, id, n, dst, which, nout);
   return hipGetLastError();
 }
 

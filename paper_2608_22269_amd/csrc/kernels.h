@@ -34,7 +34,8 @@ hipError_t launch_scan_f64(const Phys &P, const Grid &g, const double4 *rec0, co
                            const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
                            const Rates &out, Scalars *sc, hipStream_t s);
 hipError_t launch_nb_count_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
-                               const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, uint32_t *cnt, hipStream_t s);
+                               const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, uint32_t *cnt, hipStream_t s,
+                               uint32_t nrows);
 hipError_t launch_nb_fill_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
                               const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, const uint32_t *did,
                               const uint32_t *off, uint32_t r0, uint32_t r1, int32_t *ids, hipStream_t s);
@@ -49,25 +50,25 @@ hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, in
                             int stage, hipStream_t s);
 hipError_t launch_advance_time(Scalars *sc, hipStream_t s);
 hipError_t launch_gather_f64(const double *src, const uint32_t *id, int64_t n, double *dst, int stride, int comp,
-                             hipStream_t s);
+                             hipStream_t s, uint32_t nout);
 hipError_t launch_gather_f32_as_f64(const float *src, const uint32_t *id, int64_t n, double *dst, int stride,
-                                    int comp, hipStream_t s);
+                                    int comp, hipStream_t s, uint32_t nout);
 hipError_t launch_gather_rec(const double4 *rec, const uint32_t *id, int64_t n, double *dst, int stride,
-                             int comp, int ncomp, hipStream_t s);
+                             int comp, int ncomp, hipStream_t s, uint32_t nout);
 hipError_t launch_gather_u32_bits(const uint32_t *src, const uint32_t *id, int64_t n, int32_t *dst,
-                                  uint32_t mask, int shift, hipStream_t s);
+                                  uint32_t mask, int shift, hipStream_t s, uint32_t nout);
 hipError_t launch_gather_i32(const int32_t *src, const uint32_t *id, int64_t n, int32_t *dst, int stride,
-                             int comp, hipStream_t s);
+                             int comp, hipStream_t s, uint32_t nout);
 hipError_t launch_gather_rows_f32(const float *src, const uint32_t *id, int64_t n, int width, float *dst,
-                                  hipStream_t s);
+                                  hipStream_t s, uint32_t nout);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 hipError_t launch_cells_of(const Grid &g, int dim, const double *const x[3], const uint32_t *id, int64_t n,
-                           int32_t *dst, hipStream_t s);
+                           int32_t *dst, hipStream_t s, uint32_t nout);
 hipError_t launch_rho_p(const Phys &P, const double *phi, const uint32_t *id, int64_t n, double *dst, int which,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t nout);
 hipError_t launch_rho_p_rec(const Phys &P, const double4 *rec, const uint32_t *id, int64_t n, double *dst,
-                            int which, hipStream_t s);
+                            int which, hipStream_t s, uint32_t nout);
 
 // Setup: split the caller's particles by kind.
 hipError_t launch_split(const Phys &P, int64_t n, const double *x, const double *u, const double *phi,

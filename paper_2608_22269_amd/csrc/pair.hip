@@ -466,7 +466,7 @@ template <int DIM>
 __global__ void __launch_bounds__(256) k_nb_count(Phys P, Grid g, const double4 *__restrict__ rec0,
                                                   const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
                                                   uint32_t nf, const uint32_t *__restrict__ fid,
-                                                  uint32_t *__restrict__ cnt) {
+                                                  uint32_t *__restrict__ cnt, uint32_t nrows) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
   double4 a = rec0[i];
@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(256) k_nb_count(Phys P, Grid g, const double4 
       if (dist2_exact<DIM>(b.x - a.x, b.y - a.y, b.z - a.z) <= P.two_h2) ++c;
     }
   }
-  cnt[fid[i]] = c;
+  if (fid[i] < nrows) cnt[fid[i]] = c;
 }
 
 template <int DIM>
@@ -524,12 +524,15 @@ __global__ void __launch_bounds__(256) k_sort_rows(const uint32_t *__restrict__ 
 }
 
 hipError_t launch_nb_count_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
-                               const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, uint32_t *cnt, hipStream_t s) {
+                               const uint32_t *cs_d, uint32_t nf, const uint32_t *fid, uint32_t *cnt, hipStream_t s,
+                               uint32_t nrows) {
   if (nf == 0) return hipSuccess;
   if (P.dim == 2)
-    hipLaunchKernelGGL(k_nb_count<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, fid, cnt);
+    hipLaunchKernelGGL(k_nb_count<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, fid, cnt,
+                       nrows);
   else
-    hipLaunchKernelGGL(k_nb_count<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, fid, cnt);
+    hipLaunchKernelGGL(k_nb_count<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, fid, cnt,
+                       nrows);
   return hipGetLastError();
 }
 
