@@ -1,0 +1,211 @@
+"""Throughput of the well-balanced WCSPH hot path on one MI355X.
+
+Workload (default): 3D sloshing tank 1.0 x 0.5 x 0.56 m, water depth 0.28 m,
+dx = 0.002 m -> 17,500,000 fluid + 2,047,296 wall dummies, horizontal tank
+forcing (A = 5 mm, period 1.2x the first natural period), delta-SPH,
+shifting, TIC and free-surface detection on.  A step is one full SSP-RK2 step:
+two right-hand sides, each with grid rebuild, wall mirror, fused pair pass,
+free-surface detection and stage update, plus the device-side dt reduction.
+
+Prints one JSON line (metric, value = pair evaluations per second of the
+headline path, ms/step, roofline of the pair pass, CPU oracle baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms/step & pair evals/s at 17.5M particles, FP64 vs mixed+learned; spurious |u|"
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed); non-packed issue equals the FP64 figure
+# Algorithmic floating-point operations of the pair pass:
+# per in-range ordered pair (3D body of Eq. sph with delta-SPH and shifting),
+# and per candidate distance test (difference vector and squared norm).
+FLOP_PER_PAIR_3D = 95
+FLOP_PER_TEST_3D = 8
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key, launches_pairs):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha") != source_sha(d.get("sources", [])):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def run_path(case, label, steps, warmup, **overrides):
+    import torch
+    from paper_2608_22269_amd import Simulation
+
+    log(f"{label}: init ({case['meta']['n_fluid']} fluid + {case['meta']['n_dummy']} dummies)")
+    t0 = time.time()
+    sim = Simulation(case, **overrides)
+    torch.cuda.synchronize()
+    log(f"{label}: init done in {time.time() - t0:.1f} s; warmup {warmup} steps")
+    sim.step(warmup)
+    sim.sync()
+    sim.profile(True)
+    sim.profile_read()
+    stream = sim.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    sim.sync()
+    prof = sim.profile_read()
+    st = sim.stats()
+    sim.profile(False)
+    pairs_rhs = st["pairs"]
+    tests_rhs = st["tests"]
+    ms_step = ms_total / steps
+    pair_evals_per_step = 2.0 * pairs_rhs
+    pair = prof["pair"]
+    pair_ms = pair["ms"] / max(pair["launches"], 1)
+    flops = pairs_rhs * FLOP_PER_PAIR_3D + tests_rhs * FLOP_PER_TEST_3D
+    achieved = flops / (pair_ms * 1e-3) / 1e12
+    out = {
+        "ms_per_step": ms_step,
+        "pair_evals_per_s": pair_evals_per_step / (ms_step * 1e-3),
+        "pairs_per_rhs": pairs_rhs,
+        "candidate_tests_per_rhs": tests_rhs,
+        "pair_pass_ms": pair_ms,
+        "pair_pass_tflops": achieved,
+        "kernel_ms_per_step": {k: v["ms"] / steps for k, v in prof.items()},
+        "t_end": st["t"],
+        "umax_end": st["umax"],
+        "fs_count": st["n_fs"],
+        "fs_candidates": st["n_cand"],
+    }
+    log(f"{label}: {ms_step:.2f} ms/step, {out['pair_evals_per_s']:.3e} pair-evals/s, "
+        f"pair pass {pair_ms:.2f} ms ({achieved:.1f} TFLOP/s)")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(dx):
+    """The CPU oracle on a bounded sample of the same workload: a 0.2 x 0.1 m
+    column of the sloshing tank at the same dx, depth and physics (one
+    right-hand side), timed on the host cores."""
+    import oracle
+    import workloads as wl
+
+    sample = wl.slosh3d(dx=dx, tank=(0.2, 0.1, 0.56), depth=0.28)
+    nthreads = oracle.num_threads()
+    log(f"cpu baseline: {sample['meta']['n_fluid']} fluid sample, {nthreads} threads")
+    t0 = time.perf_counter()
+    r = oracle.eval_rates(sample)
+    el = time.perf_counter() - t0
+    f = sample["kind"] == 0
+    pairs = float(r["nnb"][f].sum())
+    return {
+        "value": pairs / el, "unit": "pair-evals/s", "cores": int(nthreads), "kind": "oracle",
+        "sample": (f"one right-hand side of a 0.2 x 0.1 x 0.56 m column of the sloshing tank at dx={dx} "
+                   f"({sample['meta']['n_fluid']} fluid + {sample['meta']['n_dummy']} dummies, "
+                   f"{pairs:.3e} ordered pairs) in {el:.2f} s"),
+    }
+
+
+def spurious_velocity():
+    """FP64 hydrostatic 2D tank (5,000 fluid): max |U| after 100 steps."""
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    case = wl.tank2d()
+    sim = Simulation(case)
+    sim.step(100)
+    u = sim.field("u")[case["kind"] == 0]
+    sim.close()
+    return float(np.abs(u).max())
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dx", type=float, default=0.002)
+    ap.add_argument("--cell", type=float, default=2.0, help="cell size in units of h")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paths", default="fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (slab decomposition is designed, "
+              "not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"device {torch.cuda.get_device_name(0)}")
+    log("generating workload")
+    case = wl.slosh3d(dx=args.dx)
+    h = case["params"]["h"]
+    case = wl.with_params(case, cell_size=args.cell * h)
+    results = {}
+    for path in args.paths.split(","):
+        if path == "fp64":
+            results["fp64"] = run_path(case, "fp64", args.steps, args.warmup)
+        else:
+            raise SystemExit(f"unknown path {path}")
+    head = results["fp64"]
+    src = ["paper_2608_22269_amd/csrc/pair.hip", "paper_2608_22269_amd/csrc/common.h"]
+    traffic = traffic_from_profiles("pair_f64_slosh3d", None)
+    roof = {
+        "bound": "alu", "achieved": head["pair_pass_tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+        "frac": head["pair_pass_tflops"] / PEAK_FP64_TFLOPS, "traffic": traffic,
+        "kernel": "k_pair_f64<3,false> (fused pair pass)", "pair_pass_ms": head["pair_pass_ms"],
+        "flop_per_launch": head["pairs_per_rhs"] * FLOP_PER_PAIR_3D
+        + head["candidate_tests_per_rhs"] * FLOP_PER_TEST_3D,
+        "source_sha": source_sha(src),
+    }
+    out = {
+        "metric": METRIC, "value": head["pair_evals_per_s"], "unit": "pair-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded lattice tank, hydrostatic start, tank-frame forcing)",
+        "config": {"workload": (f"3D sloshing tank 1.0x0.5x0.56 m, depth 0.28 m, dx={args.dx}: "
+                                f"{case['meta']['n_fluid']} fluid + {case['meta']['n_dummy']} dummies"),
+                   "path": "fp64", "cell_size_over_h": args.cell, "fs_mode": "exact",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "paths": results,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.dx)
+    out["spurious_u_fp64_tank2d_100steps"] = spurious_velocity()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

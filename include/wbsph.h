@@ -86,7 +86,8 @@ typedef struct sph_params {
     double forcing_amp[3];  /* G(t) = G0 + amp w^2 sin(w t) (tank-frame forcing) */
     double forcing_omega;
     double domain_lo[3], domain_hi[3]; /* hashed box; particles must stay inside */
-    double cell_size;       /* background cell R (0 -> 2h); must be >= 2h        */
+    double cell_size;       /* background cell R (0 -> 2h); >= 2h/3: the search
+                               spans ceil(2h/R) cells on each side                */
 } sph_params;
 
 typedef struct sph_ctx sph_ctx;
@@ -146,6 +147,10 @@ sph_status sph_step(sph_ctx *ctx, int32_t nsteps, double dt_override);
  * rebuild, mirror, pair pass, detection.  Results readable by sph_fields. */
 sph_status sph_eval_rates(sph_ctx *ctx);
 
+/* Sets the simulation time of the state (e.g. when resuming from fields
+ * saved at time t; the forcing G(t) depends on it).  Stream ordered. */
+sph_status sph_set_time(sph_ctx *ctx, double t);
+
 /* Waits for the stream and reports deferred device errors. */
 sph_status sph_sync(sph_ctx *ctx);
 
@@ -180,8 +185,19 @@ sph_status sph_fields(sph_ctx *ctx, int32_t field, void *out, int32_t out_on_dev
  * right-hand side, [4] fluid count, [5] dummy count, [6] free-surface count,
  * [7] TIC-branch count, [8] scan-pass candidates, [9] MLP-decided count,
  * [10] singular-L count, [11] sum of fluid neighbour counts of the last
- * right-hand side (ordered pairs).  Synchronises. */
+ * right-hand side (ordered pairs), [12] free-surface candidates of the last
+ * right-hand side, [13] candidate pairs the last pair pass tested (distance
+ * computations).  Synchronises. */
 sph_status sph_stats(sph_ctx *ctx, double out[16]);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * each launch group while enabled: [0] pair pass, [1] wall mirror, [2] grid
+ * rebuild (hash, sort, reorder), [3] free-surface detection, [4] stage
+ * updates and reductions.  sph_profile_read synchronises and writes
+ * out[2k] = total milliseconds and out[2k+1] = launch count of group k, then
+ * clears the totals. */
+sph_status sph_profile(sph_ctx *ctx, int32_t enable);
+sph_status sph_profile_read(sph_ctx *ctx, double out[16]);
 
 /* Neighbour lists N(i) = {j != i : |x_j - x_i| <= 2h} (Algorithm 1) of every
  * particle at the current positions, as CSR over ORIGINAL indices: offsets

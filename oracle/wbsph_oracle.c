@@ -250,22 +250,26 @@ static int cell_list_build(const orc_params *p, int64_t n, const double *x, cell
     return ORC_OK;
 }
 
-/* Visit the candidates of particle i in Algorithm 1's order; emit j in range.
- * Returns the number found (writes at most cap ids). */
+/* Visit the candidates of particle i in Algorithm 1's order (z outermost, x
+ * innermost); emit j in range.  With R = 2h the stencil is Algorithm 1's
+ * 3^d cells; a smaller R widens it to ceil(2h / R) cells on each side so that
+ * the same neighbour set is found.  Returns the number found (writes at most
+ * cap ids). */
 static int64_t cell_list_query(const orc_params *p, const cell_list *cl, const double *x, int64_t i,
                                int32_t *ids, int64_t cap, int *zero_dist) {
     int dim = p->dim;
     double two_h = 2.0 * p->h;
     const int32_t *ci = cl->cell3 + i * 3;
     int64_t k = 0;
-    int zr = dim == 3 ? 1 : 0;
+    int reach = (int)ceil(two_h / cell_R(p));
+    int zr = dim == 3 ? reach : 0;
     for (int dz = -zr; dz <= zr; ++dz) {
         int64_t cz = ci[2] + dz;
         if (cz < 0 || cz >= cl->N[2]) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
+        for (int dy = -reach; dy <= reach; ++dy) {
             int64_t cy = ci[1] + dy;
             if (cy < 0 || cy >= cl->N[1]) continue;
-            for (int dxc = -1; dxc <= 1; ++dxc) {
+            for (int dxc = -reach; dxc <= reach; ++dxc) {
                 int64_t cx = ci[0] + dxc;
                 if (cx < 0 || cx >= cl->N[0]) continue;
                 int64_t c = cx + cy * cl->N[0] + cz * cl->N[0] * cl->N[1];

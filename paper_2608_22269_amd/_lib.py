@@ -79,9 +79,12 @@ def lib():
         "sph_step": (i32, [vp, i32, C.c_double]),
         "sph_eval_rates": (i32, [vp]),
         "sph_sync": (i32, [vp]),
+        "sph_set_time": (i32, [vp, C.c_double]),
         "sph_fields": (i32, [vp, i32, vp, i32]),
         "sph_stats": (i32, [vp, vp]),
         "sph_neighbors": (i32, [vp, vp, vp, i64, C.POINTER(i64)]),
+        "sph_profile": (i32, [vp, i32]),
+        "sph_profile_read": (i32, [vp, vp]),
         "sph_set_classifier": (i32, [vp, vp, i64, vp, vp, C.c_float]),
         "sph_mlp_workspace_bytes": (sz, [i64]),
         "sph_mlp_create": (i32, [i64, vp, vp, vp, vp, sz, vp, C.POINTER(vp)]),
@@ -105,8 +108,8 @@ def exported_symbols():
     """Names the binding expects the library to export."""
     return [
         "sph_validate", "sph_workspace_bytes", "sph_status_string", "sph_init", "sph_destroy",
-        "sph_last_error", "sph_build_cells", "sph_step", "sph_eval_rates", "sph_sync", "sph_fields",
-        "sph_stats", "sph_neighbors", "sph_set_classifier", "sph_mlp_workspace_bytes", "sph_mlp_create",
+        "sph_last_error", "sph_build_cells", "sph_step", "sph_eval_rates", "sph_sync", "sph_set_time", "sph_fields",
+        "sph_stats", "sph_neighbors", "sph_profile", "sph_profile_read", "sph_set_classifier", "sph_mlp_workspace_bytes", "sph_mlp_create",
         "sph_mlp_destroy", "sph_mlp_forward", "sph_mlp_loss_grad", "sph_mlp_adam", "sph_mlp_train_epoch",
         "sph_mlp_get_params", "sph_mlp_infer_bf16",
     ]

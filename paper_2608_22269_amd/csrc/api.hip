@@ -68,6 +68,13 @@ struct sph_ctx {
   Classifier clf;
   bool has_clf;
 
+  // per-kernel timing (sph_profile)
+  bool profiling;
+  std::vector<hipEvent_t> ev_a, ev_b;
+  std::vector<int> ev_kind;
+  size_t ev_used;
+  double prof_ms[8], prof_cnt[8];
+
   sph_status status;
   std::string err;
   bool cells_current;  // grid/order match the current positions
@@ -267,9 +274,44 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   return cv.off + kAlign;
 }
 
+// ----------------------------------------------------------- profiling
+
+constexpr size_t kProfSlots = 512;
+
+void prof_drain(sph_ctx *c) {
+  if (c->ev_used == 0) return;
+  hipStreamSynchronize(c->s);
+  for (size_t k = 0; k < c->ev_used; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_a[k], c->ev_b[k]) == hipSuccess) {
+      c->prof_ms[c->ev_kind[k]] += ms;
+      c->prof_cnt[c->ev_kind[k]] += 1.0;
+    }
+  }
+  c->ev_used = 0;
+}
+
+// RAII bracket: records a start event now and a stop event at scope end.
+struct ProfScope {
+  sph_ctx *c;
+  size_t slot;
+  bool on;
+  ProfScope(sph_ctx *ctx, int kind) : c(ctx), slot(0), on(ctx->profiling) {
+    if (!on) return;
+    if (c->ev_used == c->ev_a.size()) prof_drain(c);
+    slot = c->ev_used++;
+    c->ev_kind[slot] = kind;
+    hipEventRecord(c->ev_a[slot], c->s);
+  }
+  ~ProfScope() {
+    if (on) hipEventRecord(c->ev_b[slot], c->s);
+  }
+};
+
 // ------------------------------------------------------------ rebuilds
 
 sph_status rebuild(sph_ctx *c, int with_stage0) {
+  ProfScope ps(c, 2);
   hipError_t e;
   if (!c->mixed) {
     e = launch_sort_keys(c->g, c->dim, c->cur.x[0], c->cur.x[1], c->cur.x[2], nullptr, c->nf, c->cur.id, c->ss,
@@ -292,18 +334,27 @@ sph_status rhs(sph_ctx *c, int stage) {
   hipError_t e = launch_stage_time(c->sc, stage, c->s);
   const bool feat = (c->p.flags & SPH_F_FEATURES) || c->p.fs_mode == SPH_FS_LEARNED;
   if (!c->mixed) {
-    if (e == hipSuccess)
+    if (e == hipSuccess) {
+      ProfScope ps(c, 1);
       e = launch_mirror_f64(c->P, c->g, c->dm, c->nd, c->rec0, c->rec1, c->rec0 + c->nf, c->rec1 + c->nf, c->cs_f,
                             (uint32_t)c->nf, c->sc, c->s, c->cur.id);
-    if (e == hipSuccess)
+    }
+    if (e == hipSuccess) {
+      ProfScope ps(c, 0);
       e = launch_pair_f64(c->P, c->g, c->rec0, c->rec1, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat,
                           c->s);
+    }
   } else {
-    if (e == hipSuccess)
+    if (e == hipSuccess) {
+      ProfScope ps(c, 1);
       e = launch_mirror_mixed(c->P, c->g, c->dm, c->nd, c->mrec, c->cs_f, (uint32_t)c->nf, c->sc, c->s, c->mcur.id);
-    if (e == hipSuccess)
+    }
+    if (e == hipSuccess) {
+      ProfScope ps(c, 0);
       e = launch_pair_mixed(c->P, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat, c->s);
+    }
   }
+  ProfScope ps_fs(c, 3);
   if (e == hipSuccess && c->p.fs_mode != SPH_FS_NONE) {
     const uint32_t *list = c->cand;
     const uint32_t *count = &c->sc->n_cand;
@@ -324,6 +375,7 @@ sph_status rhs(sph_ctx *c, int stage) {
 }
 
 sph_status umax_of_current(sph_ctx *c) {
+  ProfScope ps(c, 4);
   hipError_t e;
   if (!c->mixed) {
     const double *u[3] = {c->cur.u[0], c->cur.u[1], c->cur.u[2]};
@@ -401,7 +453,12 @@ size_t sph_workspace_bytes(const sph_params *p, int64_t n_fluid, int64_t n_dummy
 
 const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-void sph_destroy(sph_ctx *ctx) { delete ctx; }
+void sph_destroy(sph_ctx *ctx) {
+  if (!ctx) return;
+  for (auto ev : ctx->ev_a) hipEventDestroy(ev);
+  for (auto ev : ctx->ev_b) hipEventDestroy(ev);
+  delete ctx;
+}
 
 sph_status sph_init(const sph_params *p, int64_t n, const double *x, const double *u, const double *phi,
                     const double *mass, const uint8_t *kind, const double *normal, int32_t inputs_on_device,
@@ -444,6 +501,9 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   c->mixed = p->precision == SPH_MIXED;
   c->status = SPH_OK;
   c->has_clf = false;
+  c->profiling = false;
+  c->ev_used = 0;
+  for (int k = 0; k < 8; ++k) c->prof_ms[k] = c->prof_cnt[k] = 0.0;
   derive(p, c->P, c->g);
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0) {
     delete c;
@@ -620,6 +680,7 @@ sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
     if (st == SPH_OK) st = rebuild(c, 0);
     if (st == SPH_OK) st = rhs(c, 1);
     if (st == SPH_OK) {
+      ProfScope ps(c, 4);
       hipError_t e = c->mixed ? launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, 1, c->s)
                               : launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, 1, c->s);
       st = hip_check(c, e, "stage 1");
@@ -628,6 +689,7 @@ sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
     if (st == SPH_OK) st = rebuild(c, 1);
     if (st == SPH_OK) st = rhs(c, 2);
     if (st == SPH_OK) {
+      ProfScope ps(c, 4);
       hipError_t e = c->mixed ? launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, 2, c->s)
                               : launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, 2, c->s);
       if (e == hipSuccess) e = launch_advance_time(c->sc, c->s);
@@ -637,6 +699,13 @@ sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
     c->cells_current = false;
   }
   return st;
+}
+
+sph_status sph_set_time(sph_ctx *c, double t) {
+  sph_status st = usable(c);
+  if (st != SPH_OK) return st;
+  if (!std::isfinite(t)) return fail(c, SPH_EINVAL, "non-finite time");
+  return hip_check(c, launch_set_time(c->sc, t, c->s), "set time");
 }
 
 sph_status sph_sync(sph_ctx *c) {
@@ -664,7 +733,35 @@ sph_status sph_stats(sph_ctx *c, double out[16]) {
   out[10] = h.n_sing;
   out[11] = (double)h.pairs;
   out[12] = h.n_cand;
+  out[13] = (double)h.tests;
   return c->status != SPH_OK ? c->status : SPH_OK;
+}
+
+sph_status sph_profile(sph_ctx *c, int32_t enable) {
+  if (!c) return SPH_EINVAL;
+  if (enable && c->ev_a.empty()) {
+    c->ev_a.resize(kProfSlots);
+    c->ev_b.resize(kProfSlots);
+    c->ev_kind.resize(kProfSlots);
+    for (size_t k = 0; k < kProfSlots; ++k) {
+      if (hipEventCreate(&c->ev_a[k]) != hipSuccess || hipEventCreate(&c->ev_b[k]) != hipSuccess)
+        return fail(c, SPH_EHIP, "event creation failed");
+    }
+  }
+  if (!enable) prof_drain(c);
+  c->profiling = enable != 0;
+  return SPH_OK;
+}
+
+sph_status sph_profile_read(sph_ctx *c, double out[16]) {
+  if (!c || !out) return SPH_EINVAL;
+  prof_drain(c);
+  for (int k = 0; k < 8; ++k) {
+    out[2 * k] = c->prof_ms[k];
+    out[2 * k + 1] = c->prof_cnt[k];
+    c->prof_ms[k] = c->prof_cnt[k] = 0.0;
+  }
+  return SPH_OK;
 }
 
 }  // extern "C"

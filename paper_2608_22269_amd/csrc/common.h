@@ -71,6 +71,7 @@ struct Scalars {
   double umax;       // sqrt of umax2 for the current right-hand side
   unsigned long long umax2_bits;  // atomic max of |U|^2 (non-negative double bits)
   unsigned long long pairs;       // sum of fluid neighbour counts of the last RHS
+  unsigned long long tests;       // candidate distance tests of the last pair pass
   uint32_t err;
   uint32_t n_cand;   // candidates listed by the pair pass
   uint32_t n_scan;   // candidates sent to the scan pass

@@ -84,10 +84,21 @@ __global__ void k_stage_time(Scalars *sc, int stage) {
   sc->n_sing = 0;
   sc->n_mlp = 0;
   sc->pairs = 0ull;
+  sc->tests = 0ull;
 }
 
 hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s) {
   hipLaunchKernelGGL(k_stage_time, dim3(1), dim3(1), 0, s, sc, stage);
+  return hipGetLastError();
+}
+
+__global__ void k_set_time(Scalars *sc, double t) {
+  sc->t = t;
+  sc->t_rhs = t;
+}
+
+hipError_t launch_set_time(Scalars *sc, double t, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(1), 0, s, sc, t);
   return hipGetLastError();
 }
 

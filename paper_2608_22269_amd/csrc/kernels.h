@@ -49,6 +49,7 @@ hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s);
 hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, const Scalars *sc,
                             int stage, hipStream_t s);
 hipError_t launch_advance_time(Scalars *sc, hipStream_t s);
+hipError_t launch_set_time(Scalars *sc, double t, hipStream_t s);
 hipError_t launch_gather_f64(const double *src, const uint32_t *id, int64_t n, double *dst, int stride, int comp,
                              hipStream_t s, uint32_t nout);
 hipError_t launch_gather_f32_as_f64(const float *src, const uint32_t *id, int64_t n, double *dst, int stride,

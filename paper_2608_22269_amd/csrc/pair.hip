@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 
   double N[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double Ds = 0.0;
   double S0 = 0.0, m1[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0}, qmin = 2.0;
-  uint32_t nnb = 0, ndum = 0;
+  uint32_t nnb = 0, ndum = 0, ntest = 0;
   bool coincident = false;
   const bool pst4 = P.pst_n == 4.0;
 
@@ -135,6 +135,7 @@ __global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 
       if (j != i) {
         double4 b = rec0[j];
         double r2 = dist2_exact<DIM>(b.x - a0.x, b.y - a0.y, b.z - a0.z);
+        ++ntest;
         if (r2 <= P.two_h2) {
           list[cnt][tid] = j;
           ++cnt;
@@ -364,11 +365,15 @@ __global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 
   wave_count(&sc->n_fs, active && (fl & kFlagFS));
   wave_count(&sc->n_cons, active && cons);
   wave_count(&sc->n_sing, active && singular);
-  // ordered-pair count
-  unsigned long long pc = active ? nnb : 0;
+  // ordered-pair and candidate-test counts
+  unsigned long long pc = active ? nnb : 0, tc = active ? ntest : 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
+  for (int o = 32; o > 0; o >>= 1) {
+    pc += __shfl_xor(pc, o, 64);
+    tc += __shfl_xor(tc, o, 64);
+  }
   if ((threadIdx.x & 63) == 0 && pc) atomicAdd(&sc->pairs, pc);
+  if ((threadIdx.x & 63) == 0 && tc) atomicAdd(&sc->tests, tc);
 }
 
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,

@@ -77,6 +77,9 @@ class Simulation:
                           C.c_void_p(ptr), nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         _check(st, "sph_init")
         self.ctx = ctx
+        t0 = float(case.get("t", 0.0))
+        if t0 != 0.0:
+            self.set_time(t0)
 
     # -- lifetime
     def close(self):
@@ -100,6 +103,9 @@ class Simulation:
     def eval_rates(self):
         _check(L.lib().sph_eval_rates(self.ctx), "sph_eval_rates", self.ctx)
 
+    def set_time(self, t):
+        _check(L.lib().sph_set_time(self.ctx, float(t)), "sph_set_time", self.ctx)
+
     def sync(self):
         _check(L.lib().sph_sync(self.ctx), "sph_sync", self.ctx)
 
@@ -120,8 +126,17 @@ class Simulation:
         out = np.zeros(16)
         _check(L.lib().sph_stats(self.ctx, out.ctypes.data_as(C.c_void_p)), "sph_stats", self.ctx)
         keys = ["t", "dt", "steps", "umax", "n_fluid", "n_dummy", "n_fs", "n_cons", "n_scan", "n_mlp",
-                "n_singular", "pairs", "n_cand"]
+                "n_singular", "pairs", "n_cand", "tests"]
         return {k: float(out[i]) for i, k in enumerate(keys)}
+
+    def profile(self, enable=True):
+        _check(L.lib().sph_profile(self.ctx, int(bool(enable))), "sph_profile", self.ctx)
+
+    def profile_read(self):
+        out = np.zeros(16)
+        _check(L.lib().sph_profile_read(self.ctx, out.ctypes.data_as(C.c_void_p)), "sph_profile_read", self.ctx)
+        names = ["pair", "mirror", "rebuild", "fs_detect", "stage"]
+        return {k: {"ms": float(out[2 * i]), "launches": int(out[2 * i + 1])} for i, k in enumerate(names)}
 
     def neighbors(self):
         lib = L.lib()

@@ -83,9 +83,12 @@ def _adversarial_cloud(dim, n, seed):
     return c["params"], x
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_cell_neighbors_equal_brute_force(orc, dim):
+@pytest.mark.parametrize("dim,cell", [(2, 1.0), (3, 1.0), (2, 0.5), (3, 1.0 / 3.0)])
+def test_cell_neighbors_equal_brute_force(orc, dim, cell):
+    """Cell-list sets equal brute force, at R = 2h (Algorithm 1) and at R = h,
+    2h/3 (wider stencil)."""
     pd, x = _adversarial_cloud(dim, 1500, seed=dim)
+    pd = dict(pd, cell_size=cell)
     ob, ib = orc.neighbors(pd, x, mode="brute")
     oc, ic = orc.neighbors(pd, x, mode="cells")
     assert np.array_equal(ob, oc)
