@@ -9,7 +9,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "lib", "libwbsph.so")
+LIB_PATH = os.environ.get("WBSPH_LIB") or os.path.join(HERE, "lib", "libwbsph.so")
 
 # status codes
 SPH_OK = 0

@@ -280,7 +280,7 @@ constexpr size_t kProfSlots = 512;
 
 void prof_drain(sph_ctx *c) {
   if (c->ev_used == 0) return;
-  hipStreamSynchronize(c->s);
+  (void)hipStreamSynchronize(c->s);
   for (size_t k = 0; k < c->ev_used; ++k) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev_a[k], c->ev_b[k]) == hipSuccess) {
@@ -301,10 +301,10 @@ struct ProfScope {
     if (c->ev_used == c->ev_a.size()) prof_drain(c);
     slot = c->ev_used++;
     c->ev_kind[slot] = kind;
-    hipEventRecord(c->ev_a[slot], c->s);
+    (void)hipEventRecord(c->ev_a[slot], c->s);
   }
   ~ProfScope() {
-    if (on) hipEventRecord(c->ev_b[slot], c->s);
+    if (on) (void)hipEventRecord(c->ev_b[slot], c->s);
   }
 };
 
@@ -455,8 +455,8 @@ const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 void sph_destroy(sph_ctx *ctx) {
   if (!ctx) return;
-  for (auto ev : ctx->ev_a) hipEventDestroy(ev);
-  for (auto ev : ctx->ev_b) hipEventDestroy(ev);
+  for (auto ev : ctx->ev_a) (void)hipEventDestroy(ev);
+  for (auto ev : ctx->ev_b) (void)hipEventDestroy(ev);
   delete ctx;
 }
 

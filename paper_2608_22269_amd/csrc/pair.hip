@@ -22,7 +22,27 @@
 
 namespace wb {
 
-constexpr int kList = 32;  // LDS list entries per lane
+// Compile-time tuning of the pair pass (values chosen by measurement on the
+// 17.5M-particle sloshing tank; they change speed, never results).
+#ifndef WB_PAIR_LIST
+#define WB_PAIR_LIST 32
+#endif
+#ifndef WB_PAIR_BATCH
+#define WB_PAIR_BATCH 4
+#endif
+#ifndef WB_PAIR_PREFETCH
+#define WB_PAIR_PREFETCH 0
+#endif
+#ifndef WB_PAIR_WAVES
+#define WB_PAIR_WAVES 3
+#endif
+constexpr int kList = WB_PAIR_LIST;    // LDS list entries per lane
+constexpr int kBatch = WB_PAIR_BATCH;  // candidates fetched per phase-1 iteration
+#if WB_PAIR_WAVES > 0
+#define WB_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(WB_PAIR_WAVES)))
+#else
+#define WB_PAIR_ATTR
+#endif
 
 __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
   // wave-aggregated atomic append; returns the slot of this lane (valid if pred)
@@ -100,7 +120,7 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
 // ----------------------------------------------------------- pair pass
 
 template <int DIM, bool FEAT>
-__global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
+__global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
                                                   const double4 *__restrict__ rec1, const uint32_t *__restrict__ cs_f,
                                                   const uint32_t *__restrict__ cs_d, uint32_t nf, Scalars *sc,
                                                   Rates out, uint32_t *__restrict__ cand) {
@@ -120,7 +140,7 @@ __global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 
 
   double L[6] = {0, 0, 0, 0, 0, 0};
   double gs[3] = {0, 0, 0}, SR[3] = {0, 0, 0}, SC[3] = {0, 0, 0}, Ps[3] = {0, 0, 0};
-  double N[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double N[6] = {0, 0, 0, 0, 0, 0};
   double Ds = 0.0;
   double S0 = 0.0, m1[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0}, qmin = 2.0;
   uint32_t nnb = 0, ndum = 0, ntest = 0;
@@ -128,25 +148,53 @@ __global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 
   const bool pst4 = P.pst_n == 4.0;
 
   for (;;) {
-    // phase 1: compact in-range candidates into this lane's LDS column
+    // phase 1: compact in-range candidates into this lane's LDS column.  Runs
+    // are contiguous, so four candidates are fetched per iteration with
+    // independent loads (the last index is clamped, never read out of range).
     int cnt = 0;
-    while (!done && cnt < kList) {
-      uint32_t j = w.cur;
-      if (j != i) {
-        double4 b = rec0[j];
-        double r2 = dist2_exact<DIM>(b.x - a0.x, b.y - a0.y, b.z - a0.z);
-        ++ntest;
-        if (r2 <= P.two_h2) {
+    while (!done && cnt <= kList - kBatch) {
+      const uint32_t j0 = w.cur;
+      const uint32_t rem = w.end - j0;
+      const uint32_t last = w.end - 1;
+      double4 b[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) b[k] = rec0[min(j0 + (uint32_t)k, last)];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const uint32_t j = j0 + k;
+        const double r2 = dist2_exact<DIM>(b[k].x - a0.x, b[k].y - a0.y, b[k].z - a0.z);
+        if ((uint32_t)k < rem && j != i && r2 <= P.two_h2) {
           list[cnt][tid] = j;
           ++cnt;
         }
       }
-      if (++w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf, a0.x, a0.y, a0.z, P.two_h);
+      const uint32_t took = rem < (uint32_t)kBatch ? rem : (uint32_t)kBatch;
+      ntest += took;
+      w.cur = j0 + took;
+      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf, a0.x, a0.y, a0.z, P.two_h);
     }
-    // phase 2: dense pair body over the list
+    // phase 2: dense pair body over the list, next records prefetched
+    double4 n0 = make_double4(0.0, 0.0, 0.0, 0.0), n1 = n0;
+    uint32_t jn = 0;
+    if (cnt > 0) {
+      jn = list[0][tid];
+      n0 = rec0[jn];
+      n1 = rec1[jn];
+    }
     for (int k = 0; k < cnt; ++k) {
-      const uint32_t j = list[k][tid];
-      const double4 b0 = rec0[j], b1 = rec1[j];
+      const uint32_t j = jn;
+      double4 b0 = n0, b1 = n1;
+      if (!WB_PAIR_PREFETCH && k > 0) {
+        b0 = rec0[j];
+        b1 = rec1[j];
+      }
+      if (WB_PAIR_PREFETCH && k + 1 < cnt) {
+        jn = list[k + 1][tid];
+        n0 = rec0[jn];
+        n1 = rec1[jn];
+      } else if (!WB_PAIR_PREFETCH && k + 1 < cnt) {
+        jn = list[k + 1][tid];
+      }
       const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
       const double r2 = dist2_exact<DIM>(rx, ry, rz);
       coincident |= (r2 == 0.0);
@@ -182,17 +230,16 @@ __global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 
         SR[2] += c2 * gz;
         SC[2] += cs * gz;
       }
-      // N_ab = sum (U_j - U_i)_a (grad W V)_b
+      // symmetric part of N_ab = sum (U_j - U_i)_a (grad W V)_b: L^-1 is
+      // symmetric, so tr(L^-1 N) only sees N + N^T (packed xx yy zz xy xz yz,
+      // off-diagonals hold N_ab + N_ba)
       N[0] += dux * gx;
-      N[1] += dux * gy;
-      N[3] += duy * gx;
-      N[4] += duy * gy;
+      N[1] += duy * gy;
+      N[3] += dux * gy + duy * gx;
       if (DIM == 3) {
-        N[2] += dux * gz;
-        N[5] += duy * gz;
-        N[6] += duz * gx;
-        N[7] += duz * gy;
-        N[8] += duz * gz;
+        N[2] += duz * gz;
+        N[4] += dux * gz + duz * gx;
+        N[5] += duy * gz + duz * gy;
       }
       Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
       const double W = P.alpha * t2 * t2 * (2.0 * q + 1.0);
@@ -248,12 +295,11 @@ __global__ void __launch_bounds__(256) k_pair_f64(Phys P, Grid g, const double4 
   // continuity: -C0^2 tr(L^-1 N) (+ delta-SPH)
   double div;
   if (singular || (tic && (flags & SPH_F_CONT_UNCORR))) {
-    div = N[0] + N[4] + (DIM == 3 ? N[8] : 0.0);
+    div = N[0] + N[1] + (DIM == 3 ? N[2] : 0.0);
   } else if (DIM == 2) {
-    div = I[0] * N[0] + I[3] * N[1] + I[3] * N[3] + I[1] * N[4];
+    div = I[0] * N[0] + I[1] * N[1] + I[3] * N[3];
   } else {
-    div = I[0] * N[0] + I[3] * N[1] + I[4] * N[2] + I[3] * N[3] + I[1] * N[4] + I[5] * N[5] + I[4] * N[6] +
-          I[5] * N[7] + I[2] * N[8];
+    div = I[0] * N[0] + I[1] * N[1] + I[2] * N[2] + I[3] * N[3] + I[4] * N[4] + I[5] * N[5];
   }
   double dphi = -P.c0 * P.c0 * div;
   if (flags & SPH_F_DELTA) dphi += P.delta * P.h * P.c0 * (2.0 * Ds);
