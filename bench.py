@@ -159,6 +159,8 @@ def main():
                          "candidates for the same neighbour sets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="fp64")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (slab decomposition is designed, "
@@ -174,6 +176,13 @@ def main():
     case = wl.slosh3d(dx=args.dx)
     h = case["params"]["h"]
     case = wl.with_params(case, cell_size=args.cell * h)
+    if args.calib:
+        src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src_t, dst_t
     results = {}
     for path in args.paths.split(","):
         if path == "fp64":
