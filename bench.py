@@ -158,7 +158,7 @@ def main():
                     help="background cell size in units of h (the paper's R = 2h is 2.0; R = h visits fewer "
                          "candidates for the same neighbour sets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paths", default="fp64")
+    ap.add_argument("--paths", default="fp64,mixed")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -187,6 +187,8 @@ def main():
     for path in args.paths.split(","):
         if path == "fp64":
             results["fp64"] = run_path(case, "fp64", args.steps, args.warmup)
+        elif path == "mixed":
+            results["mixed"] = run_path(wl.with_params(case, precision="mixed"), "mixed", args.steps, args.warmup)
         else:
             raise SystemExit(f"unknown path {path}")
     head = results["fp64"]
@@ -214,6 +216,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.dx)
+    if "mixed" in results:
+        out["mixed_over_fp64_step_rate"] = results["fp64"]["ms_per_step"] / results["mixed"]["ms_per_step"]
     out["spurious_u_fp64_tank2d_100steps"] = spurious_velocity()
     print(json.dumps(out), flush=True)
 

@@ -230,6 +230,7 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
     }
     c->mrec.r0 = cv.take<float4>(nf + nd);
     c->mrec.r1 = cv.take<float4>(nf + nd);
+    c->mrec.xa = cv.take<float4>(nf + nd);
     c->mrec.phi = f64(nf + nd);
   }
   c->rec0 = mixed ? nullptr : cv.take<double4>(nf + nd);
@@ -844,7 +845,7 @@ extern "C" sph_status sph_fields(sph_ctx *c, int32_t field, void *out, int32_t o
   }
   if (c->mixed && (field == SPH_FIELD_X || field == SPH_FIELD_U || field == SPH_FIELD_PHI || field == SPH_FIELD_RHO ||
                    field == SPH_FIELD_P || field == SPH_FIELD_MASS || field == SPH_FIELD_CELL)) {
-    e = launch_fields_mixed(c->P, c->g, c->mcur, nf, field, dst, s);
+    e = launch_fields_mixed(c->P, c->g, c->mcur, nf, field, dst, s, (uint32_t)c->n);
   } else {
     switch (field) {
       case SPH_FIELD_X:
@@ -880,15 +881,15 @@ extern "C" sph_status sph_fields(sph_ctx *c, int32_t field, void *out, int32_t o
       }
       case SPH_FIELD_U:
         if (!c->mixed) e = launch_gather_rec(c->rec1 + nf, c->dm.id, nd, dd, dim, 0, dim, s, (uint32_t)c->n);
-        else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s);
+        else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s, (uint32_t)c->n);
         break;
       case SPH_FIELD_PHI:
         if (!c->mixed) e = launch_gather_rec(c->rec0 + nf, c->dm.id, nd, dd, 1, 3, 1, s, (uint32_t)c->n);
-        else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s);
+        else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s, (uint32_t)c->n);
         break;
       case SPH_FIELD_RHO: case SPH_FIELD_P:
         if (!c->mixed) e = launch_rho_p_rec(c->P, c->rec0 + nf, c->dm.id, nd, dd, field == SPH_FIELD_RHO ? 0 : 1, s, (uint32_t)c->n);
-        else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s);
+        else e = launch_dummy_fields_mixed(c->P, c->mrec, nf, c->dm.id, nd, field, dst, s, (uint32_t)c->n);
         break;
       case SPH_FIELD_MIRROR_SRC:
         if (nd > 0)

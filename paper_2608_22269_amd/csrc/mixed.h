@@ -10,9 +10,9 @@ namespace wb {
 
 // Neighbour-facing records of the mixed path (fluid rows then dummy rows):
 // r0 = (offset x, y, z, packed cell as float bits), r1 = (u, v, w, V) in FP32,
-// phi in FP64.
+// phi in FP64, xa = FP32 absolute position (candidate tests only).
 struct MixedRec {
-  float4 *r0, *r1;
+  float4 *r0, *r1, *xa;
   double *phi;
 };
 
@@ -34,9 +34,9 @@ hipError_t launch_stage_mixed(const Phys &P, const Grid &g, const FluidMixed &f,
                               const Scalars *sc, int stage, hipStream_t s);
 // state fields of the fluid rows (x, u, phi, rho, p, mass, cell) in original order
 hipError_t launch_fields_mixed(const Phys &P, const Grid &g, const FluidMixed &f, int64_t nf, int field, void *dst,
-                               hipStream_t s);
+                               hipStream_t s, uint32_t nout);
 // dummy rows of u, phi, rho, p from the mixed records
 hipError_t launch_dummy_fields_mixed(const Phys &P, const MixedRec &rec, int64_t nf, const uint32_t *did, int64_t nd,
-                                     int field, void *dst, hipStream_t s);
+                                     int field, void *dst, hipStream_t s, uint32_t nout);
 
 }  // namespace wb

@@ -1,11 +1,623 @@
+// Mixed-precision path.
+//
+// Storage: each fluid particle's position is its background cell (packed
+// ix | iy << 11 | iz << 22) plus an FP32 offset inside the cell, with a Kahan
+// compensation; velocity FP32 with a Kahan compensation; the potential FP64.
+// The offset keeps ~2^-24 R resolution anywhere in the domain (a few 1e-10 m
+// at R = h = 2.6 mm), where absolute FP32 positions would give ~6e-8 m.
+//
+// Pair pass: candidate tests on FP32 absolute positions (set membership only
+// changes for pairs within ~1e-7 m of 2h, whose terms vanish like (1-q/2)^3);
+// the pair vector r from cell difference and offsets in FP32; W, grad W, the
+// Lax-Friedrichs, shifting and delta-SPH terms in FP32.  The correction
+// matrix L, the Riemann sum S_R and the conservative sum S_C accumulate in
+// FP64 from the same promoted r and grad W V, so L^-T S_R reproduces a linear
+// potential to FP64 round-off whatever the FP32 rounding of r and grad W (the
+// correction is kept outside the sum, Sec. 3).  The remaining sums use FP32
+// partial sums per LDS chunk (<= 32 neighbours) flushed into FP64 totals.  The
+// epilogue (eigenvalues, solves, branches) is the FP64 one of the FP64 path.
+//
+// Integrator: SSP-RK2 in its incremental form -- stage 1 adds dt*rate(q0),
+// stage 2 adds (dt*rate(q1) - dt*rate(q0)) / 2, equal in exact arithmetic to
+// q0/2 + (q1 + dt*rate(q1))/2 -- with Kahan-compensated FP32 adds for offsets
+// and velocity, then the offset is brought back into [0, R) by moving cells.
 #include "mixed.h"
+#include "pair_common.h"
+
 namespace wb {
-hipError_t launch_to_mixed(const Phys &, const Grid &, const FluidF64 &, int64_t, const FluidMixed &, Scalars *, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_reorder_mixed(const Phys &, const Grid &, const uint32_t *, int64_t, const FluidMixed &, const FluidMixed &, const MixedRec &, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_mirror_mixed(const Phys &, const Grid &, const Dummies &, int64_t, const MixedRec &, const uint32_t *, uint32_t, const Scalars *, hipStream_t, const uint32_t *) { return hipErrorNotSupported; }
-hipError_t launch_pair_mixed(const Phys &, const Grid &, const MixedRec &, const uint32_t *, const uint32_t *, uint32_t, Scalars *, const Rates &, uint32_t *, bool, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_scan_mixed(const Phys &, const Grid &, const MixedRec &, const uint32_t *, const uint32_t *, uint32_t, const uint32_t *, const uint32_t *, const Rates &, Scalars *, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_stage_mixed(const Phys &, const Grid &, const FluidMixed &, const Rates &, int64_t, const Scalars *, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_fields_mixed(const Phys &, const Grid &, const FluidMixed &, int64_t, int, void *, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_dummy_fields_mixed(const Phys &, const MixedRec &, int64_t, const uint32_t *, int64_t, int, void *, hipStream_t) { return hipErrorNotSupported; }
+
+#ifndef WB_MIXED_WAVES
+#define WB_MIXED_WAVES 3
+#endif
+#if WB_MIXED_WAVES > 0
+#define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(WB_MIXED_WAVES)))
+#else
+#define WB_MIXED_ATTR
+#endif
+constexpr int kMList = 32;
+constexpr int kMBatch = 4;
+
+__device__ __forceinline__ uint32_t pack_cell(int x, int y, int z) {
+  return (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)z << 22);
 }
+__device__ __forceinline__ int cell_x(uint32_t c) { return (int)(c & 2047u); }
+__device__ __forceinline__ int cell_y(uint32_t c) { return (int)((c >> 11) & 2047u); }
+__device__ __forceinline__ int cell_z(uint32_t c) { return (int)(c >> 22); }
+
+// Kahan-compensated add of an FP64 increment to an FP32 sum; s - c is the
+// represented value.
+__device__ __forceinline__ void kahan_add(float &s, float &c, double d) {
+  float y = (float)(d + (double)c * -1.0);
+  float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// Position along one axis reconstructed in FP64: lo + c R + (o - oc).
+__device__ __forceinline__ double pos_of(double lo, double R, int c, float o) {
+  return lo + (double)c * R + (double)o;
+}
+
+// ------------------------------------------------------------ conversion
+
+template <int DIM>
+__global__ void k_to_mixed(Phys P, Grid g, FluidF64 src, int64_t n, FluidMixed dst, Scalars *sc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c[3] = {0, 0, 0};
+  for (int a = 0; a < DIM; ++a) {
+    double x = src.x[a][i];
+    int ca = cell_coord(x, g.lo[a], g.R);
+    if (!(x >= g.lo[a] && x <= g.hi[a]) || ca < 0 || ca >= g.N[a]) {
+      atomicOr(&sc->err, kErrDomain);
+      ca = 0;
+    }
+    c[a] = ca;
+    dst.o[a][i] = (float)(x - (g.lo[a] + (double)ca * g.R));
+    dst.oc[a][i] = 0.0f;
+    dst.u[a][i] = (float)src.u[a][i];
+    dst.uc[a][i] = 0.0f;
+    dst.dx1[a][i] = 0.0f;
+    dst.du1[a][i] = 0.0f;
+  }
+  dst.cell[i] = pack_cell(c[0], c[1], c[2]);
+  dst.phi[i] = src.phi[i];
+  dst.dphi1[i] = 0.0;
+  dst.m[i] = (float)src.m[i];
+  dst.id[i] = src.id[i];
+}
+
+hipError_t launch_to_mixed(const Phys &P, const Grid &g, const FluidF64 &src, int64_t nf, const FluidMixed &dst,
+                           Scalars *sc, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_to_mixed<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, src, nf, dst, sc);
+  else
+    hipLaunchKernelGGL(k_to_mixed<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, src, nf, dst, sc);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- reorder
+
+// Gathers the mixed state into HashID order and writes the records:
+// r0 = (offset, cell bits), r1 = (U, V), phi, xa = FP32 absolute position.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_reorder_mixed(Phys P, Grid g, const uint32_t *__restrict__ perm, int64_t n,
+                                                       FluidMixed src, FluidMixed dst, MixedRec rec, int with_stage0) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint32_t o = perm[k];
+  uint32_t c = src.cell[o];
+  dst.cell[k] = c;
+  float of[3] = {0.f, 0.f, 0.f}, uf[3] = {0.f, 0.f, 0.f};
+  for (int a = 0; a < DIM; ++a) {
+    of[a] = src.o[a][o];
+    uf[a] = src.u[a][o];
+    dst.o[a][k] = of[a];
+    dst.oc[a][k] = src.oc[a][o];
+    dst.u[a][k] = uf[a];
+    dst.uc[a][k] = src.uc[a][o];
+    if (with_stage0) {
+      dst.dx1[a][k] = src.dx1[a][o];
+      dst.du1[a][k] = src.du1[a][o];
+    }
+  }
+  double ph = src.phi[o];
+  dst.phi[k] = ph;
+  float m = src.m[o];
+  dst.m[k] = m;
+  dst.id[k] = src.id[o];
+  if (with_stage0) dst.dphi1[k] = src.dphi1[o];
+  float V = (float)((double)m / (P.rho0 * exp(ph * P.inv_c02)));
+  int cc[3] = {cell_x(c), cell_y(c), cell_z(c)};
+  float xa[3] = {0.f, 0.f, 0.f};
+  for (int a = 0; a < DIM; ++a) xa[a] = (float)pos_of(g.lo[a], g.R, cc[a], of[a]);
+  rec.r0[k] = make_float4(of[0], of[1], of[2], __uint_as_float(c));
+  rec.r1[k] = make_float4(uf[0], uf[1], uf[2], V);
+  rec.phi[k] = ph;
+  rec.xa[k] = make_float4(xa[0], xa[1], xa[2], 0.f);
+}
+
+hipError_t launch_reorder_mixed(const Phys &P, const Grid &g, const uint32_t *perm, int64_t nf, const FluidMixed &src,
+                                const FluidMixed &dst, const MixedRec &rec, int with_stage0, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_reorder_mixed<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, perm, nf, src, dst, rec,
+                       with_stage0);
+  else
+    hipLaunchKernelGGL(k_reorder_mixed<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, perm, nf, src, dst, rec,
+                       with_stage0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- mirror
+
+// Dummy records of the mixed path (Sec. 2.4): nearest fluid particle within
+// 2h by the FP32 test (ties -> lower original index); phi_d = phi_f +
+// G.(x_d - x_f) with both positions in FP64; slip velocity; V_d = m_d/rho.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_mirror_mixed(Phys P, Grid g, Dummies d, int64_t nd, MixedRec rec,
+                                                      const uint32_t *__restrict__ cs_f, uint32_t nf,
+                                                      const Scalars *__restrict__ sc,
+                                                      const uint32_t *__restrict__ fid) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nd) return;
+  const double xd = d.x[0][k], yd = d.x[1][k], zd = DIM == 3 ? d.x[2][k] : 0.0;
+  const float xf = (float)xd, yf = (float)yd, zf = (float)zd;
+  const float two_h2 = (float)P.two_h2;
+  RowWalker w;
+  walker_init<DIM>(w, g, xd, yd, zd);
+  int64_t best = -1;
+  uint32_t best_id = 0;
+  float best_r2 = 0.f;
+  while (walker_next<DIM>(w, g, cs_f, cs_f, nf, xd, yd, zd, P.two_h)) {
+    if (w.cur >= nf) continue;
+    for (uint32_t j = w.cur; j < w.end; ++j) {
+      float4 b = rec.xa[j];
+      float dxv = b.x - xf, dyv = b.y - yf, dzv = DIM == 3 ? b.z - zf : 0.f;
+      float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
+      if (r2 <= two_h2) {
+        uint32_t jid = fid[j];
+        if (best < 0 || r2 < best_r2 || (r2 == best_r2 && jid < best_id)) {
+          best = j;
+          best_r2 = r2;
+          best_id = jid;
+        }
+      }
+    }
+  }
+  d.src[k] = (int32_t)best;
+  // static part of the record: cell and offset of the dummy
+  int c[3] = {0, 0, 0};
+  float of[3] = {0.f, 0.f, 0.f};
+  const double xs[3] = {xd, yd, zd};
+  for (int a = 0; a < DIM; ++a) {
+    c[a] = cell_coord(xs[a], g.lo[a], g.R);
+    of[a] = (float)(xs[a] - (g.lo[a] + (double)c[a] * g.R));
+  }
+  const uint32_t cb = pack_cell(c[0], c[1], c[2]);
+  const uint32_t o = nf + (uint32_t)k;
+  rec.r0[o] = make_float4(of[0], of[1], of[2], __uint_as_float(cb));
+  rec.xa[o] = make_float4(xf, yf, zf, 0.f);
+  if (best < 0) {
+    rec.r1[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+    rec.phi[o] = d.phi_in[k];
+    return;
+  }
+  double G[3];
+  body_force(P, sc->t_rhs, G);
+  const float4 f0 = rec.r0[best], f1 = rec.r1[best];
+  const uint32_t fc = __float_as_uint(f0.w);
+  const double xfs[3] = {pos_of(g.lo[0], g.R, cell_x(fc), f0.x), pos_of(g.lo[1], g.R, cell_y(fc), f0.y),
+                         DIM == 3 ? pos_of(g.lo[2], g.R, cell_z(fc), f0.z) : 0.0};
+  double gp = 0.0;
+  for (int a = 0; a < DIM; ++a) gp += G[a] * (xs[a] - xfs[a]);
+  const double phid = rec.phi[best] + gp;
+  const float nx = (float)d.n[0][k], ny = (float)d.n[1][k], nz = DIM == 3 ? (float)d.n[2][k] : 0.f;
+  const float un = f1.x * nx + f1.y * ny + f1.z * nz;
+  const float V = (float)(d.m[k] / (P.rho0 * exp(phid * P.inv_c02)));
+  rec.r1[o] = make_float4(f1.x - un * nx, f1.y - un * ny, DIM == 3 ? f1.z - un * nz : 0.f, V);
+  rec.phi[o] = phid;
+}
+
+hipError_t launch_mirror_mixed(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const MixedRec &rec,
+                               const uint32_t *cs_f, uint32_t nf, const Scalars *sc, hipStream_t s,
+                               const uint32_t *fid) {
+  if (nd <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_mirror_mixed<2>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec, cs_f, nf, sc, fid);
+  else
+    hipLaunchKernelGGL(k_mirror_mixed<3>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec, cs_f, nf, sc, fid);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- pair pass
+
+template <int DIM, bool FEAT>
+__global__ void __launch_bounds__(256) WB_MIXED_ATTR
+    k_pair_mixed(Phys P, Grid g, MixedRec rec, const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
+                 uint32_t nf, Scalars *sc, Rates out, uint32_t *__restrict__ cand) {
+  __shared__ uint32_t list[kMList][kBlock];
+  const int tid = threadIdx.x;
+  const uint32_t i = blockIdx.x * kBlock + tid;
+  const bool active = i < nf;
+
+  float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0, axa = a0;
+  double phii = 0.0;
+  if (active) {
+    a0 = rec.r0[i];
+    a1 = rec.r1[i];
+    axa = rec.xa[i];
+    phii = rec.phi[i];
+  }
+  const uint32_t ci = __float_as_uint(a0.w);
+  const int cix = cell_x(ci), ciy = cell_y(ci), ciz = cell_z(ci);
+  // the walker works on FP64 positions reconstructed from cell + offset
+  const double px = pos_of(g.lo[0], g.R, cix, a0.x), py = pos_of(g.lo[1], g.R, ciy, a0.y),
+               pz = DIM == 3 ? pos_of(g.lo[2], g.R, ciz, a0.z) : 0.0;
+  RowWalker w;
+  walker_init<DIM>(w, g, px, py, pz);
+  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf, px, py, pz, P.two_h);
+
+  const float two_h2 = (float)P.two_h2;
+  const double Rd = g.R;
+  const double oxi = a0.x, oyi = a0.y, ozi = a0.z;
+  const float inv_h = (float)P.inv_h, kfac = (float)P.kfac, alpha = (float)P.alpha, w0inv = (float)P.w0inv;
+  const float c0f = (float)P.c0, pstR = (float)P.pst_R;
+  const bool pst4 = P.pst_n == 4.0;
+
+  PairSums S;
+  sums_zero(S);
+
+  for (;;) {
+    int cnt = 0;
+    while (!done && cnt <= kMList - kMBatch) {
+      const uint32_t j0 = w.cur;
+      const uint32_t rem = w.end - j0;
+      const uint32_t last = w.end - 1;
+      float4 b[kMBatch];
+#pragma unroll
+      for (int k = 0; k < kMBatch; ++k) b[k] = rec.xa[min(j0 + (uint32_t)k, last)];
+#pragma unroll
+      for (int k = 0; k < kMBatch; ++k) {
+        const uint32_t j = j0 + k;
+        const float dx = b[k].x - axa.x, dy = b[k].y - axa.y, dz = DIM == 3 ? b[k].z - axa.z : 0.f;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if ((uint32_t)k < rem && j != i && r2 <= two_h2) {
+          list[cnt][tid] = j;
+          ++cnt;
+        }
+      }
+      const uint32_t took = rem < (uint32_t)kMBatch ? rem : (uint32_t)kMBatch;
+      S.ntest += took;
+      w.cur = j0 + took;
+      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf, px, py, pz, P.two_h);
+    }
+    // FP32 partial sums of this chunk (flushed into the FP64 totals below)
+    float gsf[3] = {0.f, 0.f, 0.f}, Nf[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, Pf[3] = {0.f, 0.f, 0.f}, Df = 0.f;
+    float S0f = 0.f, m1f[3] = {0.f, 0.f, 0.f}, m2f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t j = list[k][tid];
+      const float4 b0 = rec.r0[j], b1 = rec.r1[j];
+      const double phij = rec.phi[j];
+      const uint32_t cj = __float_as_uint(b0.w);
+      // r = (c_j - c_i) R + (o_j - o_i), formed in FP64 from the integer cell
+      // difference and the promoted offsets (one rounding): the same r enters
+      // L and S_R, and phi_j - phi_i of a linear potential equals G.r to FP64
+      // round-off.  Its FP32 rounding feeds the FP32 part of the body.
+      const double rxd = (double)(cell_x(cj) - cix) * Rd + ((double)b0.x - oxi);
+      const double ryd = (double)(cell_y(cj) - ciy) * Rd + ((double)b0.y - oyi);
+      const double rzd = DIM == 3 ? (double)(cell_z(cj) - ciz) * Rd + ((double)b0.z - ozi) : 0.0;
+      const float rx = (float)rxd, ry = (float)ryd, rz = (float)rzd;
+      const float r2 = rx * rx + ry * ry + rz * rz;
+      S.coincident |= (r2 == 0.f);
+      const float is = rsqrtf(r2);
+      const float s = r2 * is;
+      const float q = fminf(s * inv_h, 2.0f);
+      const float t = 1.0f - 0.5f * q;
+      const float t2 = t * t, t3 = t2 * t;
+      const float wv = kfac * t3 * b1.w;
+      const float gx = wv * rx, gy = wv * ry, gz = wv * rz;
+      // FP64: L, S_R, S_C from the same FP64 r and grad W V = wv r
+      const double wvd = wv;
+      const double gxd = wvd * rxd, gyd = wvd * ryd, gzd = wvd * rzd;
+      S.L[0] += rxd * gxd;
+      S.L[1] += ryd * gyd;
+      S.L[3] += rxd * gyd;
+      if (DIM == 3) {
+        S.L[2] += rzd * gzd;
+        S.L[4] += rxd * gzd;
+        S.L[5] += ryd * gzd;
+      }
+      const double dph = phij - phii;
+      const float dux = b1.x - a1.x, duy = b1.y - a1.y, duz = DIM == 3 ? b1.z - a1.z : 0.f;
+      const float dun = (dux * rx + duy * ry + duz * rz) * is;
+      const double c2 = dph - (double)(c0f * dun);
+      const double cs = phij + phii;
+      S.SR[0] += c2 * gxd;
+      S.SR[1] += c2 * gyd;
+      S.SC[0] += cs * gxd;
+      S.SC[1] += cs * gyd;
+      if (DIM == 3) {
+        S.SR[2] += c2 * gzd;
+        S.SC[2] += cs * gzd;
+      }
+      // FP32 chunk sums
+      gsf[0] += gx;
+      gsf[1] += gy;
+      if (DIM == 3) gsf[2] += gz;
+      Nf[0] += dux * gx;
+      Nf[1] += duy * gy;
+      Nf[3] += dux * gy + duy * gx;
+      if (DIM == 3) {
+        Nf[2] += duz * gz;
+        Nf[4] += dux * gz + duz * gx;
+        Nf[5] += duy * gz + duz * gy;
+      }
+      Df += wv * (float)dph;
+      const float W = alpha * t2 * t2 * (2.0f * q + 1.0f);
+      const float wr = W * w0inv;
+      const float wrn = pst4 ? (wr * wr) * (wr * wr) : powf(wr, (float)P.pst_n);
+      const float pw = 1.0f + pstR * wrn;
+      Pf[0] += pw * gx;
+      Pf[1] += pw * gy;
+      if (DIM == 3) Pf[2] += pw * gz;
+      if (FEAT) {
+        const float WV = W * b1.w;
+        S0f += WV;
+        m1f[0] += WV * rx;
+        m1f[1] += WV * ry;
+        m2f[0] += WV * rx * rx;
+        m2f[1] += WV * ry * ry;
+        m2f[3] += WV * rx * ry;
+        if (DIM == 3) {
+          m1f[2] += WV * rz;
+          m2f[2] += WV * rz * rz;
+          m2f[4] += WV * rx * rz;
+          m2f[5] += WV * ry * rz;
+        }
+        S.qmin = fmin(S.qmin, (double)q);
+        S.ndum += (j >= nf) ? 1u : 0u;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      S.gs[a] += gsf[a];
+      S.Ps[a] += Pf[a];
+      S.m1[a] += m1f[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      S.N[a] += Nf[a];
+      S.m2[a] += m2f[a];
+    }
+    S.Ds += Df;
+    S.S0 += S0f;
+    S.nnb += cnt;
+    if (done) break;
+  }
+  pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
+}
+
+hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
+                             const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
+                             bool features, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  dim3 gr(grid_for(nf)), bl(kBlock);
+  if (P.dim == 2) {
+    if (features)
+      hipLaunchKernelGGL((k_pair_mixed<2, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+    else
+      hipLaunchKernelGGL((k_pair_mixed<2, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+  } else {
+    if (features)
+      hipLaunchKernelGGL((k_pair_mixed<3, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+    else
+      hipLaunchKernelGGL((k_pair_mixed<3, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- scan-region pass
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_scan_mixed(Phys P, Grid g, MixedRec rec, const uint32_t *__restrict__ cs_f,
+                                                    const uint32_t *__restrict__ cs_d, uint32_t nf,
+                                                    const uint32_t *__restrict__ list,
+                                                    const uint32_t *__restrict__ count, Rates out, Scalars *sc) {
+  const uint32_t total = *count;
+  const double two_h2_scan = 2.0 * P.h * P.h;
+  const double h2 = P.h * P.h;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+    const uint32_t i = list[k];
+    const float4 a = rec.r0[i];
+    const uint32_t ci = __float_as_uint(a.w);
+    const double px = pos_of(g.lo[0], g.R, cell_x(ci), a.x), py = pos_of(g.lo[1], g.R, cell_y(ci), a.y),
+                 pz = DIM == 3 ? pos_of(g.lo[2], g.R, cell_z(ci), a.z) : 0.0;
+    const double n0 = out.nrm[0][i], n1 = out.nrm[1][i], n2 = DIM == 3 ? out.nrm[2][i] : 0.0;
+    const double T0 = px + P.h * n0, T1 = py + P.h * n1, T2 = DIM == 3 ? pz + P.h * n2 : 0.0;
+    RowWalker w;
+    walker_init<DIM>(w, g, px, py, pz);
+    bool covered = false;
+    while (!covered && walker_next<DIM>(w, g, cs_f, cs_d, nf, px, py, pz, P.two_h)) {
+      for (uint32_t j = w.cur; j < w.end && !covered; ++j) {
+        if (j == i) continue;
+        const float4 b = rec.r0[j];
+        const uint32_t cj = __float_as_uint(b.w);
+        const double qx = pos_of(g.lo[0], g.R, cell_x(cj), b.x), qy = pos_of(g.lo[1], g.R, cell_y(cj), b.y),
+                     qz = DIM == 3 ? pos_of(g.lo[2], g.R, cell_z(cj), b.z) : 0.0;
+        const double s2 = (qx - px) * (qx - px) + (qy - py) * (qy - py) + (qz - pz) * (qz - pz);
+        if (s2 > P.two_h2) continue;
+        const double d0 = qx - T0, d1 = qy - T1, d2 = DIM == 3 ? qz - T2 : 0.0;
+        if (s2 >= two_h2_scan) {
+          covered = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
+        } else {
+          const double dn = n0 * d0 + n1 * d1 + n2 * d2;
+          const double e0 = d0 - dn * n0, e1 = d1 - dn * n1, e2 = d2 - dn * n2;
+          covered = fabs(dn) + sqrt(e0 * e0 + e1 * e1 + e2 * e2) < P.h;
+        }
+      }
+    }
+    uint32_t fl = out.flags[i] | kFlagByScan;
+    if (!covered) {
+      fl |= kFlagFS;
+      if ((P.flags & SPH_F_FS_PROJECT) && (P.flags & SPH_F_PST)) {
+        double u0 = out.dus[0][i], u1 = out.dus[1][i], u2 = DIM == 3 ? out.dus[2][i] : 0.0;
+        double d = u0 * n0 + u1 * n1 + u2 * n2;
+        out.dus[0][i] = u0 - d * n0;
+        out.dus[1][i] = u1 - d * n1;
+        if (DIM == 3) out.dus[2][i] = u2 - d * n2;
+      }
+      atomicAdd(&sc->n_fs, 1u);
+    }
+    out.flags[i] = fl;
+  }
+}
+
+hipError_t launch_scan_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
+                             const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
+                             const Rates &out, Scalars *sc, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  unsigned blocks = grid_for(nf);
+  if (blocks > 2048) blocks = 2048;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_scan_mixed<2>, dim3(blocks), dim3(kBlock), 0, s, P, g, rec, cs_f, cs_d, nf, list, count, out,
+                       sc);
+  else
+    hipLaunchKernelGGL(k_scan_mixed<3>, dim3(blocks), dim3(kBlock), 0, s, P, g, rec, cs_f, cs_d, nf, list, count, out,
+                       sc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ integration
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_stage_mixed(Grid g, FluidMixed f, Rates r, int64_t n,
+                                                     const Scalars *__restrict__ sc, int stage) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double dt = sc->dt;
+  uint32_t c = f.cell[i];
+  int cc[3] = {cell_x(c), cell_y(c), cell_z(c)};
+  for (int a = 0; a < DIM; ++a) {
+    float o = f.o[a][i], oc = f.oc[a][i], u = f.u[a][i], uc = f.uc[a][i];
+    // position first (uses the stage's velocity), then velocity
+    const double vx = ((double)u - (double)uc + r.dus[a][i]) * dt;
+    const double va = r.acc[a][i] * dt;
+    if (stage == 1) {
+      kahan_add(o, oc, vx);
+      kahan_add(u, uc, va);
+      f.dx1[a][i] = (float)vx;
+      f.du1[a][i] = (float)va;
+    } else {
+      kahan_add(o, oc, 0.5 * (vx - (double)f.dx1[a][i]));
+      kahan_add(u, uc, 0.5 * (va - (double)f.du1[a][i]));
+    }
+    // keep the offset inside its cell: move whole cells, subtract k R exactly
+    const double ov = (double)o - (double)oc;
+    const int kc = (int)floor(ov / g.R);
+    if (kc != 0) {
+      cc[a] += kc;
+      kahan_add(o, oc, -(double)kc * g.R);
+    }
+    f.o[a][i] = o;
+    f.oc[a][i] = oc;
+    f.u[a][i] = u;
+    f.uc[a][i] = uc;
+  }
+  // cells outside the grid are caught by the next hash (domain error); keep
+  // the packed fields from wrapping meanwhile
+  for (int a = 0; a < 3; ++a) cc[a] = min(max(cc[a], 0), a == 2 ? 1023 : 2047);
+  f.cell[i] = pack_cell(cc[0], cc[1], cc[2]);
+  const double dp = r.dphi[i] * dt;
+  if (stage == 1) {
+    f.phi[i] += dp;
+    f.dphi1[i] = dp;
+  } else {
+    f.phi[i] += 0.5 * (dp - f.dphi1[i]);
+  }
+}
+
+hipError_t launch_stage_mixed(const Phys &P, const Grid &g, const FluidMixed &f, const Rates &r, int64_t nf,
+                              const Scalars *sc, int stage, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_stage_mixed<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, g, f, r, nf, sc, stage);
+  else
+    hipLaunchKernelGGL(k_stage_mixed<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, g, f, r, nf, sc, stage);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- fields
+
+template <int DIM>
+__global__ void k_fields_mixed(Phys P, Grid g, FluidMixed f, int64_t n, int field, void *dst, uint32_t nout) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t id = f.id[k];
+  if (id >= nout) return;
+  const uint32_t c = f.cell[k];
+  const int cc[3] = {cell_x(c), cell_y(c), cell_z(c)};
+  double *dd = (double *)dst;
+  int32_t *di = (int32_t *)dst;
+  switch (field) {
+    case SPH_FIELD_X:
+      for (int a = 0; a < DIM; ++a)
+        dd[(int64_t)id * DIM + a] = g.lo[a] + (double)cc[a] * g.R + ((double)f.o[a][k] - (double)f.oc[a][k]);
+      break;
+    case SPH_FIELD_U:
+      for (int a = 0; a < DIM; ++a) dd[(int64_t)id * DIM + a] = (double)f.u[a][k] - (double)f.uc[a][k];
+      break;
+    case SPH_FIELD_PHI: dd[id] = f.phi[k]; break;
+    case SPH_FIELD_MASS: dd[id] = (double)f.m[k]; break;
+    case SPH_FIELD_RHO: dd[id] = P.rho0 * exp(f.phi[k] * P.inv_c02); break;
+    case SPH_FIELD_P: dd[id] = P.c0 * P.c0 * (P.rho0 * exp(f.phi[k] * P.inv_c02) - P.rho0); break;
+    case SPH_FIELD_CELL:
+      for (int a = 0; a < 3; ++a) di[(int64_t)id * 3 + a] = cc[a];
+      break;
+    default: break;
+  }
+}
+
+hipError_t launch_fields_mixed(const Phys &P, const Grid &g, const FluidMixed &f, int64_t nf, int field, void *dst,
+                               hipStream_t s, uint32_t nout) {
+  if (nf <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_fields_mixed<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, f, nf, field, dst, nout);
+  else
+    hipLaunchKernelGGL(k_fields_mixed<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, f, nf, field, dst, nout);
+  return hipGetLastError();
+}
+
+__global__ void k_dummy_fields_mixed(Phys P, MixedRec rec, int64_t nf, const uint32_t *__restrict__ did, int64_t nd,
+                                     int field, void *dst, int dim, uint32_t nout) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nd) return;
+  const uint32_t id = did[k];
+  if (id >= nout) return;
+  double *dd = (double *)dst;
+  const int64_t o = nf + k;
+  const double ph = rec.phi[o];
+  switch (field) {
+    case SPH_FIELD_U: {
+      const float4 v = rec.r1[o];
+      const float c[3] = {v.x, v.y, v.z};
+      for (int a = 0; a < dim; ++a) dd[(int64_t)id * dim + a] = (double)c[a];
+      break;
+    }
+    case SPH_FIELD_PHI: dd[id] = ph; break;
+    case SPH_FIELD_RHO: dd[id] = P.rho0 * exp(ph * P.inv_c02); break;
+    case SPH_FIELD_P: dd[id] = P.c0 * P.c0 * (P.rho0 * exp(ph * P.inv_c02) - P.rho0); break;
+    default: break;
+  }
+}
+
+hipError_t launch_dummy_fields_mixed(const Phys &P, const MixedRec &rec, int64_t nf, const uint32_t *did, int64_t nd,
+                                     int field, void *dst, hipStream_t s, uint32_t nout) {
+  if (nd <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dummy_fields_mixed, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, rec, nf, did, nd, field, dst,
+                     P.dim, nout);
+  return hipGetLastError();
+}
+
+}  // namespace wb

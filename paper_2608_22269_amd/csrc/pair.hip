@@ -19,6 +19,7 @@
 // real neighbours only instead of every candidate of the 3^d cells.
 #include "common.h"
 #include "kernels.h"
+#include "pair_common.h"
 
 namespace wb {
 
@@ -43,24 +44,6 @@ constexpr int kBatch = WB_PAIR_BATCH;  // candidates fetched per phase-1 iterati
 #else
 #define WB_PAIR_ATTR
 #endif
-
-__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
-  // wave-aggregated atomic append; returns the slot of this lane (valid if pred)
-  unsigned long long mask = __ballot(pred);
-  uint32_t base = 0;
-  if (mask) {
-    int leader = __ffsll((long long)mask) - 1;
-    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader, 64);
-  }
-  return base + (uint32_t)__popcll(mask & __lanemask_lt());
-}
-
-__device__ __forceinline__ void wave_count(uint32_t *counter, bool pred) {
-  unsigned long long mask = __ballot(pred);
-  if (mask && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)mask) - 1))
-    atomicAdd(counter, (uint32_t)__popcll(mask));
-}
 
 // ------------------------------------------------------------------ mirror
 
@@ -138,13 +121,8 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
   walker_init<DIM>(w, g, a0.x, a0.y, a0.z);
   bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf, a0.x, a0.y, a0.z, P.two_h);
 
-  double L[6] = {0, 0, 0, 0, 0, 0};
-  double gs[3] = {0, 0, 0}, SR[3] = {0, 0, 0}, SC[3] = {0, 0, 0}, Ps[3] = {0, 0, 0};
-  double N[6] = {0, 0, 0, 0, 0, 0};
-  double Ds = 0.0;
-  double S0 = 0.0, m1[3] = {0, 0, 0}, m2[6] = {0, 0, 0, 0, 0, 0}, qmin = 2.0;
-  uint32_t nnb = 0, ndum = 0, ntest = 0;
-  bool coincident = false;
+  PairSums S;
+  sums_zero(S);
   const bool pst4 = P.pst_n == 4.0;
 
   for (;;) {
@@ -169,7 +147,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
         }
       }
       const uint32_t took = rem < (uint32_t)kBatch ? rem : (uint32_t)kBatch;
-      ntest += took;
+      S.ntest += took;
       w.cur = j0 + took;
       if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf, a0.x, a0.y, a0.z, P.two_h);
     }
@@ -197,7 +175,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
       }
       const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
       const double r2 = dist2_exact<DIM>(rx, ry, rz);
-      coincident |= (r2 == 0.0);
+      S.coincident |= (r2 == 0.0);
       const double is = rsqrt(r2);
       const double s = r2 * is;
       const double q = s * P.inv_h;
@@ -205,221 +183,73 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
       const double t2 = t * t, t3 = t2 * t;
       const double wv = P.kfac * t3 * b1.w;  // |grad W| / |r| times V_j
       const double gx = wv * rx, gy = wv * ry, gz = wv * rz;
-      // L = sum r (x) grad W V  (symmetric for the radial kernel)
-      L[0] += rx * gx;
-      L[1] += ry * gy;
-      L[3] += rx * gy;
+      // S.L = sum r (x) grad W V  (symmetric for the radial kernel)
+      S.L[0] += rx * gx;
+      S.L[1] += ry * gy;
+      S.L[3] += rx * gy;
       if (DIM == 3) {
-        L[2] += rz * gz;
-        L[4] += rx * gz;
-        L[5] += ry * gz;
+        S.L[2] += rz * gz;
+        S.L[4] += rx * gz;
+        S.L[5] += ry * gz;
       }
-      gs[0] += gx;
-      gs[1] += gy;
-      if (DIM == 3) gs[2] += gz;
+      S.gs[0] += gx;
+      S.gs[1] += gy;
+      if (DIM == 3) S.gs[2] += gz;
       const double dph = b0.w - a0.w;
       const double dux = b1.x - a1.x, duy = b1.y - a1.y, duz = DIM == 3 ? b1.z - a1.z : 0.0;
       const double dun = (dux * rx + duy * ry + duz * rz) * is;
       const double c2 = dph - P.c0 * dun;  // 2 (phi*_ij - phi_i)
       const double cs = b0.w + a0.w;        // conservative form
-      SR[0] += c2 * gx;
-      SR[1] += c2 * gy;
-      SC[0] += cs * gx;
-      SC[1] += cs * gy;
+      S.SR[0] += c2 * gx;
+      S.SR[1] += c2 * gy;
+      S.SC[0] += cs * gx;
+      S.SC[1] += cs * gy;
       if (DIM == 3) {
-        SR[2] += c2 * gz;
-        SC[2] += cs * gz;
+        S.SR[2] += c2 * gz;
+        S.SC[2] += cs * gz;
       }
-      // symmetric part of N_ab = sum (U_j - U_i)_a (grad W V)_b: L^-1 is
-      // symmetric, so tr(L^-1 N) only sees N + N^T (packed xx yy zz xy xz yz,
+      // symmetric part of N_ab = sum (U_j - U_i)_a (grad W V)_b: S.L^-1 is
+      // symmetric, so tr(S.L^-1 S.N) only sees S.N + S.N^T (packed xx yy zz xy xz yz,
       // off-diagonals hold N_ab + N_ba)
-      N[0] += dux * gx;
-      N[1] += duy * gy;
-      N[3] += dux * gy + duy * gx;
+      S.N[0] += dux * gx;
+      S.N[1] += duy * gy;
+      S.N[3] += dux * gy + duy * gx;
       if (DIM == 3) {
-        N[2] += duz * gz;
-        N[4] += dux * gz + duz * gx;
-        N[5] += duy * gz + duz * gy;
+        S.N[2] += duz * gz;
+        S.N[4] += dux * gz + duz * gx;
+        S.N[5] += duy * gz + duz * gy;
       }
-      Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
+      S.Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
       const double W = P.alpha * t2 * t2 * (2.0 * q + 1.0);
       const double wr = W * P.w0inv;
       const double wrn = pst4 ? (wr * wr) * (wr * wr) : pow(wr, P.pst_n);
       const double pw = 1.0 + P.pst_R * wrn;
-      Ps[0] += pw * gx;
-      Ps[1] += pw * gy;
-      if (DIM == 3) Ps[2] += pw * gz;
+      S.Ps[0] += pw * gx;
+      S.Ps[1] += pw * gy;
+      if (DIM == 3) S.Ps[2] += pw * gz;
       if (FEAT) {
         const double WV = W * b1.w;
-        S0 += WV;
-        m1[0] += WV * rx;
-        m1[1] += WV * ry;
-        m2[0] += WV * rx * rx;
-        m2[1] += WV * ry * ry;
-        m2[3] += WV * rx * ry;
+        S.S0 += WV;
+        S.m1[0] += WV * rx;
+        S.m1[1] += WV * ry;
+        S.m2[0] += WV * rx * rx;
+        S.m2[1] += WV * ry * ry;
+        S.m2[3] += WV * rx * ry;
         if (DIM == 3) {
-          m1[2] += WV * rz;
-          m2[2] += WV * rz * rz;
-          m2[4] += WV * rx * rz;
-          m2[5] += WV * ry * rz;
+          S.m1[2] += WV * rz;
+          S.m2[2] += WV * rz * rz;
+          S.m2[4] += WV * rx * rz;
+          S.m2[5] += WV * ry * rz;
         }
-        qmin = fmin(qmin, q);
-        ndum += (j >= nf) ? 1u : 0u;
+        S.qmin = fmin(S.qmin, q);
+        S.ndum += (j >= nf) ? 1u : 0u;
       }
     }
-    nnb += cnt;
+    S.nnb += cnt;
     if (done) break;
   }
 
-  // ------------------------------------------------------------- epilogue
-  const uint32_t flags = P.flags;
-  double lam[3];
-  eig_sym<DIM>(L, lam);
-  const double lmin = lam[0];
-  const bool singular = lmin <= P.lambda_sing;
-  const bool tic = (flags & SPH_F_TIC) && lmin < P.lambda_tic;
-  const bool cons = singular || tic;
-  double I[6] = {0, 0, 0, 0, 0, 0};
-  if (!singular) inv_sym<DIM>(L, I);
-  double G[3];
-  body_force(P, sc->t_rhs, G);
-  // momentum: a = -L^-T S_R + G  or  -S_C + G
-  double grad[3];
-  if (cons) {
-    grad[0] = SC[0];
-    grad[1] = SC[1];
-    grad[2] = SC[2];
-  } else {
-    sym_mul<DIM>(I, SR, grad);
-  }
-  // continuity: -C0^2 tr(L^-1 N) (+ delta-SPH)
-  double div;
-  if (singular || (tic && (flags & SPH_F_CONT_UNCORR))) {
-    div = N[0] + N[1] + (DIM == 3 ? N[2] : 0.0);
-  } else if (DIM == 2) {
-    div = I[0] * N[0] + I[1] * N[1] + I[3] * N[3];
-  } else {
-    div = I[0] * N[0] + I[1] * N[1] + I[2] * N[2] + I[3] * N[3] + I[4] * N[4] + I[5] * N[5];
-  }
-  double dphi = -P.c0 * P.c0 * div;
-  if (flags & SPH_F_DELTA) dphi += P.delta * P.h * P.c0 * (2.0 * Ds);
-  // free-surface normal n = -L^-T g / |.|
-  double ng[3];
-  if (singular) {
-    ng[0] = -gs[0];
-    ng[1] = -gs[1];
-    ng[2] = -gs[2];
-  } else {
-    sym_mul<DIM>(I, gs, ng);
-    ng[0] = -ng[0];
-    ng[1] = -ng[1];
-    ng[2] = -ng[2];
-  }
-  const double nn = sqrt(ng[0] * ng[0] + ng[1] * ng[1] + (DIM == 3 ? ng[2] * ng[2] : 0.0));
-  double nrm[3] = {0.0, 0.0, 0.0};
-  if (nn > 0.0) {
-    nrm[0] = ng[0] / nn;
-    nrm[1] = ng[1] / nn;
-    if (DIM == 3) nrm[2] = ng[2] / nn;
-  }
-  // shifting: dU* = -2 h U_max P, clamped to U_max / 2
-  double dus[3] = {0.0, 0.0, 0.0};
-  const double umax = sc->umax;
-  if (flags & SPH_F_PST) {
-    double ds[3] = {-2.0 * P.h * umax * Ps[0], -2.0 * P.h * umax * Ps[1], -2.0 * P.h * umax * Ps[2]};
-    double dn = sqrt(ds[0] * ds[0] + ds[1] * ds[1] + (DIM == 3 ? ds[2] * ds[2] : 0.0));
-    if (dn > 0.0) {
-      double mag = dn < 0.5 * umax ? dn : 0.5 * umax;
-      dus[0] = mag * ds[0] / dn;
-      dus[1] = mag * ds[1] / dn;
-      if (DIM == 3) dus[2] = mag * ds[2] / dn;
-    }
-  }
-  // free-surface pre-classification by lambda_min
-  uint32_t fl = (cons ? kFlagCons : 0u) | (singular ? kFlagSingular : 0u);
-  bool is_cand = false;
-  if (P.fs_mode != SPH_FS_NONE) {
-    bool fs = false;
-    if (lmin <= P.lambda_lo) fs = true;
-    else if (lmin > P.lambda_hi) fs = false;
-    else if (nn == 0.0) fs = true;
-    else is_cand = true;
-    if (fs) {
-      fl |= kFlagFS;
-      if ((flags & SPH_F_FS_PROJECT) && (flags & SPH_F_PST)) {
-        double d = dus[0] * nrm[0] + dus[1] * nrm[1] + dus[2] * nrm[2];
-        dus[0] -= d * nrm[0];
-        dus[1] -= d * nrm[1];
-        dus[2] -= d * nrm[2];
-      }
-    }
-    if (is_cand) fl |= kFlagCand;
-  }
-  if (active) {
-    for (int a = 0; a < DIM; ++a) {
-      out.acc[a][i] = -grad[a] + G[a];
-      out.dus[a][i] = dus[a];
-      out.nrm[a][i] = nrm[a];
-    }
-    out.dphi[i] = dphi;
-    out.lam[0][i] = lam[0];
-    out.lam[1][i] = lam[1];
-    out.lam[2][i] = lam[2];
-    out.flags[i] = fl;
-    out.nnb[i] = nnb;
-    if (coincident) atomicOr(&sc->err, kErrNonFinite);
-    if (FEAT) {
-      float *f = out.feat + (size_t)i * kNFeat;
-      const double S0s = S0 + P.wself * a1.w;
-      double m1n = 0, m1sq = 0, nm2n = 0, trm2 = 0, gn2 = 0, pn2 = 0, ngr = 0, gg2 = 0;
-      const double M2[3][3] = {{m2[0], m2[3], m2[4]}, {m2[3], m2[1], m2[5]}, {m2[4], m2[5], m2[2]}};
-      for (int a = 0; a < DIM; ++a) {
-        m1n += nrm[a] * m1[a];
-        m1sq += m1[a] * m1[a];
-        trm2 += M2[a][a];
-        gn2 += gs[a] * gs[a];
-        pn2 += Ps[a] * Ps[a];
-        ngr += nrm[a] * G[a];
-        gg2 += G[a] * G[a];
-        for (int b = 0; b < DIM; ++b) nm2n += nrm[a] * M2[a][b] * nrm[b];
-      }
-      double detL = DIM == 2 ? L[0] * L[1] - L[3] * L[3]
-                             : L[0] * (L[1] * L[2] - L[5] * L[5]) - L[3] * (L[3] * L[2] - L[5] * L[4]) +
-                                   L[4] * (L[3] * L[5] - L[1] * L[4]);
-      f[0] = (float)lam[0];
-      f[1] = (float)lam[1];
-      f[2] = (float)(DIM == 3 ? lam[2] : lam[1]);
-      f[3] = (float)detL;
-      f[4] = (float)S0s;
-      f[5] = (float)nnb;
-      f[6] = (float)(sqrt(gn2) * P.h);
-      f[7] = (float)(S0s > 0.0 ? m1n / (S0s * P.h) : 0.0);
-      f[8] = (float)(S0s > 0.0 ? sqrt(m1sq) / (S0s * P.h) : 0.0);
-      f[9] = (float)(S0s > 0.0 ? nm2n / (S0s * P.h * P.h) : 0.0);
-      f[10] = (float)(S0s > 0.0 ? (trm2 - nm2n) / (S0s * P.h * P.h) : 0.0);
-      f[11] = (float)(nn * P.h);
-      f[12] = (float)(gg2 > 0.0 ? ngr / sqrt(gg2) : 0.0);
-      f[13] = (float)(nnb > 0 ? (double)ndum / (double)nnb : 0.0);
-      f[14] = (float)qmin;
-      f[15] = (float)(sqrt(pn2) * P.h);
-    }
-  }
-  // candidate list and statistics (wave-aggregated atomics)
-  const bool cand_l = active && is_cand;
-  uint32_t slot = wave_append(&sc->n_cand, cand_l);
-  if (cand_l) cand[slot] = i;
-  wave_count(&sc->n_fs, active && (fl & kFlagFS));
-  wave_count(&sc->n_cons, active && cons);
-  wave_count(&sc->n_sing, active && singular);
-  // ordered-pair and candidate-test counts
-  unsigned long long pc = active ? nnb : 0, tc = active ? ntest : 0;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    pc += __shfl_xor(pc, o, 64);
-    tc += __shfl_xor(tc, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0 && pc) atomicAdd(&sc->pairs, pc);
-  if ((threadIdx.x & 63) == 0 && tc) atomicAdd(&sc->tests, tc);
+  pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
 }
 
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,

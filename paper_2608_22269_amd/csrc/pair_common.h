@@ -1,0 +1,205 @@
+// Shared pieces of the pair passes (FP64 and mixed paths): the sums one
+// particle accumulates over its neighbours and the epilogue that turns them
+// into the rates of Eq. (sph) -- closed-form eigenvalues of L (Sec. 3), the
+// L^T solves, the TIC / singular branch (Sec. 2.3), the continuity term, the
+// delta-SPH term, the shifting velocity with its clamp, the free-surface
+// pre-classification by lambda_min and the classifier features.
+#pragma once
+
+#include "common.h"
+
+namespace wb {
+
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
+  // wave-aggregated atomic append; returns the slot of this lane (valid if pred)
+  unsigned long long mask = __ballot(pred);
+  uint32_t base = 0;
+  if (mask) {
+    int leader = __ffsll((long long)mask) - 1;
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+  }
+  return base + (uint32_t)__popcll(mask & __lanemask_lt());
+}
+
+__device__ __forceinline__ void wave_count(uint32_t *counter, bool pred) {
+  unsigned long long mask = __ballot(pred);
+  if (mask && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)mask) - 1))
+    atomicAdd(counter, (uint32_t)__popcll(mask));
+}
+
+// Neighbour sums of one particle (FP64).  L, N and m2 are symmetric and
+// packed as (xx, yy, zz, xy, xz, yz); N holds N_ab + N_ba off the diagonal.
+struct PairSums {
+  double L[6], gs[3], SR[3], SC[3], Ps[3], N[6], Ds;
+  double S0, m1[3], m2[6], qmin;
+  uint32_t nnb, ndum, ntest;
+  bool coincident;
+};
+
+__device__ __forceinline__ void sums_zero(PairSums &S) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) S.L[k] = S.N[k] = S.m2[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S.gs[k] = S.SR[k] = S.SC[k] = S.Ps[k] = S.m1[k] = 0.0;
+  S.Ds = S.S0 = 0.0;
+  S.qmin = 2.0;
+  S.nnb = S.ndum = S.ntest = 0;
+  S.coincident = false;
+}
+
+// Must be reached by every lane of the wave (wave-level atomics at the end).
+template <int DIM, bool FEAT>
+__device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const Rates &out, uint32_t *cand,
+                                              uint32_t i, bool active, double Vi, const PairSums &S) {
+  const uint32_t flags = P.flags;
+  double lam[3];
+  eig_sym<DIM>(S.L, lam);
+  const double lmin = lam[0];
+  const bool singular = lmin <= P.lambda_sing;
+  const bool tic = (flags & SPH_F_TIC) && lmin < P.lambda_tic;
+  const bool cons = singular || tic;
+  double I[6] = {0, 0, 0, 0, 0, 0};
+  if (!singular) inv_sym<DIM>(S.L, I);
+  double G[3];
+  body_force(P, sc->t_rhs, G);
+  // momentum: a = -S.L^-T S_R + G  or  -S_C + G
+  double grad[3];
+  if (cons) {
+    grad[0] = S.SC[0];
+    grad[1] = S.SC[1];
+    grad[2] = S.SC[2];
+  } else {
+    sym_mul<DIM>(I, S.SR, grad);
+  }
+  // continuity: -C0^2 tr(S.L^-1 S.N) (+ delta-SPH)
+  double div;
+  if (singular || (tic && (flags & SPH_F_CONT_UNCORR))) {
+    div = S.N[0] + S.N[1] + (DIM == 3 ? S.N[2] : 0.0);
+  } else if (DIM == 2) {
+    div = I[0] * S.N[0] + I[1] * S.N[1] + I[3] * S.N[3];
+  } else {
+    div = I[0] * S.N[0] + I[1] * S.N[1] + I[2] * S.N[2] + I[3] * S.N[3] + I[4] * S.N[4] + I[5] * S.N[5];
+  }
+  double dphi = -P.c0 * P.c0 * div;
+  if (flags & SPH_F_DELTA) dphi += P.delta * P.h * P.c0 * (2.0 * S.Ds);
+  // free-surface normal n = -S.L^-T g / |.|
+  double ng[3];
+  if (singular) {
+    ng[0] = -S.gs[0];
+    ng[1] = -S.gs[1];
+    ng[2] = -S.gs[2];
+  } else {
+    sym_mul<DIM>(I, S.gs, ng);
+    ng[0] = -ng[0];
+    ng[1] = -ng[1];
+    ng[2] = -ng[2];
+  }
+  const double nn = sqrt(ng[0] * ng[0] + ng[1] * ng[1] + (DIM == 3 ? ng[2] * ng[2] : 0.0));
+  double nrm[3] = {0.0, 0.0, 0.0};
+  if (nn > 0.0) {
+    nrm[0] = ng[0] / nn;
+    nrm[1] = ng[1] / nn;
+    if (DIM == 3) nrm[2] = ng[2] / nn;
+  }
+  // shifting: dU* = -2 h U_max P, clamped to U_max / 2
+  double dus[3] = {0.0, 0.0, 0.0};
+  const double umax = sc->umax;
+  if (flags & SPH_F_PST) {
+    double ds[3] = {-2.0 * P.h * umax * S.Ps[0], -2.0 * P.h * umax * S.Ps[1], -2.0 * P.h * umax * S.Ps[2]};
+    double dn = sqrt(ds[0] * ds[0] + ds[1] * ds[1] + (DIM == 3 ? ds[2] * ds[2] : 0.0));
+    if (dn > 0.0) {
+      double mag = dn < 0.5 * umax ? dn : 0.5 * umax;
+      dus[0] = mag * ds[0] / dn;
+      dus[1] = mag * ds[1] / dn;
+      if (DIM == 3) dus[2] = mag * ds[2] / dn;
+    }
+  }
+  // free-surface pre-classification by lambda_min
+  uint32_t fl = (cons ? kFlagCons : 0u) | (singular ? kFlagSingular : 0u);
+  bool is_cand = false;
+  if (P.fs_mode != SPH_FS_NONE) {
+    bool fs = false;
+    if (lmin <= P.lambda_lo) fs = true;
+    else if (lmin > P.lambda_hi) fs = false;
+    else if (nn == 0.0) fs = true;
+    else is_cand = true;
+    if (fs) {
+      fl |= kFlagFS;
+      if ((flags & SPH_F_FS_PROJECT) && (flags & SPH_F_PST)) {
+        double d = dus[0] * nrm[0] + dus[1] * nrm[1] + dus[2] * nrm[2];
+        dus[0] -= d * nrm[0];
+        dus[1] -= d * nrm[1];
+        dus[2] -= d * nrm[2];
+      }
+    }
+    if (is_cand) fl |= kFlagCand;
+  }
+  if (active) {
+    for (int a = 0; a < DIM; ++a) {
+      out.acc[a][i] = -grad[a] + G[a];
+      out.dus[a][i] = dus[a];
+      out.nrm[a][i] = nrm[a];
+    }
+    out.dphi[i] = dphi;
+    out.lam[0][i] = lam[0];
+    out.lam[1][i] = lam[1];
+    out.lam[2][i] = lam[2];
+    out.flags[i] = fl;
+    out.nnb[i] = S.nnb;
+    if (S.coincident) atomicOr(&sc->err, kErrNonFinite);
+    if (FEAT) {
+      float *f = out.feat + (size_t)i * kNFeat;
+      const double S0s = S.S0 + P.wself * Vi;
+      double m1n = 0, m1sq = 0, nm2n = 0, trm2 = 0, gn2 = 0, pn2 = 0, ngr = 0, gg2 = 0;
+      const double M2[3][3] = {{S.m2[0], S.m2[3], S.m2[4]}, {S.m2[3], S.m2[1], S.m2[5]}, {S.m2[4], S.m2[5], S.m2[2]}};
+      for (int a = 0; a < DIM; ++a) {
+        m1n += nrm[a] * S.m1[a];
+        m1sq += S.m1[a] * S.m1[a];
+        trm2 += M2[a][a];
+        gn2 += S.gs[a] * S.gs[a];
+        pn2 += S.Ps[a] * S.Ps[a];
+        ngr += nrm[a] * G[a];
+        gg2 += G[a] * G[a];
+        for (int b = 0; b < DIM; ++b) nm2n += nrm[a] * M2[a][b] * nrm[b];
+      }
+      double detL = DIM == 2 ? S.L[0] * S.L[1] - S.L[3] * S.L[3]
+                             : S.L[0] * (S.L[1] * S.L[2] - S.L[5] * S.L[5]) - S.L[3] * (S.L[3] * S.L[2] - S.L[5] * S.L[4]) +
+                                   S.L[4] * (S.L[3] * S.L[5] - S.L[1] * S.L[4]);
+      f[0] = (float)lam[0];
+      f[1] = (float)lam[1];
+      f[2] = (float)(DIM == 3 ? lam[2] : lam[1]);
+      f[3] = (float)detL;
+      f[4] = (float)S0s;
+      f[5] = (float)S.nnb;
+      f[6] = (float)(sqrt(gn2) * P.h);
+      f[7] = (float)(S0s > 0.0 ? m1n / (S0s * P.h) : 0.0);
+      f[8] = (float)(S0s > 0.0 ? sqrt(m1sq) / (S0s * P.h) : 0.0);
+      f[9] = (float)(S0s > 0.0 ? nm2n / (S0s * P.h * P.h) : 0.0);
+      f[10] = (float)(S0s > 0.0 ? (trm2 - nm2n) / (S0s * P.h * P.h) : 0.0);
+      f[11] = (float)(nn * P.h);
+      f[12] = (float)(gg2 > 0.0 ? ngr / sqrt(gg2) : 0.0);
+      f[13] = (float)(S.nnb > 0 ? (double)S.ndum / (double)S.nnb : 0.0);
+      f[14] = (float)S.qmin;
+      f[15] = (float)(sqrt(pn2) * P.h);
+    }
+  }
+  // candidate list and statistics (wave-aggregated atomics)
+  const bool cand_l = active && is_cand;
+  uint32_t slot = wave_append(&sc->n_cand, cand_l);
+  if (cand_l) cand[slot] = i;
+  wave_count(&sc->n_fs, active && (fl & kFlagFS));
+  wave_count(&sc->n_cons, active && cons);
+  wave_count(&sc->n_sing, active && singular);
+  // ordered-pair and candidate-test counts
+  unsigned long long pc = active ? S.nnb : 0, tc = active ? S.ntest : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    pc += __shfl_xor(pc, o, 64);
+    tc += __shfl_xor(tc, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && pc) atomicAdd(&sc->pairs, pc);
+  if ((threadIdx.x & 63) == 0 && tc) atomicAdd(&sc->tests, tc);
+}
+
+}  // namespace wb

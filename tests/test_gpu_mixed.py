@@ -1,0 +1,147 @@
+"""Mixed-precision path (int cell + FP32 offset positions, FP32 pair
+evaluation, FP64 accumulation of L and the potential-gradient sums) against
+the FP64 CPU oracle evaluated at the mixed path's own positions.
+
+Bars (derived from FP32 evaluation, unit round-off 6e-8, of terms summed over
+~80 neighbours and then multiplied by L^-1, whose norm is below ~2.1 at the
+surface): accelerations and Dphi/Dt within 2e-5 of their field scale; the
+neighbour count exact except for pairs the FP32 test puts on the other side
+of 2h (at most 1e-4 of the particles); lambda within 1e-5.  A linear
+potential consistent with the stored positions is reproduced to FP64
+round-off (1e-12): the property the FP64 accumulation exists for.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2608_22269_amd import Simulation
+    return Simulation
+
+
+def _flags_all(**kw):
+    return dict(delta_sph=True, pst=True, tic=True, fs_project=True, cont_uncorr=True, fs_mode="exact", **kw)
+
+
+def _mixed(case):
+    return wl.with_params(case, precision="mixed")
+
+
+def _own_state_case(sim, case):
+    """The oracle's input: the mixed path's positions, velocities, potential
+    and masses as it stores them."""
+    c = dict(case)
+    c["x"] = sim.field("x")
+    c["u"] = sim.field("u")
+    c["phi"] = sim.field("phi")
+    c["mass"] = sim.field("mass")
+    d = case["kind"] == 1
+    c["u"][d] = case["u"][d]
+    c["phi"][d] = case["phi"][d]
+    return c
+
+
+CASES = [
+    ("tank2d-dyn", wl.random_potential(wl.random_velocity(wl.jitter(wl.tank2d(dx=0.01, **_flags_all()), 0.1, 3),
+                                                          0.05, 4), 0.05, 5)),
+    ("box3d-dyn", wl.random_velocity(wl.jitter(wl.box3d(0.02, (0.4, 0.3, 0.4), (0.4, 0.3, 0.2), **_flags_all()),
+                                               0.1, 6), 0.05, 7)),
+    ("tank2d-hydro", wl.tank2d(dx=0.01)),
+]
+
+
+@pytest.mark.parametrize("name,case", CASES, ids=[c[0] for c in CASES])
+def test_mixed_rates_vs_oracle(Sim, name, case):
+    sim = Sim(_mixed(case))
+    sim.eval_rates()
+    ref = oracle.eval_rates(_own_state_case(sim, case))
+    f = case["kind"] == 0
+    gmag = 9.81
+    acc = sim.field("dudt")
+    s_acc = max(gmag, np.abs(ref["acc"][f]).max())
+    err_acc = np.abs(acc[f] - ref["acc"][f]).max() / s_acc
+    dphi = sim.field("dphidt")
+    s_dphi = max(np.abs(ref["dphi"][f]).max(), case["params"]["c0"] * gmag * case["params"]["h"])
+    err_dphi = np.abs(dphi[f] - ref["dphi"][f]).max() / s_dphi
+    nnb = sim.field("nnb")
+    bad_nnb = int((nnb[f] != ref["nnb"][f]).sum())
+    lam = sim.field("lambda")
+    err_lam = np.abs(lam[f] - ref["lam"][f]).max()
+    print(f"{name}: acc {err_acc:.2e} dphi {err_dphi:.2e} lambda {err_lam:.2e} nnb mismatches {bad_nnb}")
+    assert err_acc <= 2e-5
+    assert err_dphi <= 2e-5
+    assert err_lam <= 1e-5
+    assert bad_nnb <= max(1, 1e-4 * f.sum())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mixed_linear_potential_is_exact(Sim, dim):
+    """Corrected gradient of phi = c.x + b on a jittered block with truncated
+    supports, phi consistent with the stored positions: a = -c to 1e-12."""
+    from tests.test_oracle_pins import _fluid_block
+    case = _fluid_block(dim, 24 if dim == 2 else 10, 0.01, seed=31)
+    case["mass"] = np.full(len(case["x"]), 1000.0 * 0.01 ** dim)
+    case = _mixed(case)
+    sim0 = Sim(case)
+    x_m = sim0.field("x")
+    sim0.close()
+    rng = np.random.default_rng(32)
+    c = rng.normal(size=dim) * 3.0
+    case2 = dict(case)
+    case2["x"] = x_m
+    case2["phi"] = x_m @ c + 0.7
+    sim = Sim(case2)
+    assert np.array_equal(sim.field("x"), x_m)  # the stored positions round-trip exactly
+    sim.eval_rates()
+    acc = sim.field("dudt")
+    err = np.abs(acc + c).max() / np.abs(c).max()
+    print(f"dim {dim}: linear reproduction error {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_mixed_hydrostatic_tank(Sim):
+    """2D tank, mixed path: the state the mixed path stores is a discrete
+    equilibrium up to the FP32 rounding of the initial offsets; spurious
+    velocity stays far below 1e-6 over the first 50 steps, and the FP64 path
+    is reported beside it."""
+    case = wl.tank2d()
+    f = case["kind"] == 0
+    sm = Sim(_mixed(case))
+    sm.eval_rates()
+    a0 = np.abs(sm.field("dudt")[f]).max()
+    sm.step(50)
+    um = np.abs(sm.field("u")[f]).max()
+    sd = Sim(case)
+    sd.step(50)
+    ud = np.abs(sd.field("u")[f]).max()
+    print(f"mixed: |a|(t=0) {a0:.2e}, max|U| after 50 steps {um:.2e}; fp64 {ud:.2e}")
+    assert a0 <= 1e-5 * 9.81
+    assert um <= 1e-6
+    assert ud <= 1e-12
+
+
+def test_mixed_trajectory_tracks_fp64(Sim):
+    """Ten steps of the dynamic 2D tank: mixed and FP64 GPU paths agree to the
+    FP32 resolution of the state."""
+    case = CASES[0][1]
+    f = case["kind"] == 0
+    sm = Sim(_mixed(case))
+    sd = Sim(case)
+    sm.step(10)
+    sd.step(10)
+    dx = np.abs(sm.field("x")[f] - sd.field("x")[f]).max()
+    du = np.abs(sm.field("u")[f] - sd.field("u")[f]).max() / np.abs(sd.field("u")[f]).max()
+    dp = np.abs(sm.field("phi")[f] - sd.field("phi")[f]).max() / np.abs(sd.field("phi")[f]).max()
+    print(f"10 steps: |dx| {dx:.2e} m, rel |dU| {du:.2e}, rel |dphi| {dp:.2e}")
+    assert dx <= 1e-7
+    assert du <= 1e-4
+    assert dp <= 1e-4
+    assert abs(sm.stats()["t"] - sd.stats()["t"]) <= 1e-12
