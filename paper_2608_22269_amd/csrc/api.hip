@@ -61,6 +61,7 @@ struct sph_ctx {
   Dummies dm;
   Rates r;
   uint32_t *cand, *fallback;
+  float *cand_logit;
   Scalars *sc;
   unsigned char *stage;
   size_t stage_bytes;
@@ -264,6 +265,7 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   c->r.logit = cv.take<float>(nf);
   c->cand = cv.take<uint32_t>(nf);
   c->fallback = cv.take<uint32_t>(nf);
+  c->cand_logit = c->p.fs_mode == SPH_FS_LEARNED ? cv.take<float>(nf) : nullptr;
   c->clf.w = cv.take<float>(kMlpParams);
   c->clf.mean = cv.take<float>(kNFeat);
   c->clf.std = cv.take<float>(kNFeat);
@@ -360,7 +362,8 @@ sph_status rhs(sph_ctx *c, int stage) {
     const uint32_t *list = c->cand;
     const uint32_t *count = &c->sc->n_cand;
     if (c->p.fs_mode == SPH_FS_LEARNED && c->has_clf) {
-      e = launch_classify(c->clf, c->r, c->cand, &c->sc->n_cand, c->fallback, c->sc, c->P, (uint32_t)c->nf, c->s);
+      e = launch_classify(c->clf, c->r, c->cand, &c->sc->n_cand, c->fallback, c->sc, c->P, (uint32_t)c->nf,
+                          c->cand_logit, c->s);
       list = c->fallback;
       count = &c->sc->n_scan;
     }
@@ -736,6 +739,28 @@ sph_status sph_stats(sph_ctx *c, double out[16]) {
   out[12] = h.n_cand;
   out[13] = (double)h.tests;
   return c->status != SPH_OK ? c->status : SPH_OK;
+}
+
+sph_status sph_set_classifier(sph_ctx *c, const float *params, int64_t nparams, const float *mean, const float *std,
+                              float margin) {
+  sph_status st = usable(c);
+  if (st != SPH_OK) return st;
+  if (!params || !mean || !std || nparams != kMlpParams || !(margin >= 0.0f))
+    return fail(c, SPH_EINVAL, "classifier: bad parameters");
+  if (c->p.fs_mode != SPH_FS_LEARNED) return fail(c, SPH_ESTATE, "classifier needs fs_mode SPH_FS_LEARNED");
+  for (int k = 0; k < kNFeat; ++k)
+    if (!(std[k] > 0.0f) || !std::isfinite(mean[k])) return fail(c, SPH_EINVAL, "classifier: bad mean/std");
+  for (int64_t k = 0; k < nparams; ++k)
+    if (!std::isfinite(params[k])) return fail(c, SPH_EINVAL, "classifier: non-finite weight");
+  hipError_t e = hipMemcpyAsync(c->clf.w, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->clf.mean, mean, sizeof(float) * kNFeat, hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->clf.std, std, sizeof(float) * kNFeat, hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  st = hip_check(c, e, "classifier upload");
+  if (st != SPH_OK) return st;
+  c->clf.margin = margin;
+  c->has_clf = true;
+  return SPH_OK;
 }
 
 sph_status sph_profile(sph_ctx *c, int32_t enable) {

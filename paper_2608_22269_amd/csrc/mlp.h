@@ -20,7 +20,7 @@ struct Classifier {
 // rows; confident ones get their free-surface flag (and the shifting
 // projection), the rest are appended to fallback (count in sc->n_scan).
 hipError_t launch_classify(const Classifier &c, const Rates &r, const uint32_t *cand, const uint32_t *n_cand,
-                           uint32_t *fallback, Scalars *sc, const Phys &P, uint32_t nf, hipStream_t s);
+                           uint32_t *fallback, Scalars *sc, const Phys &P, uint32_t nf, float *lgbuf, hipStream_t s);
 
 // Stateless BF16 MFMA inference over n feature rows.
 hipError_t launch_mlp_infer(const float *w, const float *mean, const float *std, const float *X,

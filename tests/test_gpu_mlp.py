@@ -1,0 +1,109 @@
+"""Learned free-surface classifier on the GPU against the NumPy FP64 oracle.
+
+Bars: FP32 forward within 1e-5 (relative to max |logit|) of the oracle; FP32
+gradient within 1e-4 of the largest gradient entry; one Adam step equal to
+the oracle's update of the same gradient to 1e-6; BF16 MFMA inference within
+the BF16 budget (8-bit mantissa through two 64-term layers: 3e-2 of the logit
+scale).  The learned mode with an infinite margin sends every candidate to the
+exact test and must reproduce the exact flags bit for bit.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp as omlp
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def learn():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2608_22269_amd import learn
+    return learn
+
+
+def _data(seed, B=512):
+    rng = np.random.default_rng(seed)
+    X = (rng.normal(size=(B, 16)) * 2.0 + 0.5).astype(np.float32)
+    y = (rng.uniform(size=B) < 0.4).astype(np.float32)
+    w = rng.uniform(0.5, 2.0, size=B).astype(np.float32)
+    mean = (rng.normal(size=16) * 0.3).astype(np.float32)
+    std = rng.uniform(0.5, 2.0, size=16).astype(np.float32)
+    th = (omlp.init_params(7) + rng.normal(size=omlp.NPARAM) * 0.05).astype(np.float32)
+    return X, y, w, mean, std, th
+
+
+def test_forward_fp32(learn):
+    X, y, w, mean, std, th = _data(1)
+    tr = learn.MLPTrainer(th, mean, std, max_batch=1024)
+    got = tr.forward(X)
+    ref = omlp.forward(th.astype(np.float64), X, mean, std)
+    assert np.abs(got - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+def test_gradient_fp32(learn):
+    X, y, w, mean, std, th = _data(2)
+    tr = learn.MLPTrainer(th, mean, std, max_batch=1024)
+    loss, g = tr.loss_grad(X, y, w)
+    rl, rg = omlp.loss_and_grad(th.astype(np.float64), X, y, w, mean, std)
+    assert abs(loss - rl) <= 1e-5 * abs(rl)
+    assert np.abs(g - rg).max() <= 1e-4 * np.abs(rg).max()
+
+
+def test_adam_step(learn):
+    X, y, w, mean, std, th = _data(3)
+    tr = learn.MLPTrainer(th, mean, std, max_batch=1024)
+    _, g = tr.loss_grad(X, y, w)
+    tr.adam(lr=1e-3)
+    got = tr.params()
+    ref, _, _ = omlp.adam_step(th.astype(np.float64), np.zeros(omlp.NPARAM), np.zeros(omlp.NPARAM),
+                               g.astype(np.float64), 1, lr=1e-3)
+    assert np.abs(got - ref).max() <= 1e-6
+
+
+def test_training_reduces_loss(learn):
+    import torch
+    rng = np.random.default_rng(4)
+    n = 20000
+    X = rng.normal(size=(n, 16)).astype(np.float32)
+    y = ((X[:, 0] + 0.5 * X[:, 1] - 0.3 * X[:, 2]) > 0).astype(np.float32)
+    th = omlp.init_params(5).astype(np.float32)
+    tr = learn.MLPTrainer(th, np.zeros(16), np.ones(16), max_batch=1024)
+    Xd, yd = torch.as_tensor(X, device="cuda"), torch.as_tensor(y, device="cuda")
+    losses = []
+    for ep in range(5):
+        perm = torch.as_tensor(rng.permutation(n).astype(np.int32), device="cuda")
+        losses.append(tr.train_epoch(Xd, yd, None, perm, 512, 3e-3))
+    assert losses[-1] < 0.5 * losses[0]
+    pred = omlp.forward(tr.params().astype(np.float64), X, np.zeros(16), np.ones(16)) > 0
+    assert (pred == (y > 0.5)).mean() > 0.97
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 1000, 4099])
+def test_bf16_mfma_inference(learn, n):
+    X, y, w, mean, std, th = _data(6, B=max(n, 16))
+    X = X[:n]
+    got = learn.infer_bf16(th, mean, std, X).cpu().numpy()
+    ref = omlp.forward(th.astype(np.float64), X, mean, std)
+    scale = max(1.0, np.abs(ref).max())
+    assert got.shape == (n,)
+    assert np.abs(got - ref).max() <= 3e-2 * scale
+
+
+def test_learned_mode_infinite_margin_equals_exact(learn):
+    """Every candidate falls back to the exact test: flags identical."""
+    from paper_2608_22269_amd import Simulation
+    base = wl.random_velocity(wl.jitter(wl.box3d(0.02, (0.4, 0.3, 0.4), (0.4, 0.3, 0.2), delta_sph=True, pst=True,
+                                                 tic=True, fs_project=True, cont_uncorr=True), 0.1, 6), 0.05, 7)
+    ex = Simulation(wl.with_params(base, fs_mode="exact"))
+    ex.eval_rates()
+    le = Simulation(wl.with_params(base, fs_mode="learned"))
+    th = omlp.init_params(3).astype(np.float32)
+    le.set_classifier(th, np.zeros(16), np.ones(16), np.inf)
+    le.eval_rates()
+    assert np.array_equal(ex.field("fs"), le.field("fs"))
+    assert np.array_equal(ex.field("delta_u"), le.field("delta_u"))
+    st = le.stats()
+    assert st["n_mlp"] == 0 and st["n_scan"] == st["n_cand"] > 0
