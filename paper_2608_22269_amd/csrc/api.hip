@@ -130,7 +130,7 @@ bool params_ok(const sph_params *p, std::string *why) {
     if (N > (a == 2 ? 1023 : 2047)) return bad("too many cells along an axis (max 2047, 2047, 1023)");
   }
   double ncell = 1;
-  for (int a = 0; a < p->dim; ++a) ncell *= std::floor((p->domain_hi[a] - p->domain_lo[a]) / R) + 1;
+  for (int a = 0; a < p->dim; ++a) ncell *= std::floor((p->domain_hi[a] - p->domain_lo[a]) / R) + 1 + 16;
   if (ncell > 2.0e9) return bad("too many cells");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->gravity[a]) || !std::isfinite(p->forcing_amp[a])) return bad("non-finite body force");
@@ -190,6 +190,36 @@ void derive(const sph_params *p, Phys &P, Grid &g) {
     g.N[a] = a < p->dim ? (int32_t)std::floor((p->domain_hi[a] - p->domain_lo[a]) / g.R) + 1 : 1;
     g.ncell *= g.N[a];
   }
+  g.B[0] = kBrickX;
+  g.B[1] = p->dim == 3 ? kBrickY : 16;
+  g.B[2] = p->dim == 3 ? kBrickZ : 1;
+  int64_t nb = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.NB[a] = (g.N[a] + g.B[a] - 1) / g.B[a];
+    nb *= g.NB[a];
+  }
+  g.nkey = nb * (int64_t)g.B[0] * g.B[1] * g.B[2];
+  g.brank = nullptr;
+}
+
+// Morton rank of every brick (bricks sorted by their interleaved coordinates).
+std::vector<uint32_t> brick_ranks(const Grid &g) {
+  auto spread = [](uint64_t v) {
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+    return r;
+  };
+  const int64_t nb = (int64_t)g.NB[0] * g.NB[1] * g.NB[2];
+  std::vector<std::pair<uint64_t, uint32_t>> code((size_t)nb);
+  for (int64_t bz = 0, k = 0; bz < g.NB[2]; ++bz)
+    for (int64_t by = 0; by < g.NB[1]; ++by)
+      for (int64_t bx = 0; bx < g.NB[0]; ++bx, ++k)
+        code[(size_t)k] = {spread((uint64_t)bx) | (spread((uint64_t)by) << 1) | (spread((uint64_t)bz) << 2),
+                           (uint32_t)k};
+  std::sort(code.begin(), code.end());
+  std::vector<uint32_t> rank((size_t)nb);
+  for (size_t r = 0; r < code.size(); ++r) rank[code[r].second] = (uint32_t)r;
+  return rank;
 }
 
 // Carves every device array of a context.  Returns the bytes used.
@@ -236,13 +266,14 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   }
   c->rec0 = mixed ? nullptr : cv.take<double4>(nf + nd);
   c->rec1 = mixed ? nullptr : cv.take<double4>(nf + nd);
-  c->cs_f = cv.take<uint32_t>(c->g.ncell + 1);
-  c->cs_d = cv.take<uint32_t>(c->g.ncell + 1);
+  c->cs_f = cv.take<uint32_t>(c->g.nkey + 1);
+  c->cs_d = cv.take<uint32_t>(c->g.nkey + 1);
+  c->g.brank = cv.take<uint32_t>((int64_t)c->g.NB[0] * c->g.NB[1] * c->g.NB[2]);
   c->perm = cv.take<uint32_t>(nmax);
   c->ss.key = cv.take<uint32_t>(nmax);
   c->ss.slot = cv.take<uint32_t>(nmax);
-  c->ss.count = cv.take<uint32_t>(c->g.ncell + 1);
-  c->ss.scan_tmp = cv.take<uint32_t>((int64_t)scan_tmp_words(std::max<int64_t>(c->g.ncell, n + 1)) + 1);
+  c->ss.count = cv.take<uint32_t>(c->g.nkey + 1);
+  c->ss.scan_tmp = cv.take<uint32_t>((int64_t)scan_tmp_words(std::max<int64_t>(c->g.nkey, n + 1)) + 1);
   for (int a = 0; a < 3; ++a) {
     c->dm.x[a] = a < dim ? f64(nd) : nullptr;
     c->dm.n[a] = a < dim ? f64(nd) : nullptr;
@@ -613,17 +644,21 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   if (e == hipSuccess) e = launch_exclusive_scan(frank, frank, n, c->ss.scan_tmp, s);
   if (e == hipSuccess) e = launch_exclusive_scan(drank, drank, n, c->ss.scan_tmp, s);
   if (e == hipSuccess) e = launch_split(c->P, n, dx_, du_, dphi_, dm_, dk_, dn_, frank, drank, f0, dst, s);
-  // scalars
+  // scalars and the brick order of the sort keys
   Scalars h;
   std::memset(&h, 0, sizeof(h));
   if (e == hipSuccess) e = hipMemcpyAsync(c->sc, &h, sizeof(Scalars), hipMemcpyHostToDevice, s);
+  const std::vector<uint32_t> ranks = brick_ranks(c->g);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void *)c->g.brank, ranks.data(), sizeof(uint32_t) * ranks.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   // dummies: sort once by (cell, original index)
   if (e == hipSuccess && nd > 0) {
     e = launch_sort_keys(c->g, dim, dst.x[0], dst.x[1], dst.x[2], nullptr, nd, dst.id, c->ss, c->cs_d, c->perm, c->sc,
                          s);
     if (e == hipSuccess) e = launch_gather_dummies(c->perm, nd, dst, c->dm, dim, s);
   } else if (e == hipSuccess) {
-    e = launch_fill_u32(c->cs_d, 0u, c->g.ncell + 1, s);
+    e = launch_fill_u32(c->cs_d, 0u, c->g.nkey + 1, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {

@@ -35,6 +35,17 @@ enum : uint32_t {
 };
 
 // Background grid (Sec. 3): N_a = floor((hi - lo) / R) + 1 cells per axis.
+//
+// Storage order of the cells.  The paper orders particles by HashID = i_x +
+// i_y N_x + i_z N_x N_y; then a particle's z-neighbours sit a whole cell layer
+// (~10 MB of records at the 17.5M tank) away and no L2 holds a wave's
+// neighbourhood.  The sort key used here keeps x-runs contiguous inside
+// bricks of B_x x B_y x B_z cells and ranks the bricks along a Morton curve:
+//   key = rank(brick) * B_x B_y B_z + (lx + ly B_x + lz B_x B_y).
+// Cell coordinates, HashID and neighbour sets are unchanged; only the order
+// particles are stored and visited in differs.
+constexpr int kBrickX = 16, kBrickY = 4, kBrickZ = 4;
+
 struct Grid {
   double lo[3];
   double hi[3];
@@ -43,7 +54,19 @@ struct Grid {
   int32_t N[3];
   int32_t reach; // cells searched on each side, ceil(2h / R)
   int64_t ncell;
+  int32_t B[3];      // brick size in cells (z = 1 in 2D)
+  int32_t NB[3];     // bricks per axis
+  int64_t nkey;      // number of sort keys = bricks * brick volume (>= ncell)
+  const uint32_t *brank;  // Morton rank of every brick (NB0 NB1 NB2 entries)
 };
+
+// Sort key of cell (x, y, z).
+__device__ __forceinline__ uint32_t cell_key(const Grid &g, int x, int y, int z) {
+  const int bx = x / kBrickX, by = y / g.B[1], bz = z / g.B[2];
+  const int lx = x - bx * kBrickX, ly = y - by * g.B[1], lz = z - bz * g.B[2];
+  const uint32_t r = g.brank[bx + (int64_t)by * g.NB[0] + (int64_t)bz * g.NB[0] * g.NB[1]];
+  return r * (uint32_t)(kBrickX * g.B[1] * g.B[2]) + (uint32_t)(lx + ly * kBrickX + lz * kBrickX * g.B[1]);
+}
 
 // Physical / numerical constants as the kernels need them.
 struct Phys {
@@ -220,18 +243,21 @@ __device__ __forceinline__ void sym_mul(const double I[6], const double v[3], do
 // ------------------------------------------------------- cell-row walker
 //
 // Algorithm 1 visits the 3^d cells around the particle's cell.  Cells along x
-// are consecutive in HashID order, so each (y, z) offset is one contiguous
-// run of particles: one "row".  With cells smaller than 2h the walker visits
-// (2 reach + 1)^(d-1) rows; a row whose (y, z) slab is farther than 2h from
-// the particle is skipped and the x span is cut to the particle's reach.  The
-// cuts are conservative (slightly widened), the exact test is done per pair.
+// are consecutive in storage inside a brick, so each (y, z) offset is one
+// contiguous run of particles, or two where the x span crosses a brick
+// boundary.  With cells smaller than 2h the walker visits (2 reach + 1)^(d-1)
+// rows; a row whose (y, z) slab is farther than 2h from the particle is
+// skipped and the x span is cut to the particle's reach.  The cuts are
+// conservative (slightly widened); the exact test is done per pair.  Each row
+// yields up to four runs: fluid and dummy records of each x sub-span.
 struct RowWalker {
   int32_t row;       // next row index in [0, nrows)
   int32_t nrows;
-  int32_t seg;       // 0: fluid part of the current row, 1: dummy part
+  int32_t sub;       // next run of the current row, 0..3 (4 = row done)
   uint32_t cur, end; // current run [cur, end) in record index space
   int32_t cx, cy, cz;
-  uint32_t dlo, dhi; // dummy run of the current row (absolute record index)
+  int32_t iy, iz;            // current row
+  int32_t xs0, xe0, xs1, xe1;  // x sub-spans of the row (xs1 > xe1: none)
 };
 
 template <int DIM>
@@ -242,34 +268,47 @@ __device__ __forceinline__ void walker_init(RowWalker &w, const Grid &g, double 
   int side = 2 * g.reach + 1;
   w.nrows = DIM == 3 ? side * side : side;
   w.row = 0;
-  w.seg = 1;
+  w.sub = 4;
   w.cur = w.end = 0;
-  w.dlo = w.dhi = 0;
+  w.iy = w.iz = 0;
+  w.xs0 = w.xs1 = 1;
+  w.xe0 = w.xe1 = 0;
 }
 
 // Advances to the next non-empty run; returns false when the walk is over.
-// cs_f / cs_d: cell start arrays (ncell + 1) of the fluid and dummy records;
-// dummy records live at index nf + k.
+// cs_f / cs_d: start index (per sort key, nkey + 1 entries) of the fluid and
+// dummy records; dummy records live at index nf + k.
 template <int DIM>
 __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const uint32_t *__restrict__ cs_f,
                                             const uint32_t *__restrict__ cs_d, uint32_t nf, double x, double y,
                                             double z, double two_h) {
   for (;;) {
-    if (w.seg == 0) {  // fluid part done: emit the dummy part of the same row
-      w.seg = 1;
-      if (w.dlo < w.dhi) {
-        w.cur = w.dlo;
-        w.end = w.dhi;
+    if (w.sub < 4) {
+      const int s = w.sub++;
+      const bool second = s >= 2, dummy = (s & 1) != 0;
+      const int xs = second ? w.xs1 : w.xs0, xe = second ? w.xe1 : w.xe0;
+      if (xs > xe) continue;
+      const uint32_t k0 = cell_key(g, xs, w.iy, w.iz);
+      const uint32_t k1 = k0 + (uint32_t)(xe - xs);  // same brick: consecutive keys
+      const uint32_t *cs = dummy ? cs_d : cs_f;
+      uint32_t lo = cs[k0], hi = cs[k1 + 1];
+      if (dummy) {
+        lo += nf;
+        hi += nf;
+      }
+      if (lo < hi) {
+        w.cur = lo;
+        w.end = hi;
         return true;
       }
       continue;
     }
     if (w.row >= w.nrows) return false;
-    int side = 2 * g.reach + 1;
-    int r = w.row++;
-    int dy = (DIM == 3 ? r % side : r) - g.reach;
-    int dz = DIM == 3 ? r / side - g.reach : 0;
-    int iy = w.cy + dy, iz = w.cz + dz;
+    const int side = 2 * g.reach + 1;
+    const int r = w.row++;
+    const int dy = (DIM == 3 ? r % side : r) - g.reach;
+    const int dz = DIM == 3 ? r / side - g.reach : 0;
+    const int iy = w.cy + dy, iz = w.cz + dz;
     if (iy < 0 || iy >= g.N[1]) continue;
     if (DIM == 3 && (iz < 0 || iz >= g.N[2])) continue;
     // distance from the particle to the row's (y, z) slab, slightly reduced
@@ -282,25 +321,40 @@ __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const u
     }
     ey = fmax(0.0, ey - 1e-12 * g.R);
     ez = fmax(0.0, ez - 1e-12 * g.R);
-    double rem = two_h * two_h - ey * ey - ez * ez;
+    const double rem = two_h * two_h - ey * ey - ez * ez;
     if (rem < 0.0) continue;
-    double reach = sqrt(rem) * (1.0 + 1e-12) + 1e-12 * g.R;
+    const double reach = sqrt(rem) * (1.0 + 1e-12) + 1e-12 * g.R;
     int x0 = cell_coord(x - reach, g.lo[0], g.R);
     int x1 = cell_coord(x + reach, g.lo[0], g.R);
     x0 = max(x0, max(w.cx - g.reach, 0));
     x1 = min(x1, min(w.cx + g.reach, g.N[0] - 1));
     if (x0 > x1) continue;
-    int64_t base = (int64_t)iy * g.N[0] + (int64_t)iz * g.N[0] * g.N[1];
-    uint32_t flo = cs_f[base + x0], fhi = cs_f[base + x1 + 1];
-    w.dlo = nf + cs_d[base + x0];
-    w.dhi = nf + cs_d[base + x1 + 1];
-    w.seg = 0;
-    if (flo < fhi) {
-      w.cur = flo;
-      w.end = fhi;
-      return true;
+    // split the span at a brick boundary (spans are shorter than a brick)
+    const int xb = (x0 / kBrickX + 1) * kBrickX;
+    w.iy = iy;
+    w.iz = iz;
+    w.xs0 = x0;
+    if (x1 >= xb) {
+      w.xe0 = xb - 1;
+      w.xs1 = xb;
+      w.xe1 = x1;
+    } else {
+      w.xe0 = x1;
+      w.xs1 = 1;
+      w.xe1 = 0;
     }
+    w.sub = 0;
   }
+}
+
+// Logical block index with consecutive logical blocks on the same XCD: the
+// hardware deals blocks round-robin over the 8 XCDs (each with its own L2),
+// so block b runs on XCD b % 8; XCD x is given the x-th contiguous share of
+// the logical range, which keeps a neighbourhood's records in one L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks) {
+  const uint32_t q = nblocks / 8, rm = nblocks % 8;
+  const uint32_t x = b % 8, k = b / 8;
+  return x * q + min(x, rm) + k;
 }
 
 // ---------------------------------------------------------- launch helpers

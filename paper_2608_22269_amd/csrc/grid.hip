@@ -124,8 +124,9 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, u
 
 // ------------------------------------------------------------ hash + count
 
-// Cell key of particle i, Eq. (ixyz) and (hashid), plus its slot inside the
-// cell (atomic arrival order).  Out-of-domain or non-finite positions set an
+// Cell of particle i, Eq. (ixyz), its sort key (the HashID's cell in the
+// brick order of cell_key), plus its slot inside the cell (atomic arrival
+// order).  Out-of-domain or non-finite positions set an
 // error bit and are parked in cell 0 so that every later index stays valid.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_hash_f64(Grid g, const double *__restrict__ x,
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(256) k_hash_f64(Grid g, const double *__restri
     }
   }
   uint32_t k = 0;
-  if (!bad) k = (uint32_t)(c[0] + (int64_t)c[1] * g.N[0] + (int64_t)c[2] * g.N[0] * g.N[1]);
+  if (!bad) k = cell_key(g, c[0], c[1], c[2]);
   key[i] = k;
   slot[i] = atomicAdd(&count[k], 1u);
 }
@@ -171,7 +172,7 @@ __global__ void __launch_bounds__(256) k_hash_packed(Grid g, const uint32_t *__r
   if (cx >= g.N[0] || cy >= g.N[1] || cz >= g.N[2]) {
     atomicOr(&sc->err, kErrDomain);
   } else {
-    k = (uint32_t)(cx + (int64_t)cy * g.N[0] + (int64_t)cz * g.N[0] * g.N[1]);
+    k = cell_key(g, cx, cy, cz);
   }
   key[i] = k;
   slot[i] = atomicAdd(&count[k], 1u);
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(256) k_canon(const uint32_t *__restrict__ star
 hipError_t launch_sort_keys(const Grid &g, int dim, const double *x, const double *y, const double *z,
                             const uint32_t *packed_cell, int64_t n, const uint32_t *id, SortScratch &ss,
                             uint32_t *start, uint32_t *perm, Scalars *sc, hipStream_t s) {
-  hipError_t e = launch_fill_u32(ss.count, 0u, g.ncell + 1, s);
+  hipError_t e = launch_fill_u32(ss.count, 0u, g.nkey + 1, s);
   if (e != hipSuccess) return e;
   if (n > 0) {
     if (packed_cell)
@@ -223,11 +224,11 @@ hipError_t launch_sort_keys(const Grid &g, int dim, const double *x, const doubl
       hipLaunchKernelGGL(k_hash_f64<3>, dim3(grid_for(n)), dim3(kBlock), 0, s, g, x, y, z, n, ss.key, ss.slot,
                          ss.count, sc);
   }
-  e = launch_exclusive_scan(ss.count, start, g.ncell, ss.scan_tmp, s);
+  e = launch_exclusive_scan(ss.count, start, g.nkey, ss.scan_tmp, s);
   if (e != hipSuccess) return e;
   if (n > 0) {
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kBlock), 0, s, ss.key, ss.slot, start, n, perm);
-    hipLaunchKernelGGL(k_canon, dim3(grid_for(g.ncell)), dim3(kBlock), 0, s, start, g.ncell, id, perm);
+    hipLaunchKernelGGL(k_canon, dim3(grid_for(g.nkey)), dim3(kBlock), 0, s, start, g.nkey, id, perm);
   }
   return hipGetLastError();
 }

@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
                  uint32_t nf, Scalars *sc, Rates out, uint32_t *__restrict__ cand) {
   __shared__ uint32_t list[kMList][kBlock];
   const int tid = threadIdx.x;
-  const uint32_t i = blockIdx.x * kBlock + tid;
+  const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + tid;
   const bool active = i < nf;
 
   float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0, axa = a0;

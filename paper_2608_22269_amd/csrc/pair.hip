@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
                                                   Rates out, uint32_t *__restrict__ cand) {
   __shared__ uint32_t list[kList][kBlock];
   const int tid = threadIdx.x;
-  const uint32_t i = blockIdx.x * kBlock + tid;
+  const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + tid;
   const bool active = i < nf;
 
   double4 a0 = make_double4(0.0, 0.0, 0.0, 0.0), a1 = a0;

@@ -2,10 +2,12 @@
 produces on the solver's own snapshots.
 
 Data: the 3D dam break (660,000 fluid at dx = 0.01; delta-SPH, shifting, TIC,
-exact detection) and a 3D sloshing tank, stepped on the GPU; at every snapshot
-the particles lambda_min alone cannot decide (0.2 < lambda <= 0.75) are
-collected with their 16 features and the scan-region label.  Split: seeded
-80/20.  Training: the library's FP32 HIP kernels (forward, backward, Adam),
+exact detection) up to t ~ 0.53 s (before the front hits the far wall), a 3D
+sloshing tank, and strongly disordered fluid blocks (lattice jitter 0.2-0.4 dx:
+candidates inside the fluid, mostly covered, supply the interior class),
+evaluated on the GPU; at every snapshot the particles lambda_min alone cannot
+decide (0.2 < lambda <= 0.75) are collected with their 16 features and the
+scan-region label.  Split: seeded 80/20.  Training: the library's FP32 HIP kernels (forward, backward, Adam),
 weighted binary cross-entropy with class weights balancing the two labels.
 The fallback margin tau is the smallest |logit| threshold whose confident
 predictions misclassify at most `target` of the validation candidates; the
@@ -51,6 +53,30 @@ def collect(case, nsteps, every, label):
         st = sim.stats()
         log(f"{label}: t={st['t']:.3f} s, max|U|={st['umax']:.3f}, candidates {len(y)} ({y.mean():.3f} surface)")
     sim.close()
+    return np.concatenate(X), np.concatenate(Y)
+
+
+def collect_disordered(seeds=(11, 12, 13, 14, 15, 16), sigmas=(0.2, 0.3, 0.4)):
+    """Candidates of jittered 3D blocks with random velocity (one right-hand
+    side each)."""
+    from paper_2608_22269_amd import Simulation
+    from paper_2608_22269_amd.learn import candidate_samples
+    import workloads as wl
+
+    X, Y = [], []
+    for sd in seeds:
+        for sg in sigmas:
+            c = wl.box3d(0.01, (0.6, 0.4, 0.5), (0.6, 0.4, 0.3), delta_sph=True, pst=True, tic=True,
+                         fs_project=True, cont_uncorr=True, features=True, fs_mode="exact")
+            c = wl.random_velocity(wl.jitter(c, sg, sd), 0.1, sd + 100)
+            c = wl.with_params(c, cell_size=c["params"]["h"])
+            sim = Simulation(c)
+            sim.eval_rates()
+            f, y = candidate_samples(sim)
+            sim.close()
+            X.append(f)
+            Y.append(y)
+            log(f"disordered block sigma={sg} seed={sd}: candidates {len(y)} ({y.mean():.3f} surface)")
     return np.concatenate(X), np.concatenate(Y)
 
 
@@ -104,8 +130,8 @@ def choose_margin(logits, y, target):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_OUT)
-    ap.add_argument("--dambreak-steps", type=int, default=16000)
-    ap.add_argument("--every", type=int, default=400)
+    ap.add_argument("--dambreak-steps", type=int, default=8000)
+    ap.add_argument("--every", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=24)
     ap.add_argument("--target", type=float, default=1e-3)
     args = ap.parse_args()
@@ -119,8 +145,9 @@ def main():
     sl = wl.slosh3d(dx=0.004, amp=0.02)
     sl = wl.with_params(sl, cell_size=sl["params"]["h"])
     Xb, yb = collect(sl, 4000, 500, "slosh3d")
-    X = np.concatenate([Xa, Xb]).astype(np.float32)
-    y = np.concatenate([ya, yb]).astype(np.float32)
+    Xc, yc = collect_disordered()
+    X = np.concatenate([Xa, Xb, Xc]).astype(np.float32)
+    y = np.concatenate([ya, yb, yc]).astype(np.float32)
     rng = np.random.default_rng(0)
     idx = rng.permutation(len(y))
     ntr = int(0.8 * len(y))
@@ -142,7 +169,8 @@ def main():
               "margin": tau, "val_confident_fraction": float(conf.mean()),
               "val_misclassification_with_fallback": err_conf, "seconds": time.time() - t0,
               "sources": {"dambreak3d": {"dx": 0.01, "steps": args.dambreak_steps, "every": args.every},
-                          "slosh3d": {"dx": 0.004, "amp": 0.02, "steps": 4000, "every": 500}}}
+                          "slosh3d": {"dx": 0.004, "amp": 0.02, "steps": 4000, "every": 500},
+                          "disordered_blocks": {"dx": 0.01, "jitter": [0.2, 0.3, 0.4], "seeds": 6}}}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(report, f, indent=1)
     log(json.dumps({k: v for k, v in report.items() if k != "loss_history"}))
