@@ -190,32 +190,24 @@ void derive(const sph_params *p, Phys &P, Grid &g) {
     g.N[a] = a < p->dim ? (int32_t)std::floor((p->domain_hi[a] - p->domain_lo[a]) / g.R) + 1 : 1;
     g.ncell *= g.N[a];
   }
-  g.B[0] = kBrickX;
-  g.B[1] = p->dim == 3 ? kBrickY : 16;
-  g.B[2] = p->dim == 3 ? kBrickZ : 1;
-  int64_t nb = 1;
-  for (int a = 0; a < 3; ++a) {
-    g.NB[a] = (g.N[a] + g.B[a] - 1) / g.B[a];
-    nb *= g.NB[a];
-  }
-  g.nkey = nb * (int64_t)g.B[0] * g.B[1] * g.B[2];
-  g.brank = nullptr;
+  g.NT[0] = kLinearOrder ? 1 : (g.N[1] + kTileY - 1) / kTileY;
+  g.NT[1] = kLinearOrder ? 1 : (g.N[2] + kTileZ - 1) / kTileZ;
+  const int64_t nb = (int64_t)g.NT[0] * g.NT[1];
+  g.nkey = kLinearOrder ? g.ncell : nb * (int64_t)g.N[0] * kTileY * kTileZ;
+  g.trank = nullptr;
 }
 
-// Morton rank of every brick (bricks sorted by their interleaved coordinates).
-std::vector<uint32_t> brick_ranks(const Grid &g) {
+// Morton rank of every (y, z) tile (tiles sorted by interleaved coordinates).
+std::vector<uint32_t> tile_ranks(const Grid &g) {
   auto spread = [](uint64_t v) {
     uint64_t r = 0;
     for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (3 * b);
     return r;
   };
-  const int64_t nb = (int64_t)g.NB[0] * g.NB[1] * g.NB[2];
+  const int64_t nb = (int64_t)g.NT[0] * g.NT[1];
   std::vector<std::pair<uint64_t, uint32_t>> code((size_t)nb);
-  for (int64_t bz = 0, k = 0; bz < g.NB[2]; ++bz)
-    for (int64_t by = 0; by < g.NB[1]; ++by)
-      for (int64_t bx = 0; bx < g.NB[0]; ++bx, ++k)
-        code[(size_t)k] = {spread((uint64_t)bx) | (spread((uint64_t)by) << 1) | (spread((uint64_t)bz) << 2),
-                           (uint32_t)k};
+  for (int64_t tz = 0, k = 0; tz < g.NT[1]; ++tz)
+    for (int64_t ty = 0; ty < g.NT[0]; ++ty, ++k) code[(size_t)k] = {spread((uint64_t)ty) | (spread((uint64_t)tz) << 1), (uint32_t)k};
   std::sort(code.begin(), code.end());
   std::vector<uint32_t> rank((size_t)nb);
   for (size_t r = 0; r < code.size(); ++r) rank[code[r].second] = (uint32_t)r;
@@ -268,7 +260,7 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   c->rec1 = mixed ? nullptr : cv.take<double4>(nf + nd);
   c->cs_f = cv.take<uint32_t>(c->g.nkey + 1);
   c->cs_d = cv.take<uint32_t>(c->g.nkey + 1);
-  c->g.brank = cv.take<uint32_t>((int64_t)c->g.NB[0] * c->g.NB[1] * c->g.NB[2]);
+  c->g.trank = cv.take<uint32_t>((int64_t)c->g.NT[0] * c->g.NT[1]);
   c->perm = cv.take<uint32_t>(nmax);
   c->ss.key = cv.take<uint32_t>(nmax);
   c->ss.slot = cv.take<uint32_t>(nmax);
@@ -648,9 +640,9 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   Scalars h;
   std::memset(&h, 0, sizeof(h));
   if (e == hipSuccess) e = hipMemcpyAsync(c->sc, &h, sizeof(Scalars), hipMemcpyHostToDevice, s);
-  const std::vector<uint32_t> ranks = brick_ranks(c->g);
+  const std::vector<uint32_t> ranks = tile_ranks(c->g);
   if (e == hipSuccess)
-    e = hipMemcpyAsync((void *)c->g.brank, ranks.data(), sizeof(uint32_t) * ranks.size(), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync((void *)c->g.trank, ranks.data(), sizeof(uint32_t) * ranks.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   // dummies: sort once by (cell, original index)
   if (e == hipSuccess && nd > 0) {

@@ -37,14 +37,27 @@ enum : uint32_t {
 // Background grid (Sec. 3): N_a = floor((hi - lo) / R) + 1 cells per axis.
 //
 // Storage order of the cells.  The paper orders particles by HashID = i_x +
-// i_y N_x + i_z N_x N_y; then a particle's z-neighbours sit a whole cell layer
-// (~10 MB of records at the 17.5M tank) away and no L2 holds a wave's
-// neighbourhood.  The sort key used here keeps x-runs contiguous inside
-// bricks of B_x x B_y x B_z cells and ranks the bricks along a Morton curve:
-//   key = rank(brick) * B_x B_y B_z + (lx + ly B_x + lz B_x B_y).
-// Cell coordinates, HashID and neighbour sets are unchanged; only the order
-// particles are stored and visited in differs.
-constexpr int kBrickX = 16, kBrickY = 4, kBrickZ = 4;
+// i_y N_x + i_z N_x N_y; a particle's z-neighbours then sit a whole cell layer
+// away.  The sort key used here groups the x-rows into tiles of B_y x B_z rows
+// (whole x-rows, so every row stays one contiguous run) and ranks the tiles
+// along a Morton curve:
+//   key = rank(y / B_y, z / B_z) * N_x B_y B_z + x + (y mod B_y) N_x
+//         + (z mod B_z) N_x B_y.
+// B_y = B_z = 0 is the paper's linear order.  Cell coordinates, HashID and the
+// neighbour sets do not depend on it; only the storage and visiting order do.
+#ifndef WB_TILE_Y
+#define WB_TILE_Y 8
+#endif
+#ifndef WB_TILE_Z
+#define WB_TILE_Z 8
+#endif
+#ifndef WB_XCD_REMAP
+#define WB_XCD_REMAP 1
+#endif
+constexpr int kTileY = WB_TILE_Y, kTileZ = WB_TILE_Z;  // powers of two (or 0)
+constexpr bool kLinearOrder = (WB_TILE_Y == 0 || WB_TILE_Z == 0);
+static_assert(kLinearOrder || ((kTileY & (kTileY - 1)) == 0 && (kTileZ & (kTileZ - 1)) == 0),
+              "tile sizes are powers of two");
 
 struct Grid {
   double lo[3];
@@ -54,18 +67,18 @@ struct Grid {
   int32_t N[3];
   int32_t reach; // cells searched on each side, ceil(2h / R)
   int64_t ncell;
-  int32_t B[3];      // brick size in cells (z = 1 in 2D)
-  int32_t NB[3];     // bricks per axis
-  int64_t nkey;      // number of sort keys = bricks * brick volume (>= ncell)
-  const uint32_t *brank;  // Morton rank of every brick (NB0 NB1 NB2 entries)
+  int32_t NT[2];     // tiles along y and z
+  int64_t nkey;      // number of sort keys (>= ncell)
+  const uint32_t *trank;  // Morton rank of every (y, z) tile (NT0 NT1 entries)
 };
 
 // Sort key of cell (x, y, z).
 __device__ __forceinline__ uint32_t cell_key(const Grid &g, int x, int y, int z) {
-  const int bx = x / kBrickX, by = y / g.B[1], bz = z / g.B[2];
-  const int lx = x - bx * kBrickX, ly = y - by * g.B[1], lz = z - bz * g.B[2];
-  const uint32_t r = g.brank[bx + (int64_t)by * g.NB[0] + (int64_t)bz * g.NB[0] * g.NB[1]];
-  return r * (uint32_t)(kBrickX * g.B[1] * g.B[2]) + (uint32_t)(lx + ly * kBrickX + lz * kBrickX * g.B[1]);
+  if (kLinearOrder) return (uint32_t)(x + (int64_t)y * g.N[0] + (int64_t)z * g.N[0] * g.N[1]);
+  const int ty = y / kTileY, tz = z / kTileZ;  // constant powers of two: shifts
+  const uint32_t r = g.trank[ty + tz * g.NT[0]];
+  return r * (uint32_t)(g.N[0] * kTileY * kTileZ) +
+         (uint32_t)(x + (y - ty * kTileY) * g.N[0] + (z - tz * kTileZ) * g.N[0] * kTileY);
 }
 
 // Physical / numerical constants as the kernels need them.
@@ -243,21 +256,19 @@ __device__ __forceinline__ void sym_mul(const double I[6], const double v[3], do
 // ------------------------------------------------------- cell-row walker
 //
 // Algorithm 1 visits the 3^d cells around the particle's cell.  Cells along x
-// are consecutive in storage inside a brick, so each (y, z) offset is one
-// contiguous run of particles, or two where the x span crosses a brick
-// boundary.  With cells smaller than 2h the walker visits (2 reach + 1)^(d-1)
-// rows; a row whose (y, z) slab is farther than 2h from the particle is
-// skipped and the x span is cut to the particle's reach.  The cuts are
-// conservative (slightly widened); the exact test is done per pair.  Each row
-// yields up to four runs: fluid and dummy records of each x sub-span.
+// are consecutive in storage, so each (y, z) offset is one contiguous run of
+// particles: one "row".  With cells smaller than 2h the walker visits
+// (2 reach + 1)^(d-1) rows; a row whose (y, z) slab is farther than 2h from
+// the particle is skipped and the x span is cut to the particle's reach.  The
+// cuts are conservative (slightly widened); the exact test is done per pair.
+// Each row yields up to two runs: its fluid and its dummy records.
 struct RowWalker {
   int32_t row;       // next row index in [0, nrows)
   int32_t nrows;
-  int32_t sub;       // next run of the current row, 0..3 (4 = row done)
+  int32_t seg;       // 0: fluid part of the current row emitted, 1: row done
   uint32_t cur, end; // current run [cur, end) in record index space
   int32_t cx, cy, cz;
-  int32_t iy, iz;            // current row
-  int32_t xs0, xe0, xs1, xe1;  // x sub-spans of the row (xs1 > xe1: none)
+  uint32_t dlo, dhi; // dummy run of the current row (absolute record index)
 };
 
 template <int DIM>
@@ -268,11 +279,9 @@ __device__ __forceinline__ void walker_init(RowWalker &w, const Grid &g, double 
   int side = 2 * g.reach + 1;
   w.nrows = DIM == 3 ? side * side : side;
   w.row = 0;
-  w.sub = 4;
+  w.seg = 1;
   w.cur = w.end = 0;
-  w.iy = w.iz = 0;
-  w.xs0 = w.xs1 = 1;
-  w.xe0 = w.xe1 = 0;
+  w.dlo = w.dhi = 0;
 }
 
 // Advances to the next non-empty run; returns false when the walk is over.
@@ -283,22 +292,11 @@ __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const u
                                             const uint32_t *__restrict__ cs_d, uint32_t nf, double x, double y,
                                             double z, double two_h) {
   for (;;) {
-    if (w.sub < 4) {
-      const int s = w.sub++;
-      const bool second = s >= 2, dummy = (s & 1) != 0;
-      const int xs = second ? w.xs1 : w.xs0, xe = second ? w.xe1 : w.xe0;
-      if (xs > xe) continue;
-      const uint32_t k0 = cell_key(g, xs, w.iy, w.iz);
-      const uint32_t k1 = k0 + (uint32_t)(xe - xs);  // same brick: consecutive keys
-      const uint32_t *cs = dummy ? cs_d : cs_f;
-      uint32_t lo = cs[k0], hi = cs[k1 + 1];
-      if (dummy) {
-        lo += nf;
-        hi += nf;
-      }
-      if (lo < hi) {
-        w.cur = lo;
-        w.end = hi;
+    if (w.seg == 0) {  // fluid part done: emit the dummy part of the same row
+      w.seg = 1;
+      if (w.dlo < w.dhi) {
+        w.cur = w.dlo;
+        w.end = w.dhi;
         return true;
       }
       continue;
@@ -329,21 +327,17 @@ __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const u
     x0 = max(x0, max(w.cx - g.reach, 0));
     x1 = min(x1, min(w.cx + g.reach, g.N[0] - 1));
     if (x0 > x1) continue;
-    // split the span at a brick boundary (spans are shorter than a brick)
-    const int xb = (x0 / kBrickX + 1) * kBrickX;
-    w.iy = iy;
-    w.iz = iz;
-    w.xs0 = x0;
-    if (x1 >= xb) {
-      w.xe0 = xb - 1;
-      w.xs1 = xb;
-      w.xe1 = x1;
-    } else {
-      w.xe0 = x1;
-      w.xs1 = 1;
-      w.xe1 = 0;
+    const uint32_t k0 = cell_key(g, x0, iy, iz);
+    const uint32_t k1 = k0 + (uint32_t)(x1 - x0) + 1u;  // x-row cells are consecutive keys
+    const uint32_t flo = cs_f[k0], fhi = cs_f[k1];
+    w.dlo = nf + cs_d[k0];
+    w.dhi = nf + cs_d[k1];
+    w.seg = 0;
+    if (flo < fhi) {
+      w.cur = flo;
+      w.end = fhi;
+      return true;
     }
-    w.sub = 0;
   }
 }
 
@@ -352,6 +346,7 @@ __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const u
 // so block b runs on XCD b % 8; XCD x is given the x-th contiguous share of
 // the logical range, which keeps a neighbourhood's records in one L2.
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks) {
+  if (!WB_XCD_REMAP) return b;
   const uint32_t q = nblocks / 8, rm = nblocks % 8;
   const uint32_t x = b % 8, k = b / 8;
   return x * q + min(x, rm) + k;
