@@ -59,13 +59,41 @@ def traffic_from_profiles(kernel_key, launches_pairs):
     return d.get("hbm_bytes_per_launch")
 
 
-def run_path(case, label, steps, warmup, **overrides):
+def load_classifier():
+    path = os.path.join(ROOT, "paper_2608_22269_amd", "data", "fs_classifier.npz")
+    with np.load(path) as z:
+        return {k: z[k] for k in ("params", "mean", "std", "margin")}
+
+
+def misclassification(sim, case, clf):
+    """Free-surface flags of the learned detector against the exact scan-region
+    criterion on the same state: one right-hand side with the trained margin,
+    one with an infinite margin (every candidate decided by the exact test)."""
+    f = case["kind"] == 0
+    sim.eval_rates()
+    fs_l = sim.field("fs")[f]
+    st = sim.stats()
+    sim.set_classifier(clf["params"], clf["mean"], clf["std"], float("inf"))
+    sim.eval_rates()
+    fs_e = sim.field("fs")[f]
+    sim.set_classifier(clf["params"], clf["mean"], clf["std"], float(clf["margin"]))
+    wrong = int((fs_l != fs_e).sum())
+    cand = max(float(st["n_cand"]), 1.0)
+    return {"fluid": int(f.sum()), "candidates": int(st["n_cand"]), "decided_by_mlp": int(st["n_mlp"]),
+            "fallback_exact": int(st["n_scan"]), "misclassified": wrong,
+            "rate_of_fluid": wrong / max(int(f.sum()), 1), "rate_of_candidates": wrong / cand,
+            "fs_exact": int(fs_e.sum()), "fs_learned": int(fs_l.sum())}
+
+
+def run_path(case, label, steps, warmup, clf=None):
     import torch
     from paper_2608_22269_amd import Simulation
 
     log(f"{label}: init ({case['meta']['n_fluid']} fluid + {case['meta']['n_dummy']} dummies)")
     t0 = time.time()
-    sim = Simulation(case, **overrides)
+    sim = Simulation(case)
+    if clf is not None:
+        sim.set_classifier(clf["params"], clf["mean"], clf["std"], float(clf["margin"]))
     torch.cuda.synchronize()
     log(f"{label}: init done in {time.time() - t0:.1f} s; warmup {warmup} steps")
     sim.step(warmup)
@@ -105,8 +133,14 @@ def run_path(case, label, steps, warmup, **overrides):
         "fs_count": st["n_fs"],
         "fs_candidates": st["n_cand"],
     }
+    if clf is not None:
+        out["fs_decided_by_mlp"] = st["n_mlp"]
+        out["fs_fallback_exact"] = st["n_scan"]
     log(f"{label}: {ms_step:.2f} ms/step, {out['pair_evals_per_s']:.3e} pair-evals/s, "
         f"pair pass {pair_ms:.2f} ms ({achieved:.1f} TFLOP/s)")
+    if clf is not None:
+        out["misclassification"] = misclassification(sim, case, clf)
+        log(f"{label}: free-surface misclassification {out['misclassification']}")
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -136,11 +170,11 @@ def cpu_baseline(dx):
     }
 
 
-def spurious_velocity():
-    """FP64 hydrostatic 2D tank (5,000 fluid): max |U| after 100 steps."""
+def spurious_velocity(precision):
+    """Hydrostatic 2D tank (5,000 fluid): max |U| after 100 steps."""
     import workloads as wl
     from paper_2608_22269_amd import Simulation
-    case = wl.tank2d()
+    case = wl.tank2d(precision=precision)
     sim = Simulation(case)
     sim.step(100)
     u = sim.field("u")[case["kind"] == 0]
@@ -158,7 +192,9 @@ def main():
                     help="background cell size in units of h (the paper's R = 2h is 2.0; R = h visits fewer "
                          "candidates for the same neighbour sets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paths", default="fp64,mixed")
+    ap.add_argument("--paths", default="fp64,mixed,mixed_learned",
+                    help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
+                         "mixed_learned: mixed precision with the trained classifier and exact fallback")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -189,6 +225,9 @@ def main():
             results["fp64"] = run_path(case, "fp64", args.steps, args.warmup)
         elif path == "mixed":
             results["mixed"] = run_path(wl.with_params(case, precision="mixed"), "mixed", args.steps, args.warmup)
+        elif path == "mixed_learned":
+            results["mixed_learned"] = run_path(wl.with_params(case, precision="mixed", fs_mode="learned"),
+                                                "mixed_learned", args.steps, args.warmup, clf=load_classifier())
         else:
             raise SystemExit(f"unknown path {path}")
     head = results["fp64"]
@@ -216,9 +255,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.dx)
-    if "mixed" in results:
-        out["mixed_over_fp64_step_rate"] = results["fp64"]["ms_per_step"] / results["mixed"]["ms_per_step"]
-    out["spurious_u_fp64_tank2d_100steps"] = spurious_velocity()
+    for k in ("mixed", "mixed_learned"):
+        if k in results:
+            out[f"{k}_over_fp64_step_rate"] = results["fp64"]["ms_per_step"] / results[k]["ms_per_step"]
+    out["spurious_u_tank2d_100steps"] = {"fp64": spurious_velocity("fp64"), "mixed": spurious_velocity("mixed")}
     print(json.dumps(out), flush=True)
 
 

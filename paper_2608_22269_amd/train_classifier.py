@@ -2,10 +2,11 @@
 produces on the solver's own snapshots.
 
 Data: the 3D dam break (660,000 fluid at dx = 0.01; delta-SPH, shifting, TIC,
-exact detection) up to t ~ 0.53 s (before the front hits the far wall), a 3D
-sloshing tank, and strongly disordered fluid blocks (lattice jitter 0.2-0.4 dx:
-candidates inside the fluid, mostly covered, supply the interior class),
-evaluated on the GPU; at every snapshot the particles lambda_min alone cannot
+exact detection) up to t ~ 0.53 s (before the front hits the far wall), a
+second, taller dam-break column (0.5 x 0.6 x 0.6 m in a 2.0 x 0.6 x 1.0 m
+tank), a 3D sloshing tank, and strongly disordered fluid blocks (lattice
+jitter 0.2-0.4 dx: candidates inside the fluid, mostly covered, supply the
+interior class), evaluated on the GPU; at every snapshot the particles lambda_min alone cannot
 decide (0.2 < lambda <= 0.75) are collected with their 16 features and the
 scan-region label.  Split: seeded 80/20.  Training: the library's FP32 HIP kernels (forward, backward, Adam),
 weighted binary cross-entropy with class weights balancing the two labels.
@@ -131,9 +132,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--dambreak-steps", type=int, default=8000)
-    ap.add_argument("--every", type=int, default=200)
+    ap.add_argument("--every", type=int, default=100)
     ap.add_argument("--epochs", type=int, default=24)
-    ap.add_argument("--target", type=float, default=1e-3)
+    ap.add_argument("--target", type=float, default=3e-4,
+                    help="misclassification allowed among the validation candidates (sets the margin)")
     args = ap.parse_args()
     import workloads as wl
     from paper_2608_22269_amd.learn import infer_bf16
@@ -142,12 +144,16 @@ def main():
     db = wl.dambreak3d(dx=0.01)
     db = wl.with_params(db, cell_size=db["params"]["h"])
     Xa, ya = collect(db, args.dambreak_steps, args.every, "dambreak3d")
+    tall = wl.dambreak3d(dx=0.01, tank=(2.0, 0.6, 1.0), column=(0.5, 0.6, 0.6))
+    tall = wl.with_params(tall, cell_size=tall["params"]["h"])
+    tall_steps = min(args.dambreak_steps, 6000)  # t ~ 0.34 s: the front reaches the far wall
+    Xt, yt = collect(tall, tall_steps, args.every, "dambreak3d tall column")
     sl = wl.slosh3d(dx=0.004, amp=0.02)
     sl = wl.with_params(sl, cell_size=sl["params"]["h"])
-    Xb, yb = collect(sl, 4000, 500, "slosh3d")
+    Xb, yb = collect(sl, 4000, 250, "slosh3d")
     Xc, yc = collect_disordered()
-    X = np.concatenate([Xa, Xb, Xc]).astype(np.float32)
-    y = np.concatenate([ya, yb, yc]).astype(np.float32)
+    X = np.concatenate([Xa, Xt, Xb, Xc]).astype(np.float32)
+    y = np.concatenate([ya, yt, yb, yc]).astype(np.float32)
     rng = np.random.default_rng(0)
     idx = rng.permutation(len(y))
     ntr = int(0.8 * len(y))
@@ -168,9 +174,14 @@ def main():
               "n_val": int(len(va_i)), "loss_history": hist, "val_misclassification_raw": err_raw,
               "margin": tau, "val_confident_fraction": float(conf.mean()),
               "val_misclassification_with_fallback": err_conf, "seconds": time.time() - t0,
-              "sources": {"dambreak3d": {"dx": 0.01, "steps": args.dambreak_steps, "every": args.every},
-                          "slosh3d": {"dx": 0.004, "amp": 0.02, "steps": 4000, "every": 500},
-                          "disordered_blocks": {"dx": 0.01, "jitter": [0.2, 0.3, 0.4], "seeds": 6}}}
+              "target": args.target,
+              "sources": {"dambreak3d": {"dx": 0.01, "steps": args.dambreak_steps, "every": args.every,
+                                         "n": int(len(ya))},
+                          "dambreak3d_tall": {"dx": 0.01, "tank": [2.0, 0.6, 1.0], "column": [0.5, 0.6, 0.6],
+                                              "steps": tall_steps, "every": args.every, "n": int(len(yt))},
+                          "slosh3d": {"dx": 0.004, "amp": 0.02, "steps": 4000, "every": 250, "n": int(len(yb))},
+                          "disordered_blocks": {"dx": 0.01, "jitter": [0.2, 0.3, 0.4], "seeds": 6,
+                                                "n": int(len(yc))}}}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(report, f, indent=1)
     log(json.dumps({k: v for k, v in report.items() if k != "loss_history"}))
