@@ -182,6 +182,68 @@ def spurious_velocity(precision):
     return float(np.abs(u).max())
 
 
+def mlp_inference(n, reps=5):
+    """BF16 MFMA inference of the trained classifier over n rows of 16 FP32
+    features (seeded normal values scaled like the training data), as one
+    call on 17.5M particles would run it; HBM bytes 16 x 4 in + 4 out per
+    row, 2 x (16 x 64 + 64 x 64 + 64) FLOP per row."""
+    import torch
+    from paper_2608_22269_amd import learn
+    clf = load_classifier()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    X = torch.randn(n, 16, device="cuda", generator=g) * torch.as_tensor(clf["std"], device="cuda") \
+        + torch.as_tensor(clf["mean"], device="cuda")
+    s = torch.cuda.current_stream()
+    learn.infer_bf16(clf["params"], clf["mean"], clf["std"], X)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        learn.infer_bf16(clf["params"], clf["mean"], clf["std"], X)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = n * (16 * 4 + 4)
+    flop = n * 2 * (16 * 64 + 64 * 64 + 64)
+    del X
+    return {"rows": n, "ms_per_call": ms, "rows_per_s": n / (ms * 1e-3),
+            "hbm_gb_s": nbytes / (ms * 1e-3) / 1e9, "hbm_frac": nbytes / (ms * 1e-3) / 8e12,
+            "tflops": flop / (ms * 1e-3) / 1e12, "bf16_mfma_frac": flop / (ms * 1e-3) / 2.5e15,
+            "note": "includes the per-call upload of the weights and the normalisation (5,345 floats)"}
+
+
+def bump_history(steps, every):
+    """2D water layer 2.0 x 0.5 m over a Gaussian bump (amplitude 0.1 m, sigma
+    0.1 m), dx = 0.002 (243.7k fluid), hydrostatic start: fluid max |U| every
+    `every` steps on the FP64 and the mixed path, with the printed scheme
+    (no stabilisers) and with the tensile-instability switch on.  A run that
+    stops on a device error (the free-surface mode's blow-up) reports the step
+    and the error."""
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    from paper_2608_22269_amd._lib import SphError
+    out = {}
+    for label, kw in (("literal", {}), ("tic", {"tic": True, "cont_uncorr": True})):
+        for prec in ("fp64", "mixed"):
+            case = wl.bump2d(precision=prec, **kw)
+            f = case["kind"] == 0
+            sim = Simulation(case)
+            hist, err = [], None
+            t0 = time.time()
+            try:
+                for k in range(0, steps, every):
+                    sim.step(every)
+                    u = sim.field("u")[f]
+                    hist.append([k + every, float(np.sqrt((u * u).sum(1)).max())])
+            except SphError as e:
+                err = str(e)
+            out[f"{label}/{prec}"] = {"max_u": hist, "error": err, "seconds": time.time() - t0,
+                                      "n_fluid": int(f.sum())}
+            log(f"bump2d {label}/{prec}: {hist[-1] if hist else None} {err or ''}")
+            sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +257,8 @@ def main():
     ap.add_argument("--paths", default="fp64,mixed,mixed_learned",
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
                          "mixed_learned: mixed precision with the trained classifier and exact fallback")
+    ap.add_argument("--bump-steps", type=int, default=10000,
+                    help="steps of the 2D Gaussian-bump spurious-velocity history (0: skip)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -258,7 +322,10 @@ def main():
     for k in ("mixed", "mixed_learned"):
         if k in results:
             out[f"{k}_over_fp64_step_rate"] = results["fp64"]["ms_per_step"] / results[k]["ms_per_step"]
+    out["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     out["spurious_u_tank2d_100steps"] = {"fp64": spurious_velocity("fp64"), "mixed": spurious_velocity("mixed")}
+    if args.bump_steps > 0:
+        out["spurious_u_bump2d"] = bump_history(args.bump_steps, 500)
     print(json.dumps(out), flush=True)
 
 

@@ -606,7 +606,7 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
 
         /* pair sums over N(i), Algorithm 1 / Eq. (sph) */
         double L[9] = {0}, g[3] = {0}, SR[3] = {0}, SC[3] = {0}, Nm[9] = {0}, P[3] = {0};
-        double Dsum = 0.0, S0 = 0.0, m1[3] = {0}, m2[9] = {0}, qmin = 2.0;
+        double Dsum = 0.0, S0 = 0.0, qmin = 2.0;
         int nd_count = 0;
         const double *xi = x + i * dim, *ui = uv + i * dim;
         const double phii = phiv[i];
@@ -648,11 +648,8 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
             double wr = Wq / W0;
             double pw = 1.0 + p->pst_R * pow(wr, p->pst_n);
             for (int a = 0; a < dim; ++a) P[a] += pw * gw[a] * Vj;
-            /* classifier moments */
+            /* classifier inputs: kernel sum, closest neighbour, dummies */
             S0 += Wq * Vj;
-            for (int a = 0; a < dim; ++a) m1[a] += Wq * r[a] * Vj;
-            for (int a = 0; a < dim; ++a)
-                for (int b = 0; b < dim; ++b) m2[a * dim + b] += Wq * r[a] * r[b] * Vj;
             if (q < qmin) qmin = q;
             if (kind[j] == 1) nd_count++;
         }
@@ -719,22 +716,24 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
             }
         }
 
-        /* features (16): eigenvalues, det, kernel sum (with self term),
-         * neighbour count, |g| h, normal-direction moments, ... */
+        /* features (16): eigenvalues of L, det L, kernel sum (with the self
+         * term), neighbour count, |g| h, the moments of the kernel-gradient
+         * sum g and of L along the normal n and across it, |L^-T g| h, n
+         * against gravity, dummy fraction, closest-neighbour q, |P| h */
         {
             double Wself = orc_W(dim, h, 0.0) * V[i];
             double S0s = S0 + Wself;
-            double m1n = 0.0, m1sq = 0.0, nm2n = 0.0, trm2 = 0.0, gn2 = 0.0, Pn2 = 0.0, ngrav = 0.0, gg2 = 0.0;
+            double ng = 0.0, gn2 = 0.0, nLn = 0.0, trL = 0.0, Pn2 = 0.0, ngrav = 0.0, gg2 = 0.0;
             for (int a = 0; a < dim; ++a) {
-                m1n += nrm[a] * m1[a];
-                m1sq += m1[a] * m1[a];
-                trm2 += m2[a * dim + a];
+                ng += nrm[a] * g[a];
                 gn2 += g[a] * g[a];
+                trL += L[a * dim + a];
                 Pn2 += P[a] * P[a];
                 ngrav += nrm[a] * G[a];
                 gg2 += G[a] * G[a];
-                for (int b = 0; b < dim; ++b) nm2n += nrm[a] * m2[a * dim + b] * nrm[b];
+                for (int b = 0; b < dim; ++b) nLn += nrm[a] * L[a * dim + b] * nrm[b];
             }
+            double gt2 = gn2 - ng * ng;
             int cnt = (int)(off[i + 1] - off[i]);
             ft[0] = lam[0];
             ft[1] = lam[1];
@@ -743,10 +742,10 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
             ft[4] = S0s;
             ft[5] = (double)cnt;
             ft[6] = sqrt(gn2) * h;
-            ft[7] = S0s > 0.0 ? m1n / (S0s * h) : 0.0;
-            ft[8] = S0s > 0.0 ? sqrt(m1sq) / (S0s * h) : 0.0;
-            ft[9] = S0s > 0.0 ? nm2n / (S0s * h * h) : 0.0;
-            ft[10] = S0s > 0.0 ? (trm2 - nm2n) / (S0s * h * h) : 0.0;
+            ft[7] = ng * h;
+            ft[8] = sqrt(gt2 > 0.0 ? gt2 : 0.0) * h;
+            ft[9] = nLn;
+            ft[10] = trL - nLn;
             ft[11] = nn * h;
             ft[12] = gg2 > 0.0 ? ngrav / sqrt(gg2) : 0.0;
             ft[13] = cnt > 0 ? (double)nd_count / (double)cnt : 0.0;

@@ -260,28 +260,79 @@ __device__ __forceinline__ void sym_mul(const double I[6], const double v[3], do
 // particles: one "row".  With cells smaller than 2h the walker visits
 // (2 reach + 1)^(d-1) rows; a row whose (y, z) slab is farther than 2h from
 // the particle is skipped and the x span is cut to the particle's reach.  The
-// cuts are conservative (slightly widened); the exact test is done per pair.
-// Each row yields up to two runs: its fluid and its dummy records.
+// cuts only bound the search, so they are evaluated in FP32 in cell units
+// from the particle's position inside its own cell and widened by 1e-5 cell
+// (far above the FP32 rounding of numbers below 2 reach + 1); set membership
+// is decided per pair by the exact test.  Each row yields up to two runs:
+// its fluid and its dummy records.
 struct RowWalker {
-  int32_t row;       // next row index in [0, nrows)
+  int32_t row;        // next row index in [0, nrows)
   int32_t nrows;
-  int32_t seg;       // 0: fluid part of the current row emitted, 1: row done
-  uint32_t cur, end; // current run [cur, end) in record index space
+  int32_t seg;        // 0: fluid part of the current row emitted, 1: row done
+  uint32_t cur, end;  // current run [cur, end) in record index space
+  uint32_t dlo, dhi;  // dummy run of the current row (absolute record index)
   int32_t cx, cy, cz;
-  uint32_t dlo, dhi; // dummy run of the current row (absolute record index)
+  float ux, uy, uz;   // position inside the own cell, in cells ([0, 1) up to rounding)
+  float rr2;          // (2h / R)^2, widened
+  int32_t tkey;       // tile of the cached rank (-1: none)
+  uint32_t tbase;     // first sort key of that tile
 };
 
+constexpr float kWalkSlack = 1e-5f;
+
+// From an FP64 position: the own cell is the exact cell index of Eq. (ixyz).
 template <int DIM>
-__device__ __forceinline__ void walker_init(RowWalker &w, const Grid &g, double x, double y, double z) {
+__device__ __forceinline__ void walker_init(RowWalker &w, const Grid &g, double x, double y, double z,
+                                            double two_h) {
   w.cx = cell_coord(x, g.lo[0], g.R);
   w.cy = cell_coord(y, g.lo[1], g.R);
   w.cz = DIM == 3 ? cell_coord(z, g.lo[2], g.R) : 0;
-  int side = 2 * g.reach + 1;
-  w.nrows = DIM == 3 ? side * side : side;
+  w.ux = (float)((x - (g.lo[0] + (double)w.cx * g.R)) * g.invR);
+  w.uy = (float)((y - (g.lo[1] + (double)w.cy * g.R)) * g.invR);
+  w.uz = DIM == 3 ? (float)((z - (g.lo[2] + (double)w.cz * g.R)) * g.invR) : 0.0f;
+  const float rr = (float)(two_h * g.invR);
+  w.rr2 = rr * rr * (1.0f + 4.0f * kWalkSlack);
+  w.nrows = DIM == 3 ? (2 * g.reach + 1) * (2 * g.reach + 1) : 2 * g.reach + 1;
   w.row = 0;
   w.seg = 1;
   w.cur = w.end = 0;
   w.dlo = w.dhi = 0;
+  w.tkey = -1;
+  w.tbase = 0;
+}
+
+// From a stored cell and the offset inside it (mixed path; offsets in metres).
+template <int DIM>
+__device__ __forceinline__ void walker_init_cell(RowWalker &w, const Grid &g, int cx, int cy, int cz, float ox,
+                                                 float oy, float oz, double two_h) {
+  w.cx = cx;
+  w.cy = cy;
+  w.cz = DIM == 3 ? cz : 0;
+  const float invR = (float)g.invR;
+  w.ux = ox * invR;
+  w.uy = oy * invR;
+  w.uz = DIM == 3 ? oz * invR : 0.0f;
+  const float rr = (float)(two_h * g.invR);
+  w.rr2 = rr * rr * (1.0f + 4.0f * kWalkSlack);
+  w.nrows = DIM == 3 ? (2 * g.reach + 1) * (2 * g.reach + 1) : 2 * g.reach + 1;
+  w.row = 0;
+  w.seg = 1;
+  w.cur = w.end = 0;
+  w.dlo = w.dhi = 0;
+  w.tkey = -1;
+  w.tbase = 0;
+}
+
+// Sort key of cell (x, y, z), reusing the walker's cached tile rank.
+__device__ __forceinline__ uint32_t walker_key(RowWalker &w, const Grid &g, int x, int y, int z) {
+  if (kLinearOrder) return cell_key(g, x, y, z);
+  const int ty = y / kTileY, tz = z / kTileZ;
+  const int t = ty + tz * g.NT[0];
+  if (t != w.tkey) {
+    w.tkey = t;
+    w.tbase = g.trank[t] * (uint32_t)(g.N[0] * kTileY * kTileZ);
+  }
+  return w.tbase + (uint32_t)(x + (y - ty * kTileY) * g.N[0] + (z - tz * kTileZ) * g.N[0] * kTileY);
 }
 
 // Advances to the next non-empty run; returns false when the walk is over.
@@ -289,8 +340,7 @@ __device__ __forceinline__ void walker_init(RowWalker &w, const Grid &g, double 
 // dummy records; dummy records live at index nf + k.
 template <int DIM>
 __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const uint32_t *__restrict__ cs_f,
-                                            const uint32_t *__restrict__ cs_d, uint32_t nf, double x, double y,
-                                            double z, double two_h) {
+                                            const uint32_t *__restrict__ cs_d, uint32_t nf) {
   for (;;) {
     if (w.seg == 0) {  // fluid part done: emit the dummy part of the same row
       w.seg = 1;
@@ -309,25 +359,20 @@ __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const u
     const int iy = w.cy + dy, iz = w.cz + dz;
     if (iy < 0 || iy >= g.N[1]) continue;
     if (DIM == 3 && (iz < 0 || iz >= g.N[2])) continue;
-    // distance from the particle to the row's (y, z) slab, slightly reduced
-    double ey = 0.0, ez = 0.0;
-    if (dy > 0) ey = (g.lo[1] + (double)iy * g.R) - y;
-    if (dy < 0) ey = y - (g.lo[1] + (double)(iy + 1) * g.R);
-    if (DIM == 3) {
-      if (dz > 0) ez = (g.lo[2] + (double)iz * g.R) - z;
-      if (dz < 0) ez = z - (g.lo[2] + (double)(iz + 1) * g.R);
-    }
-    ey = fmax(0.0, ey - 1e-12 * g.R);
-    ez = fmax(0.0, ez - 1e-12 * g.R);
-    const double rem = two_h * two_h - ey * ey - ez * ez;
-    if (rem < 0.0) continue;
-    const double reach = sqrt(rem) * (1.0 + 1e-12) + 1e-12 * g.R;
-    int x0 = cell_coord(x - reach, g.lo[0], g.R);
-    int x1 = cell_coord(x + reach, g.lo[0], g.R);
+    // distance (cells) from the particle to the row's (y, z) slab, shortened
+    float ey = dy > 0 ? (float)dy - w.uy : (dy < 0 ? w.uy - (float)(dy + 1) : 0.0f);
+    float ez = DIM == 3 ? (dz > 0 ? (float)dz - w.uz : (dz < 0 ? w.uz - (float)(dz + 1) : 0.0f)) : 0.0f;
+    ey = fmaxf(0.0f, ey - kWalkSlack);
+    ez = fmaxf(0.0f, ez - kWalkSlack);
+    const float rem = w.rr2 - ey * ey - ez * ez;
+    if (rem < 0.0f) continue;
+    const float reach = sqrtf(rem) + kWalkSlack;
+    int x0 = w.cx + (int)floorf(w.ux - reach);
+    int x1 = w.cx + (int)floorf(w.ux + reach);
     x0 = max(x0, max(w.cx - g.reach, 0));
     x1 = min(x1, min(w.cx + g.reach, g.N[0] - 1));
     if (x0 > x1) continue;
-    const uint32_t k0 = cell_key(g, x0, iy, iz);
+    const uint32_t k0 = walker_key(w, g, x0, iy, iz);
     const uint32_t k1 = k0 + (uint32_t)(x1 - x0) + 1u;  // x-row cells are consecutive keys
     const uint32_t flo = cs_f[k0], fhi = cs_f[k1];
     w.dlo = nf + cs_d[k0];

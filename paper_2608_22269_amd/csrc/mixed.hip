@@ -26,14 +26,14 @@
 
 namespace wb {
 
+// waves per SIMD the register allocation targets (plain / with features)
 #ifndef WB_MIXED_WAVES
-#define WB_MIXED_WAVES 3
+#define WB_MIXED_WAVES 4
 #endif
-#if WB_MIXED_WAVES > 0
-#define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(WB_MIXED_WAVES)))
-#else
-#define WB_MIXED_ATTR
+#ifndef WB_MIXED_WAVES_FEAT
+#define WB_MIXED_WAVES_FEAT 3
 #endif
+#define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_MIXED_WAVES_FEAT : WB_MIXED_WAVES)))
 constexpr int kMList = 32;
 constexpr int kMBatch = 4;
 
@@ -166,11 +166,11 @@ __global__ void __launch_bounds__(256) k_mirror_mixed(Phys P, Grid g, Dummies d,
   const float xf = (float)xd, yf = (float)yd, zf = (float)zd;
   const float two_h2 = (float)P.two_h2;
   RowWalker w;
-  walker_init<DIM>(w, g, xd, yd, zd);
+  walker_init<DIM>(w, g, xd, yd, zd, P.two_h);
   int64_t best = -1;
   uint32_t best_id = 0;
   float best_r2 = 0.f;
-  while (walker_next<DIM>(w, g, cs_f, cs_f, nf, xd, yd, zd, P.two_h)) {
+  while (walker_next<DIM>(w, g, cs_f, cs_f, nf)) {
     if (w.cur >= nf) continue;
     for (uint32_t j = w.cur; j < w.end; ++j) {
       float4 b = rec.xa[j];
@@ -233,7 +233,8 @@ hipError_t launch_mirror_mixed(const Phys &P, const Grid &g, const Dummies &d, i
 
 // -------------------------------------------------------------- pair pass
 
-template <int DIM, bool FEAT>
+// PST4: the shifting exponent is 4 (two squarings); otherwise powf().
+template <int DIM, bool FEAT, bool PST4>
 __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     k_pair_mixed(Phys P, Grid g, MixedRec rec, const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
                  uint32_t nf, Scalars *sc, Rates out, uint32_t *__restrict__ cand) {
@@ -252,19 +253,15 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
   }
   const uint32_t ci = __float_as_uint(a0.w);
   const int cix = cell_x(ci), ciy = cell_y(ci), ciz = cell_z(ci);
-  // the walker works on FP64 positions reconstructed from cell + offset
-  const double px = pos_of(g.lo[0], g.R, cix, a0.x), py = pos_of(g.lo[1], g.R, ciy, a0.y),
-               pz = DIM == 3 ? pos_of(g.lo[2], g.R, ciz, a0.z) : 0.0;
   RowWalker w;
-  walker_init<DIM>(w, g, px, py, pz);
-  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf, px, py, pz, P.two_h);
+  walker_init_cell<DIM>(w, g, cix, ciy, ciz, a0.x, a0.y, a0.z, P.two_h);
+  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf);
 
   const float two_h2 = (float)P.two_h2;
   const double Rd = g.R;
   const double oxi = a0.x, oyi = a0.y, ozi = a0.z;
   const float inv_h = (float)P.inv_h, kfac = (float)P.kfac, alpha = (float)P.alpha, w0inv = (float)P.w0inv;
   const float c0f = (float)P.c0, pstR = (float)P.pst_R;
-  const bool pst4 = P.pst_n == 4.0;
 
   PairSums S;
   sums_zero(S);
@@ -283,19 +280,20 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
         const uint32_t j = j0 + k;
         const float dx = b[k].x - axa.x, dy = b[k].y - axa.y, dz = DIM == 3 ? b[k].z - axa.z : 0.f;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        if ((uint32_t)k < rem && j != i && r2 <= two_h2) {
-          list[cnt][tid] = j;
-          ++cnt;
-        }
+        // branch-free append: the slot is written either way and kept only
+        // if taken (cnt <= kList - batch on entry keeps every write in range)
+        const bool take = (uint32_t)k < rem && j != i && r2 <= two_h2;
+        list[cnt][tid] = j;
+        cnt += take ? 1 : 0;
       }
       const uint32_t took = rem < (uint32_t)kMBatch ? rem : (uint32_t)kMBatch;
       S.ntest += took;
       w.cur = j0 + took;
-      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf, px, py, pz, P.two_h);
+      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf);
     }
     // FP32 partial sums of this chunk (flushed into the FP64 totals below)
     float gsf[3] = {0.f, 0.f, 0.f}, Nf[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, Pf[3] = {0.f, 0.f, 0.f}, Df = 0.f;
-    float S0f = 0.f, m1f[3] = {0.f, 0.f, 0.f}, m2f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float S0f = 0.f;
     for (int k = 0; k < cnt; ++k) {
       const uint32_t j = list[k][tid];
       const float4 b0 = rec.r0[j], b1 = rec.r1[j];
@@ -357,25 +355,13 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
       Df += wv * (float)dph;
       const float W = alpha * t2 * t2 * (2.0f * q + 1.0f);
       const float wr = W * w0inv;
-      const float wrn = pst4 ? (wr * wr) * (wr * wr) : powf(wr, (float)P.pst_n);
+      const float wrn = PST4 ? (wr * wr) * (wr * wr) : powf(wr, (float)P.pst_n);
       const float pw = 1.0f + pstR * wrn;
       Pf[0] += pw * gx;
       Pf[1] += pw * gy;
       if (DIM == 3) Pf[2] += pw * gz;
       if (FEAT) {
-        const float WV = W * b1.w;
-        S0f += WV;
-        m1f[0] += WV * rx;
-        m1f[1] += WV * ry;
-        m2f[0] += WV * rx * rx;
-        m2f[1] += WV * ry * ry;
-        m2f[3] += WV * rx * ry;
-        if (DIM == 3) {
-          m1f[2] += WV * rz;
-          m2f[2] += WV * rz * rz;
-          m2f[4] += WV * rx * rz;
-          m2f[5] += WV * ry * rz;
-        }
+        S0f += W * b1.w;
         S.qmin = fmin(S.qmin, (double)q);
         S.ndum += (j >= nf) ? 1u : 0u;
       }
@@ -384,13 +370,9 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     for (int a = 0; a < 3; ++a) {
       S.gs[a] += gsf[a];
       S.Ps[a] += Pf[a];
-      S.m1[a] += m1f[a];
     }
 #pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      S.N[a] += Nf[a];
-      S.m2[a] += m2f[a];
-    }
+    for (int a = 0; a < 6; ++a) S.N[a] += Nf[a];
     S.Ds += Df;
     S.S0 += S0f;
     S.nnb += cnt;
@@ -399,21 +381,31 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
 }
 
+template <int DIM, bool FEAT>
+void launch_pair_mixed_inst(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
+                            const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
+                            hipStream_t s) {
+  dim3 gr(grid_for(nf)), bl(kBlock);
+  if (P.pst_n == 4.0)
+    hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+  else
+    hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+}
+
 hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                              const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
                              bool features, hipStream_t s) {
   if (nf == 0) return hipSuccess;
-  dim3 gr(grid_for(nf)), bl(kBlock);
   if (P.dim == 2) {
     if (features)
-      hipLaunchKernelGGL((k_pair_mixed<2, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+      launch_pair_mixed_inst<2, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, s);
     else
-      hipLaunchKernelGGL((k_pair_mixed<2, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+      launch_pair_mixed_inst<2, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, s);
   } else {
     if (features)
-      hipLaunchKernelGGL((k_pair_mixed<3, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+      launch_pair_mixed_inst<3, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, s);
     else
-      hipLaunchKernelGGL((k_pair_mixed<3, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+      launch_pair_mixed_inst<3, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, s);
   }
   return hipGetLastError();
 }
@@ -437,9 +429,9 @@ __global__ void __launch_bounds__(256) k_scan_mixed(Phys P, Grid g, MixedRec rec
     const double n0 = out.nrm[0][i], n1 = out.nrm[1][i], n2 = DIM == 3 ? out.nrm[2][i] : 0.0;
     const double T0 = px + P.h * n0, T1 = py + P.h * n1, T2 = DIM == 3 ? pz + P.h * n2 : 0.0;
     RowWalker w;
-    walker_init<DIM>(w, g, px, py, pz);
+    walker_init_cell<DIM>(w, g, cell_x(ci), cell_y(ci), cell_z(ci), a.x, a.y, a.z, P.two_h);
     bool covered = false;
-    while (!covered && walker_next<DIM>(w, g, cs_f, cs_d, nf, px, py, pz, P.two_h)) {
+    while (!covered && walker_next<DIM>(w, g, cs_f, cs_d, nf)) {
       for (uint32_t j = w.cur; j < w.end && !covered; ++j) {
         if (j == i) continue;
         const float4 b = rec.r0[j];

@@ -31,19 +31,20 @@ namespace wb {
 #ifndef WB_PAIR_BATCH
 #define WB_PAIR_BATCH 4
 #endif
-#ifndef WB_PAIR_PREFETCH
-#define WB_PAIR_PREFETCH 0
+#ifndef WB_PAIR_UNROLL
+#define WB_PAIR_UNROLL 1
 #endif
+// waves per SIMD the register allocation targets: the plain instance fits 4
+// without spills, the one with classifier features 3
 #ifndef WB_PAIR_WAVES
-#define WB_PAIR_WAVES 3
+#define WB_PAIR_WAVES 4
+#endif
+#ifndef WB_PAIR_WAVES_FEAT
+#define WB_PAIR_WAVES_FEAT 3
 #endif
 constexpr int kList = WB_PAIR_LIST;    // LDS list entries per lane
 constexpr int kBatch = WB_PAIR_BATCH;  // candidates fetched per phase-1 iteration
-#if WB_PAIR_WAVES > 0
-#define WB_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(WB_PAIR_WAVES)))
-#else
-#define WB_PAIR_ATTR
-#endif
+#define WB_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_PAIR_WAVES_FEAT : WB_PAIR_WAVES)))
 
 // ------------------------------------------------------------------ mirror
 
@@ -58,13 +59,13 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
   if (k >= nd) return;
   double xd = d.x[0][k], yd = d.x[1][k], zd = DIM == 3 ? d.x[2][k] : 0.0;
   RowWalker w;
-  walker_init<DIM>(w, g, xd, yd, zd);
+  walker_init<DIM>(w, g, xd, yd, zd, P.two_h);
   int64_t best = -1;
   uint32_t best_id = 0;
   double best_r2 = 0.0;
   // fluid runs only (the dummy cell-start array is not needed: pass cs_f twice
   // and stop at the first dummy run)
-  while (walker_next<DIM>(w, g, cs_f, cs_f, nf, xd, yd, zd, P.two_h)) {
+  while (walker_next<DIM>(w, g, cs_f, cs_f, nf)) {
     if (w.cur >= nf) continue;
     for (uint32_t j = w.cur; j < w.end; ++j) {
       double4 b = rec0[j];
@@ -102,7 +103,9 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
 
 // ----------------------------------------------------------- pair pass
 
-template <int DIM, bool FEAT>
+// PST4: the shifting exponent is 4 (the paper's value), evaluated as two
+// squarings; otherwise pow().
+template <int DIM, bool FEAT, bool PST4>
 __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
                                                   const double4 *__restrict__ rec1, const uint32_t *__restrict__ cs_f,
                                                   const uint32_t *__restrict__ cs_d, uint32_t nf, Scalars *sc,
@@ -118,12 +121,11 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
     a1 = rec1[i];
   }
   RowWalker w;
-  walker_init<DIM>(w, g, a0.x, a0.y, a0.z);
-  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf, a0.x, a0.y, a0.z, P.two_h);
+  walker_init<DIM>(w, g, a0.x, a0.y, a0.z, P.two_h);
+  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf);
 
   PairSums S;
   sums_zero(S);
-  const bool pst4 = P.pst_n == 4.0;
 
   for (;;) {
     // phase 1: compact in-range candidates into this lane's LDS column.  Runs
@@ -141,38 +143,19 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
       for (int k = 0; k < kBatch; ++k) {
         const uint32_t j = j0 + k;
         const double r2 = dist2_exact<DIM>(b[k].x - a0.x, b[k].y - a0.y, b[k].z - a0.z);
-        if ((uint32_t)k < rem && j != i && r2 <= P.two_h2) {
-          list[cnt][tid] = j;
-          ++cnt;
-        }
+        // branch-free append: the slot is written either way and kept only
+        // if taken (cnt <= kList - batch on entry keeps every write in range)
+        const bool take = (uint32_t)k < rem && j != i && r2 <= P.two_h2;
+        list[cnt][tid] = j;
+        cnt += take ? 1 : 0;
       }
       const uint32_t took = rem < (uint32_t)kBatch ? rem : (uint32_t)kBatch;
       S.ntest += took;
       w.cur = j0 + took;
-      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf, a0.x, a0.y, a0.z, P.two_h);
+      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf);
     }
-    // phase 2: dense pair body over the list, next records prefetched
-    double4 n0 = make_double4(0.0, 0.0, 0.0, 0.0), n1 = n0;
-    uint32_t jn = 0;
-    if (cnt > 0) {
-      jn = list[0][tid];
-      n0 = rec0[jn];
-      n1 = rec1[jn];
-    }
-    for (int k = 0; k < cnt; ++k) {
-      const uint32_t j = jn;
-      double4 b0 = n0, b1 = n1;
-      if (!WB_PAIR_PREFETCH && k > 0) {
-        b0 = rec0[j];
-        b1 = rec1[j];
-      }
-      if (WB_PAIR_PREFETCH && k + 1 < cnt) {
-        jn = list[k + 1][tid];
-        n0 = rec0[jn];
-        n1 = rec1[jn];
-      } else if (!WB_PAIR_PREFETCH && k + 1 < cnt) {
-        jn = list[k + 1][tid];
-      }
+    // phase 2: dense pair body over the list
+    auto body = [&](const double4 &b0, const double4 &b1, const uint32_t j) {
       const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
       const double r2 = dist2_exact<DIM>(rx, ry, rz);
       S.coincident |= (r2 == 0.0);
@@ -222,29 +205,41 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
       S.Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
       const double W = P.alpha * t2 * t2 * (2.0 * q + 1.0);
       const double wr = W * P.w0inv;
-      const double wrn = pst4 ? (wr * wr) * (wr * wr) : pow(wr, P.pst_n);
+      const double wrn = PST4 ? (wr * wr) * (wr * wr) : pow(wr, P.pst_n);
       const double pw = 1.0 + P.pst_R * wrn;
       S.Ps[0] += pw * gx;
       S.Ps[1] += pw * gy;
       if (DIM == 3) S.Ps[2] += pw * gz;
       if (FEAT) {
-        const double WV = W * b1.w;
-        S.S0 += WV;
-        S.m1[0] += WV * rx;
-        S.m1[1] += WV * ry;
-        S.m2[0] += WV * rx * rx;
-        S.m2[1] += WV * ry * ry;
-        S.m2[3] += WV * rx * ry;
-        if (DIM == 3) {
-          S.m1[2] += WV * rz;
-          S.m2[2] += WV * rz * rz;
-          S.m2[4] += WV * rx * rz;
-          S.m2[5] += WV * ry * rz;
-        }
+        S.S0 += W * b1.w;
         S.qmin = fmin(S.qmin, q);
         S.ndum += (j >= nf) ? 1u : 0u;
       }
+    };
+#if WB_PAIR_UNROLL > 1
+    // two neighbours per iteration: both records in flight at once; the list
+    // entries of the next two are read one iteration ahead
+    int k = 0;
+    uint32_t ja = cnt > 0 ? list[0][tid] : 0u, jb = cnt > 1 ? list[1][tid] : 0u;
+    for (; k + 1 < cnt; k += 2) {
+      const double4 pa0 = rec0[ja], pa1 = rec1[ja], pb0 = rec0[jb], pb1 = rec1[jb];
+      const uint32_t ca = ja, cb = jb;
+      if (k + 2 < cnt) ja = list[k + 2][tid];
+      if (k + 3 < cnt) jb = list[k + 3][tid];
+      body(pa0, pa1, ca);
+      body(pb0, pb1, cb);
     }
+    if (k < cnt) body(rec0[ja], rec1[ja], ja);
+#else
+    // one neighbour per iteration, the next list entry read one iteration ahead
+    uint32_t jn = cnt > 0 ? list[0][tid] : 0u;
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t j = jn;
+      const double4 b0 = rec0[j], b1 = rec1[j];
+      if (k + 1 < cnt) jn = list[k + 1][tid];
+      body(b0, b1, j);
+    }
+#endif
     S.nnb += cnt;
     if (done) break;
   }
@@ -252,21 +247,31 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
 }
 
+template <int DIM, bool FEAT>
+void launch_pair_f64_inst(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
+                          const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
+                          uint32_t *cand, hipStream_t s) {
+  dim3 gr(grid_for(nf)), bl(kBlock);
+  if (P.pst_n == 4.0)
+    hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+  else
+    hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+}
+
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
                            uint32_t *cand, bool features, hipStream_t s) {
   if (nf == 0) return hipSuccess;
-  dim3 gr(grid_for(nf)), bl(kBlock);
   if (P.dim == 2) {
     if (features)
-      hipLaunchKernelGGL((k_pair_f64<2, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+      launch_pair_f64_inst<2, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
     else
-      hipLaunchKernelGGL((k_pair_f64<2, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+      launch_pair_f64_inst<2, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
   } else {
     if (features)
-      hipLaunchKernelGGL((k_pair_f64<3, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+      launch_pair_f64_inst<3, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
     else
-      hipLaunchKernelGGL((k_pair_f64<3, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+      launch_pair_f64_inst<3, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
   }
   return hipGetLastError();
 }
@@ -292,9 +297,9 @@ __global__ void __launch_bounds__(256) k_scan_f64(Phys P, Grid g, const double4 
     const double n0 = out.nrm[0][i], n1 = out.nrm[1][i], n2 = DIM == 3 ? out.nrm[2][i] : 0.0;
     const double T0 = a.x + P.h * n0, T1 = a.y + P.h * n1, T2 = DIM == 3 ? a.z + P.h * n2 : 0.0;
     RowWalker w;
-    walker_init<DIM>(w, g, a.x, a.y, a.z);
+    walker_init<DIM>(w, g, a.x, a.y, a.z, P.two_h);
     bool covered = false;
-    while (!covered && walker_next<DIM>(w, g, cs_f, cs_d, nf, a.x, a.y, a.z, P.two_h)) {
+    while (!covered && walker_next<DIM>(w, g, cs_f, cs_d, nf)) {
       for (uint32_t j = w.cur; j < w.end && !covered; ++j) {
         if (j == i) continue;
         const double4 b = rec0[j];
@@ -352,9 +357,9 @@ __global__ void __launch_bounds__(256) k_nb_count(Phys P, Grid g, const double4 
   if (i >= nf) return;
   double4 a = rec0[i];
   RowWalker w;
-  walker_init<DIM>(w, g, a.x, a.y, a.z);
+  walker_init<DIM>(w, g, a.x, a.y, a.z, P.two_h);
   uint32_t c = 0;
-  while (walker_next<DIM>(w, g, cs_f, cs_d, nf, a.x, a.y, a.z, P.two_h)) {
+  while (walker_next<DIM>(w, g, cs_f, cs_d, nf)) {
     for (uint32_t j = w.cur; j < w.end; ++j) {
       if (j == i) continue;
       double4 b = rec0[j];
@@ -376,9 +381,9 @@ __global__ void __launch_bounds__(256) k_nb_fill(Phys P, Grid g, const double4 *
   if (row < r0 || row >= r1) return;
   double4 a = rec0[i];
   RowWalker w;
-  walker_init<DIM>(w, g, a.x, a.y, a.z);
+  walker_init<DIM>(w, g, a.x, a.y, a.z, P.two_h);
   uint32_t o = off[row];
-  while (walker_next<DIM>(w, g, cs_f, cs_d, nf, a.x, a.y, a.z, P.two_h)) {
+  while (walker_next<DIM>(w, g, cs_f, cs_d, nf)) {
     for (uint32_t j = w.cur; j < w.end; ++j) {
       if (j == i) continue;
       double4 b = rec0[j];

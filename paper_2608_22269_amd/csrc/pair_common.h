@@ -28,20 +28,21 @@ __device__ __forceinline__ void wave_count(uint32_t *counter, bool pred) {
     atomicAdd(counter, (uint32_t)__popcll(mask));
 }
 
-// Neighbour sums of one particle (FP64).  L, N and m2 are symmetric and
-// packed as (xx, yy, zz, xy, xz, yz); N holds N_ab + N_ba off the diagonal.
+// Neighbour sums of one particle (FP64).  L and N are symmetric and packed
+// as (xx, yy, zz, xy, xz, yz); N holds N_ab + N_ba off the diagonal.  S0,
+// qmin and ndum only feed the classifier features.
 struct PairSums {
   double L[6], gs[3], SR[3], SC[3], Ps[3], N[6], Ds;
-  double S0, m1[3], m2[6], qmin;
+  double S0, qmin;
   uint32_t nnb, ndum, ntest;
   bool coincident;
 };
 
 __device__ __forceinline__ void sums_zero(PairSums &S) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) S.L[k] = S.N[k] = S.m2[k] = 0.0;
+  for (int k = 0; k < 6; ++k) S.L[k] = S.N[k] = 0.0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) S.gs[k] = S.SR[k] = S.SC[k] = S.Ps[k] = S.m1[k] = 0.0;
+  for (int k = 0; k < 3; ++k) S.gs[k] = S.SR[k] = S.SC[k] = S.Ps[k] = 0.0;
   S.Ds = S.S0 = 0.0;
   S.qmin = 2.0;
   S.nnb = S.ndum = S.ntest = 0;
@@ -149,20 +150,23 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
     out.nnb[i] = S.nnb;
     if (S.coincident) atomicOr(&sc->err, kErrNonFinite);
     if (FEAT) {
+      // eigenvalues, det L, kernel sum, neighbour count, |g| h, moments of g
+      // and L along the normal and across it, |L^-T g| h, n against gravity,
+      // dummy fraction, closest-neighbour q, |P| h
       float *f = out.feat + (size_t)i * kNFeat;
       const double S0s = S.S0 + P.wself * Vi;
-      double m1n = 0, m1sq = 0, nm2n = 0, trm2 = 0, gn2 = 0, pn2 = 0, ngr = 0, gg2 = 0;
-      const double M2[3][3] = {{S.m2[0], S.m2[3], S.m2[4]}, {S.m2[3], S.m2[1], S.m2[5]}, {S.m2[4], S.m2[5], S.m2[2]}};
+      const double Lm[3][3] = {{S.L[0], S.L[3], S.L[4]}, {S.L[3], S.L[1], S.L[5]}, {S.L[4], S.L[5], S.L[2]}};
+      double ngs = 0, gn2 = 0, nLn = 0, trL = 0, pn2 = 0, ngr = 0, gg2 = 0;
       for (int a = 0; a < DIM; ++a) {
-        m1n += nrm[a] * S.m1[a];
-        m1sq += S.m1[a] * S.m1[a];
-        trm2 += M2[a][a];
+        ngs += nrm[a] * S.gs[a];
         gn2 += S.gs[a] * S.gs[a];
+        trL += Lm[a][a];
         pn2 += S.Ps[a] * S.Ps[a];
         ngr += nrm[a] * G[a];
         gg2 += G[a] * G[a];
-        for (int b = 0; b < DIM; ++b) nm2n += nrm[a] * M2[a][b] * nrm[b];
+        for (int b = 0; b < DIM; ++b) nLn += nrm[a] * Lm[a][b] * nrm[b];
       }
+      const double gt2 = gn2 - ngs * ngs;
       double detL = DIM == 2 ? S.L[0] * S.L[1] - S.L[3] * S.L[3]
                              : S.L[0] * (S.L[1] * S.L[2] - S.L[5] * S.L[5]) - S.L[3] * (S.L[3] * S.L[2] - S.L[5] * S.L[4]) +
                                    S.L[4] * (S.L[3] * S.L[5] - S.L[1] * S.L[4]);
@@ -173,10 +177,10 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
       f[4] = (float)S0s;
       f[5] = (float)S.nnb;
       f[6] = (float)(sqrt(gn2) * P.h);
-      f[7] = (float)(S0s > 0.0 ? m1n / (S0s * P.h) : 0.0);
-      f[8] = (float)(S0s > 0.0 ? sqrt(m1sq) / (S0s * P.h) : 0.0);
-      f[9] = (float)(S0s > 0.0 ? nm2n / (S0s * P.h * P.h) : 0.0);
-      f[10] = (float)(S0s > 0.0 ? (trm2 - nm2n) / (S0s * P.h * P.h) : 0.0);
+      f[7] = (float)(ngs * P.h);
+      f[8] = (float)(sqrt(gt2 > 0.0 ? gt2 : 0.0) * P.h);
+      f[9] = (float)nLn;
+      f[10] = (float)(trL - nLn);
       f[11] = (float)(nn * P.h);
       f[12] = (float)(gg2 > 0.0 ? ngr / sqrt(gg2) : 0.0);
       f[13] = (float)(S.nnb > 0 ? (double)S.ndum / (double)S.nnb : 0.0);

@@ -157,7 +157,7 @@ def test_features_parity(Sim):
     rf = ref["feat"][f]
     defined = rf[:, 11] > 1e-6
     for k in range(16):
-        rows = defined if k in (7, 9, 10, 12) else np.ones(len(rf), bool)
+        rows = defined if k in (7, 8, 9, 10, 12) else np.ones(len(rf), bool)
         scale = max(np.abs(rf[rows, k]).max(), 1e-6)
         assert np.abs(ft[rows, k] - rf[rows, k]).max() <= 2e-6 * scale, k
 
