@@ -156,6 +156,9 @@ void derive(const sph_params *p, Phys &P, Grid &g) {
   P.kfac = 5.0 * P.alpha / (p->h * p->h);
   P.w0inv = 1.0 / wendland(p->dim, p->h, p->dx / p->h);
   P.wself = wendland(p->dim, p->h, 0.0);
+  P.m_half_inv_h = -0.5 / p->h;
+  P.two_inv_h = 2.0 / p->h;
+  P.aw0 = P.alpha * P.w0inv;
   P.delta = p->delta;
   P.pst_R = p->pst_R;
   P.pst_n = p->pst_n;
@@ -253,10 +256,10 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
     }
     c->mrec.r0 = cv.take<float4>(nf + nd);
     c->mrec.r1 = cv.take<float4>(nf + nd);
-    c->mrec.xa = cv.take<float4>(nf + nd);
+    c->mrec.xa = cv.take<float4>(nf + nd + kRecPad);
     c->mrec.phi = f64(nf + nd);
   }
-  c->rec0 = mixed ? nullptr : cv.take<double4>(nf + nd);
+  c->rec0 = mixed ? nullptr : cv.take<double4>(nf + nd + kRecPad);
   c->rec1 = mixed ? nullptr : cv.take<double4>(nf + nd);
   c->cs_f = cv.take<uint32_t>(c->g.nkey + 1);
   c->cs_d = cv.take<uint32_t>(c->g.nkey + 1);
@@ -652,6 +655,12 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   } else if (e == hipSuccess) {
     e = launch_fill_u32(c->cs_d, 0u, c->g.nkey + 1, s);
   }
+  // padding records after the FP64 neighbour records (read by batched
+  // candidate loads, never used)
+  if (e == hipSuccess && !c->mixed)
+    e = launch_fill_u32(reinterpret_cast<uint32_t *>(c->rec0 + c->n), 0u, (int64_t)kRecPad * 8, s);
+  if (e == hipSuccess && c->mixed)
+    e = launch_fill_u32(reinterpret_cast<uint32_t *>(c->mrec.xa + c->n), 0u, (int64_t)kRecPad * 4, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete c;

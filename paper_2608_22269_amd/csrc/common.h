@@ -14,6 +14,9 @@
 namespace wb {
 
 constexpr int kBlock = 256;   // threads per block for streaming kernels
+// padding records after the FP64 neighbour records: candidate loads are
+// issued in batches and may run this many records past a run's end
+constexpr int kRecPad = 8;
 constexpr int kNFeat = 16;    // classifier features per particle
 constexpr int kMaxReach = 3;  // cells searched each side: ceil(2h / R) <= 3
 
@@ -93,6 +96,9 @@ struct Phys {
   double kfac;     // 5 alpha / h^2:  grad_i W_ij = kfac t^3 (x_j - x_i)
   double w0inv;    // 1 / W(dx / h)
   double wself;    // W(0)
+  double m_half_inv_h;  // -1 / (2h):  t = 1 - q/2 = 1 + s m_half_inv_h
+  double two_inv_h;     // 2 / h:      2q + 1 = 1 + s two_inv_h
+  double aw0;           // alpha / W(dx):  W / W(dx) = aw0 t^4 (2q + 1)
   double delta, pst_R, pst_n;
   double lambda_tic, lambda_lo, lambda_hi, lambda_sing;
   double grav[3], famp[3], fomega;
@@ -171,6 +177,16 @@ __device__ __forceinline__ double dist2_exact(double rx, double ry, double rz) {
   s = s + ry * ry;
   if (DIM == 3) s = s + rz * rz;
   return s;
+}
+
+// 1 / sqrt(x) for a finite, normal x > 0: the hardware estimate (relative
+// error below 2^-22) refined by one third-order step, y (1 + e/2 + 3e^2/8)
+// with e = 1 - x y^2, which leaves an error of order e^3 (below FP64
+// rounding).  Zero, infinite and denormal arguments are not handled.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 // Closed-form eigenvalues of a symmetric 2x2 / 3x3 matrix (Sec. 3),
@@ -366,7 +382,7 @@ __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const u
     ez = fmaxf(0.0f, ez - kWalkSlack);
     const float rem = w.rr2 - ey * ey - ez * ez;
     if (rem < 0.0f) continue;
-    const float reach = sqrtf(rem) + kWalkSlack;
+    const float reach = __builtin_amdgcn_sqrtf(rem) + kWalkSlack;  // hardware sqrt (~1 ulp), covered by the slack
     int x0 = w.cx + (int)floorf(w.ux - reach);
     int x1 = w.cx + (int)floorf(w.ux + reach);
     x0 = max(x0, max(w.cx - g.reach, 0));

@@ -23,6 +23,7 @@
 // and velocity, then the offset is brought back into [0, R) by moving cells.
 #include "mixed.h"
 #include "pair_common.h"
+#include "coop.h"
 
 namespace wb {
 
@@ -34,6 +35,9 @@ namespace wb {
 #define WB_MIXED_WAVES_FEAT 3
 #endif
 #define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_MIXED_WAVES_FEAT : WB_MIXED_WAVES)))
+#ifndef WB_MIXED_COOP
+#define WB_MIXED_COOP 0
+#endif
 constexpr int kMList = 32;
 constexpr int kMBatch = 4;
 
@@ -253,44 +257,18 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
   }
   const uint32_t ci = __float_as_uint(a0.w);
   const int cix = cell_x(ci), ciy = cell_y(ci), ciz = cell_z(ci);
-  RowWalker w;
-  walker_init_cell<DIM>(w, g, cix, ciy, ciz, a0.x, a0.y, a0.z, P.two_h);
-  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf);
 
   const float two_h2 = (float)P.two_h2;
   const double Rd = g.R;
   const double oxi = a0.x, oyi = a0.y, ozi = a0.z;
   const float inv_h = (float)P.inv_h, kfac = (float)P.kfac, alpha = (float)P.alpha, w0inv = (float)P.w0inv;
-  const float c0f = (float)P.c0, pstR = (float)P.pst_R;
+  const float c0f = (float)P.c0;
 
   PairSums S;
   sums_zero(S);
 
-  for (;;) {
-    int cnt = 0;
-    while (!done && cnt <= kMList - kMBatch) {
-      const uint32_t j0 = w.cur;
-      const uint32_t rem = w.end - j0;
-      const uint32_t last = w.end - 1;
-      float4 b[kMBatch];
-#pragma unroll
-      for (int k = 0; k < kMBatch; ++k) b[k] = rec.xa[min(j0 + (uint32_t)k, last)];
-#pragma unroll
-      for (int k = 0; k < kMBatch; ++k) {
-        const uint32_t j = j0 + k;
-        const float dx = b[k].x - axa.x, dy = b[k].y - axa.y, dz = DIM == 3 ? b[k].z - axa.z : 0.f;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        // branch-free append: the slot is written either way and kept only
-        // if taken (cnt <= kList - batch on entry keeps every write in range)
-        const bool take = (uint32_t)k < rem && j != i && r2 <= two_h2;
-        list[cnt][tid] = j;
-        cnt += take ? 1 : 0;
-      }
-      const uint32_t took = rem < (uint32_t)kMBatch ? rem : (uint32_t)kMBatch;
-      S.ntest += took;
-      w.cur = j0 + took;
-      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf);
-    }
+  // dense pair body over the first cnt entries of this lane's list
+  auto run_list = [&](int cnt) {
     // FP32 partial sums of this chunk (flushed into the FP64 totals below)
     float gsf[3] = {0.f, 0.f, 0.f}, Nf[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, Pf[3] = {0.f, 0.f, 0.f}, Df = 0.f;
     float S0f = 0.f;
@@ -356,10 +334,10 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
       const float W = alpha * t2 * t2 * (2.0f * q + 1.0f);
       const float wr = W * w0inv;
       const float wrn = PST4 ? (wr * wr) * (wr * wr) : powf(wr, (float)P.pst_n);
-      const float pw = 1.0f + pstR * wrn;
-      Pf[0] += pw * gx;
-      Pf[1] += pw * gy;
-      if (DIM == 3) Pf[2] += pw * gz;
+      // (W / W(dx))^n grad W V; the epilogue adds grad W V times 1 / R
+      Pf[0] += wrn * gx;
+      Pf[1] += wrn * gy;
+      if (DIM == 3) Pf[2] += wrn * gz;
       if (FEAT) {
         S0f += W * b1.w;
         S.qmin = fmin(S.qmin, (double)q);
@@ -376,8 +354,66 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     S.Ds += Df;
     S.S0 += S0f;
     S.nnb += cnt;
+  };
+
+#if WB_MIXED_COOP
+  // candidate search with the rows walked in lockstep by the wave
+  CellPos cp;
+  cp.cx = cix;
+  cp.cy = ciy;
+  cp.cz = DIM == 3 ? ciz : 0;
+  cp.ux = a0.x * (float)g.invR;
+  cp.uy = a0.y * (float)g.invR;
+  cp.uz = DIM == 3 ? a0.z * (float)g.invR : 0.0f;
+  auto load = [&](uint32_t j) { return rec.xa[j]; };
+  auto near = [&](const float4 &b, uint32_t j) {
+    const float dx = b.x - axa.x, dy = b.y - axa.y, dz = DIM == 3 ? b.z - axa.z : 0.f;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    return j != i && r2 <= two_h2;
+  };
+  int cnt = 0;
+  CoopWalk cw;
+  coop_init(cw, g, active, (float)P.two_h, DIM);
+  for (;;) {
+    const bool fin =
+        coop_fill<DIM, kMList, kMBatch>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, load, near);
+    run_list(cnt);
+    cnt = 0;
+    if (fin) break;
+  }
+#else
+  RowWalker w;
+  walker_init_cell<DIM>(w, g, cix, ciy, ciz, a0.x, a0.y, a0.z, P.two_h);
+  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf);
+  for (;;) {
+    int cnt = 0;
+    while (!done && cnt <= kMList - kMBatch) {
+      const uint32_t j0 = w.cur;
+      const uint32_t rem = w.end - j0;
+      const uint32_t last = w.end - 1;
+      float4 b[kMBatch];
+#pragma unroll
+      for (int k = 0; k < kMBatch; ++k) b[k] = rec.xa[min(j0 + (uint32_t)k, last)];
+#pragma unroll
+      for (int k = 0; k < kMBatch; ++k) {
+        const uint32_t j = j0 + k;
+        const float dx = b[k].x - axa.x, dy = b[k].y - axa.y, dz = DIM == 3 ? b[k].z - axa.z : 0.f;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        // branch-free append: the slot is written either way and kept only
+        // if taken (cnt <= kList - batch on entry keeps every write in range)
+        const bool take = (uint32_t)k < rem && j != i && r2 <= two_h2;
+        list[cnt][tid] = j;
+        cnt += take ? 1 : 0;
+      }
+      const uint32_t took = rem < (uint32_t)kMBatch ? rem : (uint32_t)kMBatch;
+      S.ntest += took;
+      w.cur = j0 + took;
+      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf);
+    }
+    run_list(cnt);
     if (done) break;
   }
+#endif
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
 }
 

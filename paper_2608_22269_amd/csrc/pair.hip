@@ -10,16 +10,17 @@
 //   - the scan-region pass over free-surface candidates;
 //   - neighbour-list export for parity checks.
 //
-// Work mapping.  One lane per fluid particle, particles in HashID order.  A
-// lane first walks the cell rows of Algorithm 1 and compacts the in-range
-// candidates into its own column of an LDS list (32 entries), then runs the
-// dense pair body over that list; it alternates until its walk ends.  Lanes of
-// one wave belong to the same or neighbouring cells, so their walks touch the
-// same records in lockstep (coalesced loads) and the expensive body runs on
-// real neighbours only instead of every candidate of the 3^d cells.
+// Work mapping.  One lane per fluid particle, particles in storage (sort key)
+// order.  The wave walks the cell rows of Algorithm 1 in lockstep; each lane
+// compacts its in-range candidates into its own column of an LDS list (32
+// entries), and whenever a list may overflow the wave runs the dense pair body
+// over the lists.  Lanes of one wave belong to the same or neighbouring cells,
+// so their candidate loads touch the same records, and the expensive body runs
+// on real neighbours only instead of every candidate of the 3^d cells.
 #include "common.h"
 #include "kernels.h"
 #include "pair_common.h"
+#include "coop.h"
 
 namespace wb {
 
@@ -43,7 +44,8 @@ namespace wb {
 #define WB_PAIR_WAVES_FEAT 3
 #endif
 constexpr int kList = WB_PAIR_LIST;    // LDS list entries per lane
-constexpr int kBatch = WB_PAIR_BATCH;  // candidates fetched per phase-1 iteration
+constexpr int kBatch = WB_PAIR_BATCH;  // candidates fetched per search iteration
+static_assert(kBatch <= kRecPad, "batched candidate loads run at most kRecPad records past a run");
 #define WB_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_PAIR_WAVES_FEAT : WB_PAIR_WAVES)))
 
 // ------------------------------------------------------------------ mirror
@@ -120,102 +122,75 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
     a0 = rec0[i];
     a1 = rec1[i];
   }
-  RowWalker w;
-  walker_init<DIM>(w, g, a0.x, a0.y, a0.z, P.two_h);
-  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf);
-
   PairSums S;
   sums_zero(S);
 
-  for (;;) {
-    // phase 1: compact in-range candidates into this lane's LDS column.  Runs
-    // are contiguous, so four candidates are fetched per iteration with
-    // independent loads (the last index is clamped, never read out of range).
-    int cnt = 0;
-    while (!done && cnt <= kList - kBatch) {
-      const uint32_t j0 = w.cur;
-      const uint32_t rem = w.end - j0;
-      const uint32_t last = w.end - 1;
-      double4 b[kBatch];
-#pragma unroll
-      for (int k = 0; k < kBatch; ++k) b[k] = rec0[min(j0 + (uint32_t)k, last)];
-#pragma unroll
-      for (int k = 0; k < kBatch; ++k) {
-        const uint32_t j = j0 + k;
-        const double r2 = dist2_exact<DIM>(b[k].x - a0.x, b[k].y - a0.y, b[k].z - a0.z);
-        // branch-free append: the slot is written either way and kept only
-        // if taken (cnt <= kList - batch on entry keeps every write in range)
-        const bool take = (uint32_t)k < rem && j != i && r2 <= P.two_h2;
-        list[cnt][tid] = j;
-        cnt += take ? 1 : 0;
-      }
-      const uint32_t took = rem < (uint32_t)kBatch ? rem : (uint32_t)kBatch;
-      S.ntest += took;
-      w.cur = j0 + took;
-      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf);
+  // dense pair body: every sum of Eq. (sph) for neighbour j
+  auto body = [&](const double4 &b0, const double4 &b1, const uint32_t j) {
+    const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
+    // membership was decided by the exact test; here |r| only feeds W and K
+    const double r2 = DIM == 3 ? fma(rx, rx, fma(ry, ry, rz * rz)) : fma(rx, rx, ry * ry);
+    S.coincident |= (r2 == 0.0);
+    const double is = rsqrt_pos(r2);
+    const double s = r2 * is;
+    const double t = fma(s, P.m_half_inv_h, 1.0);  // 1 - q/2
+    const double t2 = t * t, t3 = t2 * t;
+    const double wv = P.kfac * t3 * b1.w;  // |grad W| / |r| times V_j
+    const double gx = wv * rx, gy = wv * ry, gz = wv * rz;
+    // S.L = sum r (x) grad W V  (symmetric for the radial kernel)
+    S.L[0] += rx * gx;
+    S.L[1] += ry * gy;
+    S.L[3] += rx * gy;
+    if (DIM == 3) {
+      S.L[2] += rz * gz;
+      S.L[4] += rx * gz;
+      S.L[5] += ry * gz;
     }
-    // phase 2: dense pair body over the list
-    auto body = [&](const double4 &b0, const double4 &b1, const uint32_t j) {
-      const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
-      const double r2 = dist2_exact<DIM>(rx, ry, rz);
-      S.coincident |= (r2 == 0.0);
-      const double is = rsqrt(r2);
-      const double s = r2 * is;
-      const double q = s * P.inv_h;
-      const double t = 1.0 - 0.5 * q;
-      const double t2 = t * t, t3 = t2 * t;
-      const double wv = P.kfac * t3 * b1.w;  // |grad W| / |r| times V_j
-      const double gx = wv * rx, gy = wv * ry, gz = wv * rz;
-      // S.L = sum r (x) grad W V  (symmetric for the radial kernel)
-      S.L[0] += rx * gx;
-      S.L[1] += ry * gy;
-      S.L[3] += rx * gy;
-      if (DIM == 3) {
-        S.L[2] += rz * gz;
-        S.L[4] += rx * gz;
-        S.L[5] += ry * gz;
-      }
-      S.gs[0] += gx;
-      S.gs[1] += gy;
-      if (DIM == 3) S.gs[2] += gz;
-      const double dph = b0.w - a0.w;
-      const double dux = b1.x - a1.x, duy = b1.y - a1.y, duz = DIM == 3 ? b1.z - a1.z : 0.0;
-      const double dun = (dux * rx + duy * ry + duz * rz) * is;
-      const double c2 = dph - P.c0 * dun;  // 2 (phi*_ij - phi_i)
-      const double cs = b0.w + a0.w;        // conservative form
-      S.SR[0] += c2 * gx;
-      S.SR[1] += c2 * gy;
-      S.SC[0] += cs * gx;
-      S.SC[1] += cs * gy;
-      if (DIM == 3) {
-        S.SR[2] += c2 * gz;
-        S.SC[2] += cs * gz;
-      }
-      // symmetric part of N_ab = sum (U_j - U_i)_a (grad W V)_b: S.L^-1 is
-      // symmetric, so tr(S.L^-1 S.N) only sees S.N + S.N^T (packed xx yy zz xy xz yz,
-      // off-diagonals hold N_ab + N_ba)
-      S.N[0] += dux * gx;
-      S.N[1] += duy * gy;
-      S.N[3] += dux * gy + duy * gx;
-      if (DIM == 3) {
-        S.N[2] += duz * gz;
-        S.N[4] += dux * gz + duz * gx;
-        S.N[5] += duy * gz + duz * gy;
-      }
-      S.Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
-      const double W = P.alpha * t2 * t2 * (2.0 * q + 1.0);
-      const double wr = W * P.w0inv;
-      const double wrn = PST4 ? (wr * wr) * (wr * wr) : pow(wr, P.pst_n);
-      const double pw = 1.0 + P.pst_R * wrn;
-      S.Ps[0] += pw * gx;
-      S.Ps[1] += pw * gy;
-      if (DIM == 3) S.Ps[2] += pw * gz;
-      if (FEAT) {
-        S.S0 += W * b1.w;
-        S.qmin = fmin(S.qmin, q);
-        S.ndum += (j >= nf) ? 1u : 0u;
-      }
-    };
+    S.gs[0] += gx;
+    S.gs[1] += gy;
+    if (DIM == 3) S.gs[2] += gz;
+    const double dph = b0.w - a0.w;
+    const double dux = b1.x - a1.x, duy = b1.y - a1.y, duz = DIM == 3 ? b1.z - a1.z : 0.0;
+    const double dun = (dux * rx + duy * ry + duz * rz) * is;
+    const double c2 = dph - P.c0 * dun;  // 2 (phi*_ij - phi_i)
+    const double cs = b0.w + a0.w;        // conservative form
+    S.SR[0] += c2 * gx;
+    S.SR[1] += c2 * gy;
+    S.SC[0] += cs * gx;
+    S.SC[1] += cs * gy;
+    if (DIM == 3) {
+      S.SR[2] += c2 * gz;
+      S.SC[2] += cs * gz;
+    }
+    // symmetric part of N_ab = sum (U_j - U_i)_a (grad W V)_b: S.L^-1 is
+    // symmetric, so tr(S.L^-1 S.N) only sees S.N + S.N^T (packed xx yy zz xy xz yz,
+    // off-diagonals hold N_ab + N_ba)
+    S.N[0] += dux * gx;
+    S.N[1] += duy * gy;
+    S.N[3] += dux * gy + duy * gx;
+    if (DIM == 3) {
+      S.N[2] += duz * gz;
+      S.N[4] += dux * gz + duz * gx;
+      S.N[5] += duy * gz + duz * gy;
+    }
+    S.Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
+    // shifting: sum (W / W(dx))^n grad W V; the epilogue adds sum grad W V
+    // times 1 / R, i.e. P = sum [1 + R (W / W(dx))^n] grad W V
+    const double u = fma(s, P.two_inv_h, 1.0);  // 2q + 1
+    const double t4u = (t2 * t2) * u;
+    const double wr = P.aw0 * t4u;
+    const double wrn = PST4 ? (wr * wr) * (wr * wr) : pow(wr, P.pst_n);
+    S.Ps[0] += wrn * gx;
+    S.Ps[1] += wrn * gy;
+    if (DIM == 3) S.Ps[2] += wrn * gz;
+    if (FEAT) {
+      S.S0 += P.alpha * t4u * b1.w;
+      S.qmin = fmin(S.qmin, s * P.inv_h);
+      S.ndum += (j >= nf) ? 1u : 0u;
+    }
+  };
+  // consume the first cnt entries of this lane's list
+  auto run_list = [&](int cnt) {
 #if WB_PAIR_UNROLL > 1
     // two neighbours per iteration: both records in flight at once; the list
     // entries of the next two are read one iteration ahead
@@ -241,7 +216,24 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
     }
 #endif
     S.nnb += cnt;
-    if (done) break;
+  };
+
+  // candidate search with the rows walked in lockstep by the wave
+  const CellPos cp = cellpos_of<DIM>(g, a0.x, a0.y, a0.z);
+  int cnt = 0;
+  auto load = [&](uint32_t j) { return rec0[j]; };
+  auto near = [&](const double4 &b, uint32_t j) {
+    const double r2 = dist2_exact<DIM>(b.x - a0.x, b.y - a0.y, DIM == 3 ? b.z - a0.z : 0.0);
+    return j != i && r2 <= P.two_h2;
+  };
+  CoopWalk cw;
+  coop_init(cw, g, active, (float)P.two_h, DIM);
+  for (;;) {
+    const bool fin =
+        coop_fill<DIM, kList, kBatch>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, load, near);
+    run_list(cnt);
+    cnt = 0;
+    if (fin) break;
   }
 
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);

@@ -29,8 +29,9 @@ __device__ __forceinline__ void wave_count(uint32_t *counter, bool pred) {
 }
 
 // Neighbour sums of one particle (FP64).  L and N are symmetric and packed
-// as (xx, yy, zz, xy, xz, yz); N holds N_ab + N_ba off the diagonal.  S0,
-// qmin and ndum only feed the classifier features.
+// as (xx, yy, zz, xy, xz, yz); N holds N_ab + N_ba off the diagonal.  Ps is
+// sum (W / W(dx))^n grad W V (the shifting sum is gs + R Ps).  S0, qmin and
+// ndum only feed the classifier features.
 struct PairSums {
   double L[6], gs[3], SR[3], SC[3], Ps[3], N[6], Ds;
   double S0, qmin;
@@ -107,7 +108,8 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
   double dus[3] = {0.0, 0.0, 0.0};
   const double umax = sc->umax;
   if (flags & SPH_F_PST) {
-    double ds[3] = {-2.0 * P.h * umax * S.Ps[0], -2.0 * P.h * umax * S.Ps[1], -2.0 * P.h * umax * S.Ps[2]};
+    const double Pv[3] = {S.gs[0] + P.pst_R * S.Ps[0], S.gs[1] + P.pst_R * S.Ps[1], S.gs[2] + P.pst_R * S.Ps[2]};
+    double ds[3] = {-2.0 * P.h * umax * Pv[0], -2.0 * P.h * umax * Pv[1], -2.0 * P.h * umax * Pv[2]};
     double dn = sqrt(ds[0] * ds[0] + ds[1] * ds[1] + (DIM == 3 ? ds[2] * ds[2] : 0.0));
     if (dn > 0.0) {
       double mag = dn < 0.5 * umax ? dn : 0.5 * umax;
@@ -161,7 +163,8 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
         ngs += nrm[a] * S.gs[a];
         gn2 += S.gs[a] * S.gs[a];
         trL += Lm[a][a];
-        pn2 += S.Ps[a] * S.Ps[a];
+        const double pa = S.gs[a] + P.pst_R * S.Ps[a];
+        pn2 += pa * pa;
         ngr += nrm[a] * G[a];
         gg2 += G[a] * G[a];
         for (int b = 0; b < DIM; ++b) nLn += nrm[a] * Lm[a][b] * nrm[b];
