@@ -55,9 +55,9 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_key, launches_pairs):
-    """HBM bytes per launch from a committed counter summary, if it was taken
-    on the current kernel source (else None)."""
+def profile_summary(kernel_key):
+    """The committed counter summary of a kernel if it was taken on the
+    current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel_key}_pmc.json")
     if not os.path.exists(path):
         return None
@@ -65,7 +65,7 @@ def traffic_from_profiles(kernel_key, launches_pairs):
         d = json.load(f)
     if d.get("source_sha") != source_sha(d.get("sources", [])):
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
 def load_classifier():
@@ -307,15 +307,21 @@ def main():
 
     def roofline(res, key, kernel):
         src = PAIR_SOURCES[key]
-        return {
+        prof = profile_summary(f"{key}_slosh3d")
+        out = {
             "bound": "alu", "achieved": res["pair_pass_tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": res["pair_pass_tflops"] / PEAK_FP64_TFLOPS,
-            "traffic": traffic_from_profiles(f"{key}_slosh3d", None),
+            "traffic": prof["hbm_bytes_per_launch"] if prof else None,
             "kernel": kernel, "pair_pass_ms": res["pair_pass_ms"],
             "flop_per_launch": res["pairs_per_rhs"] * FLOP_PER_PAIR_3D
             + res["candidate_tests_per_rhs"] * FLOP_PER_TEST_3D,
             "source_sha": source_sha(src),
         }
+        if prof and "valu_issue_frac" in prof:
+            # the binding roof: VALU instruction issue (counted by the SQ)
+            out["valu_issue"] = {"frac": prof["valu_issue_frac"], "lane_instr_per_s": prof["valu_lane_instr_per_s"],
+                                 "peak": prof["valu_issue_peak"], "from": f"profiles/{key}_slosh3d_pmc.json"}
+        return out
 
     roof = roofline(head, "pair_f64", "k_pair_f64<3,false,true> (fused pair pass, FP64)")
     out = {

@@ -63,7 +63,9 @@ typedef int32_t sph_status;
 #define SPH_F_TIC 4u         /* conservative gradient where lambda_min < tic    */
 #define SPH_F_FS_PROJECT 8u  /* shifting keeps only its tangential part at FS   */
 #define SPH_F_CONT_UNCORR 16u /* uncorrected continuity where TIC is active     */
-#define SPH_F_FEATURES 32u   /* keep the 16 classifier features per particle    */
+#define SPH_F_FEATURES 32u   /* keep the 16 classifier features of every fluid  */
+                             /* particle (without it, the learned mode computes */
+                             /* them for free-surface candidates only)          */
 
 typedef struct sph_params {
     int32_t dim;        /* 2 or 3; gravity usually along the last axis          */

@@ -1,5 +1,5 @@
-// Candidate search of the FP64 pair pass with the rows walked in lockstep by
-// the wave (Algorithm 1).
+// Candidate search of the pair passes (FP64 and mixed) with the rows walked
+// in lockstep by the wave (Algorithm 1).
 //
 // The lanes of a wave hold consecutive particles in storage order, so they
 // sit in one x-row of cells or in two adjacent ones, and they visit the same
@@ -40,6 +40,9 @@ struct CellPos {
   float ux, uy, uz;
 };
 
+// A particle outside the grid (an error the hash reports) keeps a cell a few
+// cells outside it, so that its windows are empty and the group arithmetic
+// cannot overflow.
 template <int DIM>
 __device__ __forceinline__ CellPos cellpos_of(const Grid &g, double x, double y, double z) {
   CellPos c;
@@ -49,6 +52,9 @@ __device__ __forceinline__ CellPos cellpos_of(const Grid &g, double x, double y,
   c.ux = (float)((x - (g.lo[0] + (double)c.cx * g.R)) * g.invR);
   c.uy = (float)((y - (g.lo[1] + (double)c.cy * g.R)) * g.invR);
   c.uz = DIM == 3 ? (float)((z - (g.lo[2] + (double)c.cz * g.R)) * g.invR) : 0.0f;
+  c.cx = min(max(c.cx, -8), g.N[0] + 8);
+  c.cy = min(max(c.cy, -8), g.N[1] + 8);
+  c.cz = min(max(c.cz, -8), g.N[2] + 8);
   return c;
 }
 
@@ -99,7 +105,9 @@ __device__ __forceinline__ bool coop_next_row(CoopWalk &w, const Grid &g, const 
       w.gcy = __builtin_amdgcn_readlane(p.cy, f);
       w.gcz = __builtin_amdgcn_readlane(p.cz, f);
       const int wmax = 62 - 2 * g.reach;  // group x span, so that ncs <= 64
-      w.mem = ((w.todo >> lane) & 1ull) && p.cy == w.gcy && p.cz == w.gcz && p.cx >= gcx && p.cx <= gcx + wmax;
+      // lane f always joins, so every group removes at least one lane
+      w.mem = lane == f ||
+              (((w.todo >> lane) & 1ull) && p.cy == w.gcy && p.cz == w.gcz && p.cx >= gcx && p.cx <= gcx + wmax);
       w.todo &= ~__ballot(w.mem);
       const int ghi = wave_max_int(w.mem ? p.cx : gcx);
       w.U0 = max(gcx - g.reach, 0);

@@ -6,8 +6,9 @@
 // The offset keeps ~2^-24 R resolution anywhere in the domain (a few 1e-10 m
 // at R = h = 2.6 mm), where absolute FP32 positions would give ~6e-8 m.
 //
-// Pair pass: candidate tests on FP32 absolute positions (set membership only
-// changes for pairs within ~1e-7 m of 2h, whose terms vanish like (1-q/2)^3);
+// Pair pass: the lockstep row search of coop.h with candidate tests on FP32
+// absolute positions (set membership only changes for pairs within ~1e-7 m
+// of 2h, whose terms vanish like (1-q/2)^3);
 // the pair vector r from cell difference and offsets in FP32; W, grad W, the
 // Lax-Friedrichs, shifting and delta-SPH terms in FP32.  The correction
 // matrix L, the Riemann sum S_R and the conservative sum S_C accumulate in
@@ -35,11 +36,9 @@ namespace wb {
 #define WB_MIXED_WAVES_FEAT 3
 #endif
 #define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_MIXED_WAVES_FEAT : WB_MIXED_WAVES)))
-#ifndef WB_MIXED_COOP
-#define WB_MIXED_COOP 0
-#endif
 constexpr int kMList = 32;
 constexpr int kMBatch = 4;
+static_assert(kMBatch <= kRecPad, "batched candidate loads run at most kRecPad records past a run");
 
 __device__ __forceinline__ uint32_t pack_cell(int x, int y, int z) {
   return (uint32_t)x | ((uint32_t)y << 11) | ((uint32_t)z << 22);
@@ -356,7 +355,6 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     S.nnb += cnt;
   };
 
-#if WB_MIXED_COOP
   // candidate search with the rows walked in lockstep by the wave
   CellPos cp;
   cp.cx = cix;
@@ -381,39 +379,6 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     cnt = 0;
     if (fin) break;
   }
-#else
-  RowWalker w;
-  walker_init_cell<DIM>(w, g, cix, ciy, ciz, a0.x, a0.y, a0.z, P.two_h);
-  bool done = !active || !walker_next<DIM>(w, g, cs_f, cs_d, nf);
-  for (;;) {
-    int cnt = 0;
-    while (!done && cnt <= kMList - kMBatch) {
-      const uint32_t j0 = w.cur;
-      const uint32_t rem = w.end - j0;
-      const uint32_t last = w.end - 1;
-      float4 b[kMBatch];
-#pragma unroll
-      for (int k = 0; k < kMBatch; ++k) b[k] = rec.xa[min(j0 + (uint32_t)k, last)];
-#pragma unroll
-      for (int k = 0; k < kMBatch; ++k) {
-        const uint32_t j = j0 + k;
-        const float dx = b[k].x - axa.x, dy = b[k].y - axa.y, dz = DIM == 3 ? b[k].z - axa.z : 0.f;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        // branch-free append: the slot is written either way and kept only
-        // if taken (cnt <= kList - batch on entry keeps every write in range)
-        const bool take = (uint32_t)k < rem && j != i && r2 <= two_h2;
-        list[cnt][tid] = j;
-        cnt += take ? 1 : 0;
-      }
-      const uint32_t took = rem < (uint32_t)kMBatch ? rem : (uint32_t)kMBatch;
-      S.ntest += took;
-      w.cur = j0 + took;
-      if (w.cur >= w.end) done = !walker_next<DIM>(w, g, cs_f, cs_d, nf);
-    }
-    run_list(cnt);
-    if (done) break;
-  }
-#endif
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
 }
 

@@ -151,7 +151,9 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
     out.flags[i] = fl;
     out.nnb[i] = S.nnb;
     if (S.coincident) atomicOr(&sc->err, kErrNonFinite);
-    if (FEAT) {
+    // the classifier reads the candidates' rows only; every row is written
+    // when the features are exported (SPH_F_FEATURES)
+    if (FEAT && (is_cand || (flags & SPH_F_FEATURES))) {
       // eigenvalues, det L, kernel sum, neighbour count, |g| h, moments of g
       // and L along the normal and across it, |L^-T g| h, n against gravity,
       // dummy fraction, closest-neighbour q, |P| h
