@@ -221,6 +221,60 @@ def mlp_inference(n, reps=5):
             "note": "includes the per-call upload of the weights and the normalisation (5,345 floats)"}
 
 
+def state_of(sim, case):
+    """A case dict holding the simulation's current fluid state."""
+    c = dict(case)
+    c["x"], c["u"], c["phi"], c["mass"] = sim.field("x"), sim.field("u"), sim.field("phi"), sim.field("mass")
+    d = case["kind"] == 1
+    c["u"][d] = case["u"][d]
+    c["phi"][d] = case["phi"][d]
+    c["t"] = sim.stats()["t"]
+    return c
+
+
+def dambreak_detection(spin, steps):
+    """Exact vs learned free-surface detection on the 3D dam break of the
+    workloads (660,000 fluid, dx = 0.01, mixed precision) after `spin` steps of
+    the collapse: step time, detection time per step and misclassification on
+    the same state."""
+    import torch
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    clf = load_classifier()
+    case = wl.dambreak3d(dx=0.01, precision="mixed")
+    case = wl.with_params(case, cell_size=case["params"]["h"])
+    sim = Simulation(case)
+    sim.step(spin)
+    state = state_of(sim, case)
+    sim.close()
+    out = {"workload": f"3D dam break dx=0.01, {case['meta']['n_fluid']} fluid, after {spin} steps (t = {state['t']:.3f} s)"}
+    for mode in ("exact", "learned"):
+        s2 = Simulation(wl.with_params(state, fs_mode=mode))
+        if mode == "learned":
+            s2.set_classifier(clf["params"], clf["mean"], clf["std"], float(clf["margin"]))
+        s2.step(2)
+        s2.sync()
+        s2.profile(True)
+        s2.profile_read()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s2.stream)
+        s2.step(steps)
+        e1.record(s2.stream)
+        torch.cuda.synchronize()
+        prof = s2.profile_read()
+        st = s2.stats()
+        s2.profile(False)
+        r = {"ms_per_step": e0.elapsed_time(e1) / steps, "fs_detect_ms_per_step": prof["fs_detect"]["ms"] / steps,
+             "pair_ms_per_step": prof["pair"]["ms"] / steps, "candidates": st["n_cand"], "fluid": st["n_fluid"]}
+        if mode == "learned":
+            r["misclassification"] = misclassification(s2, state, clf)
+        s2.close()
+        out[mode] = r
+        log(f"dam break {mode}: {r}")
+    return out
+
+
 def bump_history(steps, every):
     """2D water layer 2.0 x 0.5 m over a Gaussian bump (amplitude 0.1 m, sigma
     0.1 m), dx = 0.002 (243.7k fluid), hydrostatic start: fluid max |U| every
@@ -266,6 +320,8 @@ def main():
     ap.add_argument("--paths", default="fp64,mixed,mixed_learned",
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
                          "mixed_learned: mixed precision with the trained classifier and exact fallback")
+    ap.add_argument("--dambreak-spin", type=int, default=4000,
+                    help="steps of the 3D dam break before the exact / learned detection comparison (0: skip)")
     ap.add_argument("--bump-steps", type=int, default=10000,
                     help="steps of the 2D Gaussian-bump spurious-velocity history (0: skip)")
     ap.add_argument("--calib", action="store_true",
@@ -346,6 +402,8 @@ def main():
         if k in results:
             out[f"{k}_over_fp64_step_rate"] = results["fp64"]["ms_per_step"] / results[k]["ms_per_step"]
     out["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
+    if args.dambreak_spin > 0:
+        out["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)
     out["spurious_u_tank2d_100steps"] = {"fp64": spurious_velocity("fp64"), "mixed": spurious_velocity("mixed")}
     if args.bump_steps > 0:
         out["spurious_u_bump2d"] = bump_history(args.bump_steps, 500)

@@ -384,6 +384,13 @@ sph_status rhs(sph_ctx *c, int stage) {
     }
   }
   ProfScope ps_fs(c, 3);
+  // classifier features: every fluid row when exported, else the candidates'
+  if (e == hipSuccess && feat) {
+    if (c->p.flags & SPH_F_FEATURES)
+      e = launch_features(c->P, c->r, nullptr, nullptr, (uint32_t)c->nf, c->sc, c->s);
+    else if (c->p.fs_mode == SPH_FS_LEARNED && c->has_clf)
+      e = launch_features(c->P, c->r, c->cand, &c->sc->n_cand, (uint32_t)c->nf, c->sc, c->s);
+  }
   if (e == hipSuccess && c->p.fs_mode != SPH_FS_NONE) {
     const uint32_t *list = c->cand;
     const uint32_t *count = &c->sc->n_cand;

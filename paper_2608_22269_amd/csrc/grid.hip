@@ -124,23 +124,50 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, u
 
 // ------------------------------------------------------------ hash + count
 
-// Cell of particle i, Eq. (ixyz), its sort key (the HashID's cell in the
-// brick order of cell_key), plus its slot inside the cell (atomic arrival
-// order).  Out-of-domain or non-finite positions set an
-// error bit and are parked in cell 0 so that every later index stays valid.
+// Slots inside the cells: lanes of a wave with the same key in a contiguous
+// run (particles arrive nearly sorted) reserve their slots with one atomic
+// add by the run's first lane.  Every lane must call it (valid lanes form a
+// prefix of the wave); returns this lane's slot.
+__device__ __forceinline__ uint32_t reserve_slot(uint32_t *count, uint32_t k, bool valid) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint32_t prev = __shfl_up(k, 1, 64);
+  const unsigned long long vmask = __ballot(valid);
+  const unsigned long long heads = __ballot(valid && (lane == 0 || prev != k));
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);  // bits 0 .. lane
+  const int h = 63 - __clzll((long long)(heads & upto));                      // this lane's run head
+  uint32_t base = 0;
+  if (valid && h == lane) {
+    const unsigned long long later = heads & ~upto;
+    const int end = later ? __ffsll((long long)later) - 1 : __popcll(vmask);
+    base = atomicAdd(&count[k], (uint32_t)(end - lane));
+  }
+  base = __shfl(base, valid ? h : lane, 64);
+  return base + (uint32_t)(lane - h);
+}
+
+// Cell of particle i, Eq. (ixyz), its sort key (the cell in the storage
+// order of cell_key), plus its slot inside the cell (arrival order).
+// Out-of-domain or non-finite positions set an error bit and are parked in
+// cell 0 so that every later index stays valid.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_hash_f64(Grid g, const double *__restrict__ x,
                                                   const double *__restrict__ y, const double *__restrict__ z,
                                                   int64_t n, uint32_t *__restrict__ key, uint32_t *__restrict__ slot,
                                                   uint32_t *__restrict__ count, Scalars *sc) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double p[3] = {x[i], y[i], DIM == 3 ? z[i] : 0.0};
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  double p[3] = {0.0, 0.0, 0.0};
+  if (valid) {
+    p[0] = x[i];
+    p[1] = y[i];
+    if (DIM == 3) p[2] = z[i];
+  }
   int c[3] = {0, 0, 0};
-  bool bad = false;
+  bool bad = !valid;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    if (!isfinite(p[a])) {
+    if (!valid) {
+    } else if (!isfinite(p[a])) {
       atomicOr(&sc->err, kErrNonFinite);
       bad = true;
     } else if (p[a] < g.lo[a] || p[a] > g.hi[a]) {
@@ -155,27 +182,33 @@ __global__ void __launch_bounds__(256) k_hash_f64(Grid g, const double *__restri
     }
   }
   uint32_t k = 0;
-  if (!bad) k = cell_key(g, c[0], c[1], c[2]);
-  key[i] = k;
-  slot[i] = atomicAdd(&count[k], 1u);
+  if (valid && !bad) k = cell_key(g, c[0], c[1], c[2]);
+  const uint32_t sl = reserve_slot(count, k, valid);
+  if (valid) {
+    key[i] = k;
+    slot[i] = sl;
+  }
 }
 
 // Mixed path: the cell is stored; the key is computed from it directly.
 __global__ void __launch_bounds__(256) k_hash_packed(Grid g, const uint32_t *__restrict__ cell, int64_t n,
                                                      uint32_t *__restrict__ key, uint32_t *__restrict__ slot,
                                                      uint32_t *__restrict__ count, Scalars *sc) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t c = cell[i];
-  int cx = c & 2047u, cy = (c >> 11) & 2047u, cz = c >> 22;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  const uint32_t c = valid ? cell[i] : 0u;
+  const int cx = c & 2047u, cy = (c >> 11) & 2047u, cz = c >> 22;
   uint32_t k = 0;
-  if (cx >= g.N[0] || cy >= g.N[1] || cz >= g.N[2]) {
+  if (valid && (cx >= g.N[0] || cy >= g.N[1] || cz >= g.N[2])) {
     atomicOr(&sc->err, kErrDomain);
-  } else {
+  } else if (valid) {
     k = cell_key(g, cx, cy, cz);
   }
-  key[i] = k;
-  slot[i] = atomicAdd(&count[k], 1u);
+  const uint32_t sl = reserve_slot(count, k, valid);
+  if (valid) {
+    key[i] = k;
+    slot[i] = sl;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_scatter(const uint32_t *__restrict__ key, const uint32_t *__restrict__ slot,

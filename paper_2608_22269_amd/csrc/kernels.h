@@ -30,6 +30,10 @@ hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
                            uint32_t *cand, bool features, hipStream_t s);
+// classifier features from the raw sums of the pair-pass epilogue, for the
+// rows of a device-counted list (count != nullptr) or rows 0 .. n - 1
+hipError_t launch_features(const Phys &P, const Rates &out, const uint32_t *list, const uint32_t *count, uint32_t n,
+                           const Scalars *sc, hipStream_t s);
 hipError_t launch_scan_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,
                            const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
                            const Rates &out, Scalars *sc, hipStream_t s);

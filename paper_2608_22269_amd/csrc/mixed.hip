@@ -28,12 +28,13 @@
 
 namespace wb {
 
-// waves per SIMD the register allocation targets (plain / with features)
+// waves per SIMD the register allocation targets (plain / with the
+// classifier sums; 4 measured faster for both)
 #ifndef WB_MIXED_WAVES
 #define WB_MIXED_WAVES 4
 #endif
 #ifndef WB_MIXED_WAVES_FEAT
-#define WB_MIXED_WAVES_FEAT 3
+#define WB_MIXED_WAVES_FEAT 4
 #endif
 #define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_MIXED_WAVES_FEAT : WB_MIXED_WAVES)))
 constexpr int kMList = 32;
@@ -338,8 +339,8 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
       Pf[1] += wrn * gy;
       if (DIM == 3) Pf[2] += wrn * gz;
       if (FEAT) {
-        S0f += W * b1.w;
-        S.qmin = fmin(S.qmin, (double)q);
+        S0f += wr * b1.w;  // W / W(dx) V
+        S.qmin = fminf(S.qmin, s);
         S.ndum += (j >= nf) ? 1u : 0u;
       }
     }

@@ -38,6 +38,16 @@ __device__ __forceinline__ float gelu_f(float z) {
   return 0.5f * z * (1.0f + tanhf(c * (z + 0.044715f * z * z * z)));
 }
 
+// GELU (tanh form) for BF16 inference: 0.5 z (1 + tanh u) = z / (1 + e^{-2u})
+// with u = sqrt(2/pi) (z + 0.044715 z^3), on the hardware exp2 and
+// reciprocal (relative error ~1e-6, far below the BF16 rounding of the
+// activations).  Saturates correctly: e -> inf gives 0, e -> 0 gives z.
+__device__ __forceinline__ float gelu_fast(float z) {
+  const float k = -2.0f * 0.7978845608028654f * 1.4426950408889634f;  // -2 sqrt(2/pi) log2(e)
+  const float e = __builtin_amdgcn_exp2f(k * z * fmaf(0.044715f, z * z, 1.0f));
+  return z * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
 __device__ __forceinline__ float gelu_grad_f(float z) {
   const float c = 0.7978845608028654f;
   const float th = tanhf(c * (z + 0.044715f * z * z * z));
@@ -197,6 +207,12 @@ __global__ void __launch_bounds__(256) k_mlp_infer_bf16(const float *__restrict_
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;  // MFMA lane coordinates
   const int64_t total = nrows_dev ? (int64_t)(*nrows_dev) : n;
+  const int64_t ntiles = (total + 15) / 16;
+  const int64_t wave_id = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  // waves without a tile leave before loading the weights (the grid is sized
+  // for the largest possible count; the device count may be far smaller)
+  if (wave_id >= ntiles) return;
 
   // B operands (weights) in registers: B[k][n] for n = col + 16 t,
   // k = 8 grp + e (+ 32 kb).  Layer 1 has K = 16: groups 2, 3 hold zeros.
@@ -225,9 +241,6 @@ __global__ void __launch_bounds__(256) k_mlp_infer_bf16(const float *__restrict_
     isd[e] = k < kMlpIn ? 1.0f / std[k] : 0.0f;
   }
 
-  const int64_t ntiles = (total + 15) / 16;
-  const int64_t wave_id = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
   for (int64_t tile = wave_id; tile < ntiles; tile += nwaves) {
     const int64_t r0 = tile * 16;
     // A operand of layer 1: row = col, k = 8 grp + e (features 0..15)
@@ -247,7 +260,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer_bf16(const float *__restrict_
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa, w1b[t], acc, 0, 0, 0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) act[wv][4 * grp + j][col + 16 * t] = to_bf16(gelu_f(acc[j] + b1c[t]));
+      for (int j = 0; j < 4; ++j) act[wv][4 * grp + j][col + 16 * t] = to_bf16(gelu_fast(acc[j] + b1c[t]));
     }
     // hand the tile to the other lanes of this wave through LDS
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -270,7 +283,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer_bf16(const float *__restrict_
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h0, w2b[t][0], acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h1, w2b[t][1], acc, 0, 0, 0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) part[j] += gelu_f(acc[j] + b2c[t]) * w3c[t];
+      for (int j = 0; j < 4; ++j) part[j] += gelu_fast(acc[j] + b2c[t]) * w3c[t];
     }
     // layer 3: reduce over the 16 lanes (columns) sharing rows 4 grp + j
 #pragma unroll

@@ -35,13 +35,14 @@ namespace wb {
 #ifndef WB_PAIR_UNROLL
 #define WB_PAIR_UNROLL 1
 #endif
-// waves per SIMD the register allocation targets: the plain instance fits 4
-// without spills, the one with classifier features 3
+// waves per SIMD the register allocation targets (plain instance / the one
+// with the classifier sums; 4 measured faster for both, despite a few spills
+// in the latter)
 #ifndef WB_PAIR_WAVES
 #define WB_PAIR_WAVES 4
 #endif
 #ifndef WB_PAIR_WAVES_FEAT
-#define WB_PAIR_WAVES_FEAT 3
+#define WB_PAIR_WAVES_FEAT 4
 #endif
 constexpr int kList = WB_PAIR_LIST;    // LDS list entries per lane
 constexpr int kBatch = WB_PAIR_BATCH;  // candidates fetched per search iteration
@@ -184,8 +185,8 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
     S.Ps[1] += wrn * gy;
     if (DIM == 3) S.Ps[2] += wrn * gz;
     if (FEAT) {
-      S.S0 += P.alpha * t4u * b1.w;
-      S.qmin = fmin(S.qmin, s * P.inv_h);
+      S.S0 += (float)(wr * b1.w);  // W / W(dx) V
+      S.qmin = fminf(S.qmin, (float)s);
       S.ndum += (j >= nf) ? 1u : 0u;
     }
   };
@@ -265,6 +266,92 @@ hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, co
     else
       launch_pair_f64_inst<3, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- classifier features
+
+// The 16 classifier features of a particle from the raw sums the pair-pass
+// epilogue left in its row (L, g = sum grad W V, the shifting sum P, the
+// kernel sum, the closest-neighbour q, the dummy fraction) and its
+// eigenvalues, normal and neighbour count: eigenvalues of L (3), det L,
+// kernel sum, neighbour count, |g| h, n.g h, tangential |g| h, n.L.n,
+// tr L - n.L.n, |L^-T g| h, n.G / |G|, dummy fraction, closest q, |P| h.
+// Rows of the device-counted list (count != nullptr) or rows 0 .. n - 1.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_features(Phys P, Rates out, const uint32_t *__restrict__ list,
+                                                  const uint32_t *__restrict__ count, uint32_t n,
+                                                  const Scalars *__restrict__ sc) {
+  const uint32_t total = count ? *count : n;
+  double G[3];
+  body_force(P, sc->t_rhs, G);
+  const double gg = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+    const uint32_t i = list ? list[k] : k;
+    float *f = out.feat + (size_t)i * kNFeat;
+    float raw[kNFeat - 1];
+#pragma unroll
+    for (int c = 0; c < kNFeat - 1; ++c) raw[c] = f[c];
+    const double L[6] = {raw[0], raw[1], raw[2], raw[3], raw[4], raw[5]};
+    const double g[3] = {raw[6], raw[7], raw[8]}, Pv[3] = {raw[9], raw[10], raw[11]};
+    const double n[3] = {out.nrm[0][i], out.nrm[1][i], DIM == 3 ? out.nrm[2][i] : 0.0};
+    const double Lm[3][3] = {{L[0], L[3], L[4]}, {L[3], L[1], L[5]}, {L[4], L[5], L[2]}};
+    double ng = 0, gn2 = 0, nLn = 0, trL = 0, pn2 = 0, ngr = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      ng += n[a] * g[a];
+      gn2 += g[a] * g[a];
+      trL += Lm[a][a];
+      pn2 += Pv[a] * Pv[a];
+      ngr += n[a] * G[a];
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) nLn += n[a] * Lm[a][b] * n[b];
+    }
+    double gt2 = 0;  // tangential part by components (no cancellation)
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const double t = g[a] - ng * n[a];
+      gt2 += t * t;
+    }
+    // |L^-T g| (L symmetric), or |g| where L is singular (the epilogue's rule)
+    double ngv[3] = {g[0], g[1], g[2]};
+    if (out.lam[0][i] > P.lambda_sing) {
+      double I[6];
+      inv_sym<DIM>(L, I);
+      sym_mul<DIM>(I, g, ngv);
+    }
+    const double nn = sqrt(ngv[0] * ngv[0] + ngv[1] * ngv[1] + (DIM == 3 ? ngv[2] * ngv[2] : 0.0));
+    const double detL = DIM == 2 ? L[0] * L[1] - L[3] * L[3]
+                                 : L[0] * (L[1] * L[2] - L[5] * L[5]) - L[3] * (L[3] * L[2] - L[5] * L[4]) +
+                                       L[4] * (L[3] * L[5] - L[1] * L[4]);
+    f[0] = (float)out.lam[0][i];
+    f[1] = (float)out.lam[1][i];
+    f[2] = (float)(DIM == 3 ? out.lam[2][i] : out.lam[1][i]);
+    f[3] = (float)detL;
+    f[4] = raw[12];
+    f[5] = (float)out.nnb[i];
+    f[6] = (float)(sqrt(gn2) * P.h);
+    f[7] = (float)(ng * P.h);
+    f[8] = (float)(sqrt(gt2) * P.h);
+    f[9] = (float)nLn;
+    f[10] = (float)(trL - nLn);
+    f[11] = (float)(nn * P.h);
+    f[12] = (float)(gg > 0.0 ? ngr / gg : 0.0);
+    f[13] = raw[14];
+    f[14] = raw[13];
+    f[15] = (float)(sqrt(pn2) * P.h);
+  }
+}
+
+hipError_t launch_features(const Phys &P, const Rates &out, const uint32_t *list, const uint32_t *count, uint32_t n,
+                           const Scalars *sc, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  unsigned blocks = grid_for(n);
+  if (blocks > 2048) blocks = 2048;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_features<2>, dim3(blocks), dim3(kBlock), 0, s, P, out, list, count, n, sc);
+  else
+    hipLaunchKernelGGL(k_features<3>, dim3(blocks), dim3(kBlock), 0, s, P, out, list, count, n, sc);
   return hipGetLastError();
 }
 

@@ -30,11 +30,11 @@ __device__ __forceinline__ void wave_count(uint32_t *counter, bool pred) {
 
 // Neighbour sums of one particle (FP64).  L and N are symmetric and packed
 // as (xx, yy, zz, xy, xz, yz); N holds N_ab + N_ba off the diagonal.  Ps is
-// sum (W / W(dx))^n grad W V (the shifting sum is gs + R Ps).  S0, qmin and
-// ndum only feed the classifier features.
+// sum (W / W(dx))^n grad W V (the shifting sum is gs + R Ps).  S0 (sum of
+// W / W(dx) V), qmin (closest distance) and ndum only feed the classifier.
 struct PairSums {
   double L[6], gs[3], SR[3], SC[3], Ps[3], N[6], Ds;
-  double S0, qmin;
+  float S0, qmin;  // classifier inputs only: FP32 is ample
   uint32_t nnb, ndum, ntest;
   bool coincident;
 };
@@ -44,8 +44,9 @@ __device__ __forceinline__ void sums_zero(PairSums &S) {
   for (int k = 0; k < 6; ++k) S.L[k] = S.N[k] = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) S.gs[k] = S.SR[k] = S.SC[k] = S.Ps[k] = 0.0;
-  S.Ds = S.S0 = 0.0;
-  S.qmin = 2.0;
+  S.Ds = 0.0;
+  S.S0 = 0.0f;
+  S.qmin = INFINITY;
   S.nnb = S.ndum = S.ntest = 0;
   S.coincident = false;
 }
@@ -58,6 +59,23 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
   double lam[3];
   eig_sym<DIM>(S.L, lam);
   const double lmin = lam[0];
+  // classifier inputs: the raw sums of the particles in the candidate window
+  // of lambda_min (every row when the features are exported), written here
+  // so that they need no registers later; k_features completes them
+  if (FEAT && active &&
+      ((flags & SPH_F_FEATURES) || (P.fs_mode != SPH_FS_NONE && lmin > P.lambda_lo && lmin <= P.lambda_hi))) {
+    float *f = out.feat + (size_t)i * kNFeat;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) f[k] = (float)S.L[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      f[6 + a] = (float)S.gs[a];
+      f[9 + a] = (float)(S.gs[a] + P.pst_R * S.Ps[a]);
+    }
+    f[12] = (float)((double)S.S0 / P.w0inv + P.wself * Vi);  // sum W V, self term included
+    f[13] = (float)fmin((double)S.qmin * P.inv_h, 2.0);
+    f[14] = (float)(S.nnb > 0 ? (double)S.ndum / (double)S.nnb : 0.0);
+  }
   const bool singular = lmin <= P.lambda_sing;
   const bool tic = (flags & SPH_F_TIC) && lmin < P.lambda_tic;
   const bool cons = singular || tic;
@@ -151,47 +169,6 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
     out.flags[i] = fl;
     out.nnb[i] = S.nnb;
     if (S.coincident) atomicOr(&sc->err, kErrNonFinite);
-    // the classifier reads the candidates' rows only; every row is written
-    // when the features are exported (SPH_F_FEATURES)
-    if (FEAT && (is_cand || (flags & SPH_F_FEATURES))) {
-      // eigenvalues, det L, kernel sum, neighbour count, |g| h, moments of g
-      // and L along the normal and across it, |L^-T g| h, n against gravity,
-      // dummy fraction, closest-neighbour q, |P| h
-      float *f = out.feat + (size_t)i * kNFeat;
-      const double S0s = S.S0 + P.wself * Vi;
-      const double Lm[3][3] = {{S.L[0], S.L[3], S.L[4]}, {S.L[3], S.L[1], S.L[5]}, {S.L[4], S.L[5], S.L[2]}};
-      double ngs = 0, gn2 = 0, nLn = 0, trL = 0, pn2 = 0, ngr = 0, gg2 = 0;
-      for (int a = 0; a < DIM; ++a) {
-        ngs += nrm[a] * S.gs[a];
-        gn2 += S.gs[a] * S.gs[a];
-        trL += Lm[a][a];
-        const double pa = S.gs[a] + P.pst_R * S.Ps[a];
-        pn2 += pa * pa;
-        ngr += nrm[a] * G[a];
-        gg2 += G[a] * G[a];
-        for (int b = 0; b < DIM; ++b) nLn += nrm[a] * Lm[a][b] * nrm[b];
-      }
-      const double gt2 = gn2 - ngs * ngs;
-      double detL = DIM == 2 ? S.L[0] * S.L[1] - S.L[3] * S.L[3]
-                             : S.L[0] * (S.L[1] * S.L[2] - S.L[5] * S.L[5]) - S.L[3] * (S.L[3] * S.L[2] - S.L[5] * S.L[4]) +
-                                   S.L[4] * (S.L[3] * S.L[5] - S.L[1] * S.L[4]);
-      f[0] = (float)lam[0];
-      f[1] = (float)lam[1];
-      f[2] = (float)(DIM == 3 ? lam[2] : lam[1]);
-      f[3] = (float)detL;
-      f[4] = (float)S0s;
-      f[5] = (float)S.nnb;
-      f[6] = (float)(sqrt(gn2) * P.h);
-      f[7] = (float)(ngs * P.h);
-      f[8] = (float)(sqrt(gt2 > 0.0 ? gt2 : 0.0) * P.h);
-      f[9] = (float)nLn;
-      f[10] = (float)(trL - nLn);
-      f[11] = (float)(nn * P.h);
-      f[12] = (float)(gg2 > 0.0 ? ngr / sqrt(gg2) : 0.0);
-      f[13] = (float)(S.nnb > 0 ? (double)S.ndum / (double)S.nnb : 0.0);
-      f[14] = (float)S.qmin;
-      f[15] = (float)(sqrt(pn2) * P.h);
-    }
   }
   // candidate list and statistics (wave-aggregated atomics)
   const bool cand_l = active && is_cand;

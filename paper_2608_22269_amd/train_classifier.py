@@ -108,7 +108,7 @@ def train(Xtr, ytr, epochs=20, batch=4096, lr=2e-3, seed=0):
     hist = []
     for ep in range(epochs):
         perm = torch.as_tensor(rng.permutation(len(ytr)).astype(np.int32), device="cuda")
-        lr_ep = lr * (0.5 ** (ep // 8))
+        lr_ep = lr * (0.5 ** (ep // 10))
         hist.append(tr.train_epoch(Xd, yd, wd, perm, batch, lr_ep))
         log(f"epoch {ep}: loss {hist[-1]:.5f}")
     return tr.params(), mean, std, hist
@@ -133,8 +133,8 @@ def main():
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--dambreak-steps", type=int, default=8000)
     ap.add_argument("--every", type=int, default=100)
-    ap.add_argument("--epochs", type=int, default=24)
-    ap.add_argument("--target", type=float, default=3e-4,
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--target", type=float, default=1e-4,
                     help="misclassification allowed among the validation candidates (sets the margin)")
     args = ap.parse_args()
     import workloads as wl
@@ -154,6 +154,8 @@ def main():
     Xc, yc = collect_disordered()
     X = np.concatenate([Xa, Xt, Xb, Xc]).astype(np.float32)
     y = np.concatenate([ya, yt, yb, yc]).astype(np.float32)
+    names = ["dambreak3d", "dambreak3d_tall", "slosh3d", "disordered_blocks"]
+    src = np.concatenate([np.full(len(v), k) for k, v in enumerate((ya, yt, yb, yc))])
     rng = np.random.default_rng(0)
     idx = rng.permutation(len(y))
     ntr = int(0.8 * len(y))
@@ -166,6 +168,15 @@ def main():
     tau = choose_margin(lg, yv, args.target)
     conf = np.abs(lg) >= tau
     err_conf = float((((lg > 0) != (yv > 0.5)) & conf).sum() / len(yv))
+    sv = src[va_i]
+    per_source = {}
+    for k, nm in enumerate(names):
+        m = sv == k
+        if m.any():
+            wrong = ((lg[m] > 0) != (yv[m] > 0.5)) & conf[m]
+            per_source[nm] = {"n_val": int(m.sum()), "misclassified": int(wrong.sum()),
+                              "rate": float(wrong.mean()), "fallback_fraction": float(1.0 - conf[m].mean())}
+    log(f"per source: {per_source}")
     log(f"validation: raw misclassification {err_raw:.4%}; tau {tau:.3f} keeps {conf.mean():.1%} of candidates "
         f"with {err_conf:.4%} errors; {1 - conf.mean():.1%} fall back to the exact test")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
@@ -173,7 +184,8 @@ def main():
     report = {"n_samples": int(len(y)), "surface_fraction": float(y.mean()), "n_train": int(ntr),
               "n_val": int(len(va_i)), "loss_history": hist, "val_misclassification_raw": err_raw,
               "margin": tau, "val_confident_fraction": float(conf.mean()),
-              "val_misclassification_with_fallback": err_conf, "seconds": time.time() - t0,
+              "val_misclassification_with_fallback": err_conf, "val_per_source": per_source,
+              "seconds": time.time() - t0, "epochs": args.epochs,
               "target": args.target,
               "sources": {"dambreak3d": {"dx": 0.01, "steps": args.dambreak_steps, "every": args.every,
                                          "n": int(len(ya))},
