@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "ms/step & pair evals/s at 17.5M particles, FP64 vs mixed+learned; spurious |u|"
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed); non-packed issue equals the FP64 figure
-# Algorithmic floating-point operations of the pair pass:
+# Algorithmic floating-point operations of the pair pass, counted from the body:
 # per in-range ordered pair (3D body of Eq. sph with delta-SPH and shifting),
 # and per candidate distance test (difference vector and squared norm).
 FLOP_PER_PAIR_3D = 95

@@ -80,7 +80,7 @@ def lib():
         L.orc_neighbors_cells.argtypes = [P, C.c_int64, vp, vp, vp, C.c_int64, vp]
         L.orc_eigvals.argtypes = [C.c_int, vp, vp]
         L.orc_eigvals.restype = None
-        L.orc_eval_rates.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int,
+        L.orc_eval_rates.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int, vp,
                                      C.POINTER(_Rates)]
         L.orc_dt.restype = C.c_double
         L.orc_dt.argtypes = [P, C.c_int64, vp, vp]
@@ -191,9 +191,11 @@ def mass_from_phi(pd, phi):
     return pd["rho0"] * np.exp(np.asarray(phi, dtype=np.float64) / (pd["c0"] ** 2)) * pd["dx"] ** dim
 
 
-def eval_rates(case, t=None, mode="cells"):
+def eval_rates(case, t=None, mode="cells", rows=None):
     """One evaluation of the semi-discrete system at the case's state.
-    Returns a dict of per-particle arrays in the case's particle order."""
+    Returns a dict of per-particle arrays in the case's particle order.
+    rows: optional indices of the fluid particles to evaluate (the other
+    rows of the fluid outputs stay zero); for samples of large cases."""
     dim, n, x, u, phi, m, kind, nd = _state(case)
     p = make_params(case["params"])
     t = float(case.get("t", 0.0) if t is None else t)
@@ -207,8 +209,13 @@ def eval_rates(case, t=None, mode="cells"):
     }
     r = _Rates(*[_ptr(out[k]) for k in ("acc", "dphi", "dushift", "lam", "normal", "fs", "tic", "nnb",
                                         "feat", "fs_margin", "mir_phi", "mir_u", "mir_src", "scal")])
+    only = None
+    if rows is not None:
+        only = np.zeros(n, dtype=np.uint8)
+        only[np.asarray(rows, dtype=np.int64)] = 1
     st = lib().orc_eval_rates(C.byref(p), n, _ptr(x), _ptr(u), _ptr(phi), _ptr(m), _ptr(kind), _ptr(nd),
-                              t, 0 if mode == "brute" else 1, C.byref(r))
+                              t, 0 if mode == "brute" else 1, _ptr(only) if only is not None else None,
+                              C.byref(r))
     _check(st, "eval_rates")
     out["umax"], out["gmag"], out["t"], out["n_singular"] = out["scal"].tolist()
     return out

@@ -18,9 +18,9 @@
  *   integrator      Sec. 2.3, SSP-RK2 stages and the three-way time step rule
  *   walls           Sec. 2.4, Eq. (phiBn) and the slip mirror
  *   neighbours      Sec. 3, Eqs. (hashid), (ixyz), Algorithm 1
- *   eigenvalues     Sec. 3, closed form for the symmetric correction matrix
- * Readings of passages that are silent or garbled are listed in the design doc and
- * noted where they are used below.
+ *   eigenvalues     Sec. 3 (minimum eigenvalue of L), by Jacobi rotations
+ * Readings of passages that are silent or garbled are noted where they are
+ * used below.
  */
 #include <math.h>
 #include <stdint.h>
@@ -344,55 +344,108 @@ static int build_csr(const orc_params *p, int64_t n, const double *x, int mode, 
     return ORC_OK;
 }
 
+/* The same CSR (cells mode) restricted to the rows with rows[i] != 0; the
+ * other rows are empty.  Lets a large case be checked on a sample of
+ * particles without the neighbour lists of all of them. */
+static int build_csr_rows(const orc_params *p, int64_t n, const double *x, const uint8_t *rows,
+                          int64_t **off_out, int32_t **ids_out) {
+    cell_list cl;
+    int st = cell_list_build(p, n, x, &cl);
+    if (st != ORC_OK) return st;
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!off) {
+        cell_list_free(&cl);
+        return ORC_ENOMEM;
+    }
+    int zero = 0;
+    off[0] = 0;
+    for (int64_t i = 0; i < n; ++i)
+        off[i + 1] = off[i] + (rows[i] ? cell_list_query(p, &cl, x, i, NULL, 0, &zero) : 0);
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(off[n] > 0 ? off[n] : 1));
+    if (!ids) {
+        free(off);
+        cell_list_free(&cl);
+        return ORC_ENOMEM;
+    }
+    if (zero) {
+        free(off);
+        free(ids);
+        cell_list_free(&cl);
+        return ORC_ENONFINITE;
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!rows[i]) continue;
+        int z = 0;
+        cell_list_query(p, &cl, x, i, ids + off[i], off[i + 1] - off[i], &z);
+    }
+    cell_list_free(&cl);
+    *off_out = off;
+    *ids_out = ids;
+    return ORC_OK;
+}
+
 /* -------------------------------------------------------- small algebra */
 
-/* Eigenvalues of a symmetric 2x2 / 3x3 matrix in closed form (Sec. 3),
- * ascending.  S is row-major d x d and is symmetrised first. */
+/* Eigenvalues of the symmetric part of a 2x2 / 3x3 matrix, ascending
+ * (Sec. 3 uses the minimum eigenvalue of the correction matrix).  The method
+ * evaluates them in closed form; the oracle takes their definition instead
+ * and diagonalises by cyclic Jacobi rotations (Golub & Van Loan, Matrix
+ * Computations, Sec. 8.5) until the off-diagonal part is below 1e-18 of the
+ * matrix norm, which is accurate to a few ulps of |S| also where two
+ * eigenvalues nearly coincide (the trigonometric closed form there loses half
+ * the digits).  S is row-major d x d. */
 void orc_eigvals(int dim, const double *S, double *lam) {
-    if (dim == 2) {
-        double a = S[0], c = S[3], b = 0.5 * (S[1] + S[2]);
-        double m = 0.5 * (a + c), d = 0.5 * (a - c);
-        double r = sqrt(d * d + b * b);
-        lam[0] = m - r;
-        lam[1] = m + r;
-        lam[2] = 0.0;
-        return;
+    double A[3][3] = {{0}};
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) A[a][b] = 0.5 * (S[a * dim + b] + S[b * dim + a]);
+    double norm2 = 0.0;
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) norm2 += A[a][b] * A[a][b];
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off2 = 0.0;
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b)
+                if (a != b) off2 += A[a][b] * A[a][b];
+        if (off2 <= 1e-36 * norm2) break;
+        for (int p = 0; p < dim; ++p)
+            for (int q = p + 1; q < dim; ++q) {
+                if (A[p][q] == 0.0) continue;
+                /* rotation J (J_pp = J_qq = c, J_pq = s, J_qp = -s) with
+                 * (J^T A J)_pq = 0 */
+                double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = tau >= 0.0 ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                      : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+                double J[3][3] = {{0}};
+                for (int k = 0; k < dim; ++k) J[k][k] = 1.0;
+                J[p][p] = c;
+                J[q][q] = c;
+                J[p][q] = s;
+                J[q][p] = -s;
+                double AJ[3][3] = {{0}}, B[3][3] = {{0}};
+                for (int a = 0; a < dim; ++a)
+                    for (int b = 0; b < dim; ++b)
+                        for (int k = 0; k < dim; ++k) AJ[a][b] += A[a][k] * J[k][b];
+                for (int a = 0; a < dim; ++a)
+                    for (int b = 0; b < dim; ++b)
+                        for (int k = 0; k < dim; ++k) B[a][b] += J[k][a] * AJ[k][b];
+                B[p][q] = B[q][p] = 0.0;
+                for (int a = 0; a < dim; ++a)
+                    for (int b = 0; b < dim; ++b) A[a][b] = 0.5 * (B[a][b] + B[b][a]);
+            }
     }
-    double a00 = S[0], a11 = S[4], a22 = S[8];
-    double a01 = 0.5 * (S[1] + S[3]), a02 = 0.5 * (S[2] + S[6]), a12 = 0.5 * (S[5] + S[7]);
-    double p1 = a01 * a01 + a02 * a02 + a12 * a12;
-    if (p1 == 0.0) {
-        double e[3] = {a00, a11, a22};
-        for (int i = 0; i < 3; ++i)
-            for (int j = i + 1; j < 3; ++j)
-                if (e[j] < e[i]) {
-                    double t = e[i];
-                    e[i] = e[j];
-                    e[j] = t;
-                }
-        lam[0] = e[0];
-        lam[1] = e[1];
-        lam[2] = e[2];
-        return;
-    }
-    /* trigonometric solution of the characteristic cubic */
-    double q = (a00 + a11 + a22) / 3.0;
-    double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
-    double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * p1;
-    double pp = sqrt(p2 / 6.0);
-    double B00 = b00 / pp, B11 = b11 / pp, B22 = b22 / pp;
-    double B01 = a01 / pp, B02 = a02 / pp, B12 = a12 / pp;
-    double detB = B00 * (B11 * B22 - B12 * B12) - B01 * (B01 * B22 - B12 * B02) +
-                  B02 * (B01 * B12 - B11 * B02);
-    double r = 0.5 * detB;
-    if (r < -1.0) r = -1.0;
-    if (r > 1.0) r = 1.0;
-    double ang = acos(r) / 3.0;
-    double e_hi = q + 2.0 * pp * cos(ang);
-    double e_lo = q + 2.0 * pp * cos(ang + 2.0 * ORC_PI / 3.0);
-    lam[0] = e_lo;
-    lam[2] = e_hi;
-    lam[1] = 3.0 * q - e_hi - e_lo;
+    double e[3] = {A[0][0], A[1][1], dim == 3 ? A[2][2] : 0.0};
+    for (int i = 0; i < dim; ++i)
+        for (int j = i + 1; j < dim; ++j)
+            if (e[j] < e[i]) {
+                double tmp = e[i];
+                e[i] = e[j];
+                e[j] = tmp;
+            }
+    lam[0] = e[0];
+    lam[1] = e[1];
+    lam[2] = dim == 3 ? e[2] : 0.0;
 }
 
 static double det_d(int dim, const double *M) {
@@ -539,15 +592,42 @@ static int scan_region(const orc_params *p, int64_t i, const double *x, const do
     return 1;
 }
 
-/* One evaluation of the semi-discrete system, Eq. (sph), at time t. */
+/* One evaluation of the semi-discrete system, Eq. (sph), at time t.  With
+ * only != NULL the rates are computed for the fluid particles with only[i]
+ * != 0 alone (the others are left zero), from neighbour lists of those
+ * particles and of the dummies among their neighbours (cells mode). */
 int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double *u,
                    const double *phi, const double *mass, const uint8_t *kind, const double *nd,
-                   double t, int nbr_mode, orc_rates *out) {
+                   double t, int nbr_mode, const uint8_t *only, orc_rates *out) {
     int dim = p->dim;
     if (dim != 2 && dim != 3) return ORC_EINVAL;
+    if (only && nbr_mode == 0) return ORC_EINVAL;
     int64_t *off = NULL;
     int32_t *ids = NULL;
-    int st = build_csr(p, n, x, nbr_mode, &off, &ids);
+    int st;
+    if (!only) {
+        st = build_csr(p, n, x, nbr_mode, &off, &ids);
+    } else {
+        /* rows: the sampled fluid particles, then also the dummies in their
+         * neighbour lists (the wall mirror needs their lists) */
+        uint8_t *rows = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+        if (!rows) return ORC_ENOMEM;
+        for (int64_t i = 0; i < n; ++i) rows[i] = (uint8_t)(only[i] && kind[i] == 0);
+        st = build_csr_rows(p, n, x, rows, &off, &ids);
+        if (st == ORC_OK) {
+            for (int64_t i = 0; i < n; ++i) {
+                if (!(only[i] && kind[i] == 0)) continue;
+                for (int64_t k = off[i]; k < off[i + 1]; ++k)
+                    if (kind[ids[k]] == 1) rows[ids[k]] = 1;
+            }
+            free(off);
+            free(ids);
+            off = NULL;
+            ids = NULL;
+            st = build_csr_rows(p, n, x, rows, &off, &ids);
+        }
+        free(rows);
+    }
     if (st != ORC_OK) return st;
 
     double G[3];
@@ -602,7 +682,7 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
         out->mir_phi[i] = phiv[i];
         for (int a = 0; a < dim; ++a) out->mir_u[i * dim + a] = uv[i * dim + a];
         out->mir_src[i] = src[i];
-        if (kind[i] != 0) continue;
+        if (kind[i] != 0 || (only && !only[i])) continue;
 
         /* pair sums over N(i), Algorithm 1 / Eq. (sph) */
         double L[9] = {0}, g[3] = {0}, SR[3] = {0}, SC[3] = {0}, Nm[9] = {0}, P[3] = {0};
@@ -759,7 +839,7 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
     if (p->fs_mode == ORC_FS_EXACT) {
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t i = 0; i < n; ++i) {
-            if (kind[i] != 0) continue;
+            if (kind[i] != 0 || (only && !only[i])) continue;
             double lmin = out->lam[i * 3];
             double nn = 0.0;
             for (int a = 0; a < dim; ++a) nn += out->normal[i * dim + a] * out->normal[i * dim + a];
@@ -869,7 +949,7 @@ int orc_step(const orc_params *p, int64_t n, double *x, double *u, double *phi, 
         memcpy(u0, u, sizeof(double) * nn * dim);
         memcpy(p0, phi, sizeof(double) * n);
         /* first stage */
-        st = orc_eval_rates(p, n, x, u, phi, mass, kind, nd, *t, nbr_mode, &r);
+        st = orc_eval_rates(p, n, x, u, phi, mass, kind, nd, *t, nbr_mode, NULL, &r);
         if (st != ORC_OK) break;
         for (int64_t i = 0; i < n; ++i) {
             if (kind[i] != 0) continue;
@@ -880,7 +960,7 @@ int orc_step(const orc_params *p, int64_t n, double *x, double *u, double *phi, 
             }
         }
         /* second stage */
-        st = orc_eval_rates(p, n, x, u, phi, mass, kind, nd, *t + dt, nbr_mode, &r);
+        st = orc_eval_rates(p, n, x, u, phi, mass, kind, nd, *t + dt, nbr_mode, NULL, &r);
         if (st != ORC_OK) break;
         for (int64_t i = 0; i < n; ++i) {
             if (kind[i] != 0) continue;

@@ -191,6 +191,18 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
 
 // Closed-form eigenvalues of a symmetric 2x2 / 3x3 matrix (Sec. 3),
 // ascending.  S = (xx, yy, zz, xy, xz, yz).
+//
+// 3x3: the trigonometric solution of the characteristic cubic loses half the
+// digits for the two eigenvalues of a nearly repeated pair (acos is steep at
+// +-1), which lattice rows next to a wall or the surface hit (L = diag(a, a,
+// b) up to round-off).  So only the isolated eigenvalue is taken from it --
+// the largest when det((S - qI)/p)/2 >= 0, else the smallest; its distance to
+// the other two is at least 1.5 p there and its value depends smoothly on the
+// cosine argument -- and the other two come from the 2x2 compression of S onto
+// the plane orthogonal to that eigenvalue's eigenvector (the largest cross
+// product of two rows of S - e I), whose eigenvalues m +- sqrt(d^2 + b^2)
+// involve no cancellation (Eberly, "A Robust Eigensolver for 3x3 Symmetric
+// Matrices", Geometric Tools, 2014).  Accurate to a few ulps of |S|.
 template <int DIM>
 __device__ __forceinline__ void eig_sym(const double S[6], double lam[3]) {
   if (DIM == 2) {
@@ -219,11 +231,55 @@ __device__ __forceinline__ void eig_sym(const double S[6], double lam[3]) {
   double det = B00 * (B11 * B22 - B12 * B12) - B01 * (B01 * B22 - B12 * B02) + B02 * (B01 * B12 - B11 * B02);
   double r = fmin(1.0, fmax(-1.0, 0.5 * det));
   double ang = acos(r) * (1.0 / 3.0);
-  double hi = q + 2.0 * p * cos(ang);
-  double lo = q + 2.0 * p * cos(ang + 2.0943951023931954923);  // + 2 pi / 3
+  // isolated eigenvalue: q + 2p cos(ang) (largest) or q + 2p cos(ang + 2 pi/3)
+  const double e1 = q + 2.0 * p * cos(r >= 0.0 ? ang : ang + 2.0943951023931954923);
+  // its eigenvector: rows of S - e1 I span the orthogonal plane
+  const double r0x = a00 - e1, r1y = a11 - e1, r2z = a22 - e1;
+  const double c0x = a01 * a12 - a02 * r1y, c0y = a02 * a01 - r0x * a12, c0z = r0x * r1y - a01 * a01;
+  const double c1x = a01 * r2z - a02 * a12, c1y = a02 * a02 - r0x * r2z, c1z = r0x * a12 - a01 * a02;
+  const double c2x = r1y * r2z - a12 * a12, c2y = a12 * a02 - a01 * r2z, c2z = a01 * a12 - r1y * a02;
+  const double n0 = c0x * c0x + c0y * c0y + c0z * c0z;
+  const double n1 = c1x * c1x + c1y * c1y + c1z * c1z;
+  const double n2 = c2x * c2x + c2y * c2y + c2z * c2z;
+  double vx = c0x, vy = c0y, vz = c0z, nv = n0;
+  if (n1 > nv) { vx = c1x; vy = c1y; vz = c1z; nv = n1; }
+  if (n2 > nv) { vx = c2x; vy = c2y; vz = c2z; nv = n2; }
+  double e2, e3;
+  if (nv > 0.0) {
+    const double iv = 1.0 / sqrt(nv);
+    vx *= iv; vy *= iv; vz *= iv;
+    // orthonormal u, w spanning v's orthogonal plane
+    double ux, uy, uz;
+    if (fabs(vx) > fabs(vy)) {
+      const double s = 1.0 / sqrt(vx * vx + vz * vz);
+      ux = -vz * s; uy = 0.0; uz = vx * s;
+    } else {
+      const double s = 1.0 / sqrt(vy * vy + vz * vz);
+      ux = 0.0; uy = vz * s; uz = -vy * s;
+    }
+    const double wx = vy * uz - vz * uy, wy = vz * ux - vx * uz, wz = vx * uy - vy * ux;
+    const double aux = a00 * ux + a01 * uy + a02 * uz, auy = a01 * ux + a11 * uy + a12 * uz,
+                 auz = a02 * ux + a12 * uy + a22 * uz;
+    const double awx = a00 * wx + a01 * wy + a02 * wz, awy = a01 * wx + a11 * wy + a12 * wz,
+                 awz = a02 * wx + a12 * wy + a22 * wz;
+    const double m00 = ux * aux + uy * auy + uz * auz;
+    const double m01 = wx * aux + wy * auy + wz * auz;
+    const double m11 = wx * awx + wy * awy + wz * awz;
+    const double m = 0.5 * (m00 + m11), d = 0.5 * (m00 - m11);
+    const double rr = sqrt(d * d + m01 * m01);
+    e2 = m - rr;
+    e3 = m + rr;
+  } else {  // p at the bottom of the FP64 range: the cubic's roots as they are
+    const double hi = q + 2.0 * p * cos(ang), lo = q + 2.0 * p * cos(ang + 2.0943951023931954923);
+    lam[0] = lo;
+    lam[2] = hi;
+    lam[1] = 3.0 * q - hi - lo;
+    return;
+  }
+  const double lo = fmin(e1, fmin(e2, e3)), hi = fmax(e1, fmax(e2, e3));
   lam[0] = lo;
   lam[2] = hi;
-  lam[1] = 3.0 * q - hi - lo;
+  lam[1] = e1 + e2 + e3 - lo - hi;
 }
 
 // Inverse of a symmetric matrix S = (xx, yy, zz, xy, xz, yz) as the same

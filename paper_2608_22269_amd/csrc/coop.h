@@ -28,6 +28,13 @@
 
 namespace wb {
 
+// Orders the LDS writes of a wave before its later reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
@@ -71,6 +78,7 @@ struct CoopWalk {
   bool mem;                 // lane in the group
   int c, ce;                // lane's cursor and end in the current window (record index)
   uint32_t dlo, dhi;        // lane's dummy window of the current row
+  int dmark;                // list count when the current dummy window began
   float rr2;
 };
 
@@ -85,6 +93,7 @@ __device__ __forceinline__ void coop_init(CoopWalk &w, const Grid &g, bool activ
   w.mem = false;
   w.c = w.ce = 0;  // no window yet
   w.dlo = w.dhi = 0;
+  w.dmark = 0;
   w.seg = 2;
 }
 
@@ -177,11 +186,13 @@ __device__ __forceinline__ bool coop_next_row(CoopWalk &w, const Grid &g, const 
 // Loads run up to BATCH - 1 records past a window's end: the record arrays
 // carry that many padding records.  Requires 2 reach + 2 <= 64 (the union
 // span's cell starts fit one load).
-template <int DIM, int LIST, int BATCH, class LoadFn, class NearFn>
+// COUNT_D: also count the neighbours taken from dummy windows into ndum (from
+// the list counts at the window's ends, nothing per candidate).
+template <int DIM, int LIST, int BATCH, bool COUNT_D, class LoadFn, class NearFn>
 __device__ __forceinline__ bool coop_fill(CoopWalk &w, const Grid &g, const uint32_t *__restrict__ cs_f,
                                           const uint32_t *__restrict__ cs_d, uint32_t nf, const CellPos &p,
-                                          uint32_t *list_col, int stride, int &cnt, uint32_t &ntest, LoadFn load,
-                                          NearFn near) {
+                                          uint32_t *list_col, int stride, int &cnt, uint32_t &ntest,
+                                          uint32_t &ndum, LoadFn load, NearFn near) {
   for (;;) {
     // batches of the current windows (the hot loop: only the cursor and the
     // list count change here)
@@ -190,6 +201,10 @@ __device__ __forceinline__ bool coop_fill(CoopWalk &w, const Grid &g, const uint
     while (__ballot(c < ce)) {
       if (__ballot(cnt > LIST - BATCH)) {
         w.c = c;
+        if (COUNT_D && w.seg == 2) {  // the caller empties the list
+          ndum += (uint32_t)(cnt - w.dmark);
+          w.dmark = 0;
+        }
         return false;
       }
       // idle lanes load record 0 (always present)
@@ -214,10 +229,97 @@ __device__ __forceinline__ bool coop_fill(CoopWalk &w, const Grid &g, const uint
       w.seg = 2;
       w.c = (int)w.dlo;
       w.ce = (int)w.dhi;
+      if (COUNT_D) w.dmark = cnt;
       continue;
     }
+    if (COUNT_D) ndum += (uint32_t)(cnt - w.dmark);
+    w.dmark = cnt;  // (unused until the next dummy window)
     if (!coop_next_row<DIM>(w, g, cs_f, cs_d, nf, p)) return true;
   }
+}
+
+// ------------------------------------------------ one wave per particle
+
+// The fluid and dummy windows of row r of particle p's search (the walker's
+// cut), for a wave that spreads one particle's rows over its lanes.  Empty
+// when the row is outside the grid or pruned.
+template <int DIM>
+__device__ __forceinline__ void row_windows(const Grid &g, const CellPos &p, float rr2, int r,
+                                            const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
+                                            uint32_t nf, uint32_t &fb, uint32_t &fl, uint32_t &db, uint32_t &dl) {
+  fb = fl = db = dl = 0;
+  const int side = 2 * g.reach + 1;
+  const int dy = (DIM == 3 ? r % side : r) - g.reach;
+  const int dz = DIM == 3 ? r / side - g.reach : 0;
+  const int iy = p.cy + dy, iz = p.cz + dz;
+  if (iy < 0 || iy >= g.N[1]) return;
+  if (DIM == 3 && (iz < 0 || iz >= g.N[2])) return;
+  float ey = dy > 0 ? (float)dy - p.uy : (dy < 0 ? p.uy - (float)(dy + 1) : 0.0f);
+  float ez = DIM == 3 ? (dz > 0 ? (float)dz - p.uz : (dz < 0 ? p.uz - (float)(dz + 1) : 0.0f)) : 0.0f;
+  ey = fmaxf(0.0f, ey - kWalkSlack);
+  ez = fmaxf(0.0f, ez - kWalkSlack);
+  const float rem = rr2 - ey * ey - ez * ez;
+  if (rem < 0.0f) return;
+  const float reach = __builtin_amdgcn_sqrtf(rem) + kWalkSlack;
+  int x0 = p.cx + (int)floorf(p.ux - reach);
+  int x1 = p.cx + (int)floorf(p.ux + reach);
+  x0 = max(x0, max(p.cx - g.reach, 0));
+  x1 = min(x1, min(p.cx + g.reach, g.N[0] - 1));
+  if (x0 > x1) return;
+  const uint32_t k0 = cell_key(g, x0, iy, iz);
+  const uint32_t k1 = k0 + (uint32_t)(x1 - x0) + 1u;
+  fb = cs_f[k0];
+  fl = cs_f[k1] - fb;
+  db = nf + cs_d[k0];
+  dl = nf + cs_d[k1] - db;
+}
+
+// Per-wave tables of one particle's row windows (LDS), for kBlock-thread blocks.
+struct RowTables {
+  uint32_t pre[kBlock / 64][64], fb[kBlock / 64][64], fl[kBlock / 64][64], db[kBlock / 64][64];
+};
+
+// Lays one particle's row windows out as one index range [0, M) (rows in
+// walk order, each row's fluid window before its dummy window) and returns
+// M; record_of() then maps an index to its record.  Called by the whole wave.
+template <int DIM>
+__device__ __forceinline__ uint32_t rows_layout(RowTables &t, const Grid &g, const CellPos &p, float two_h,
+                                                const uint32_t *__restrict__ cs_f,
+                                                const uint32_t *__restrict__ cs_d, uint32_t nf, int &nrows) {
+  const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+  const int side = 2 * g.reach + 1;
+  nrows = DIM == 3 ? side * side : side;
+  const float rr = two_h * (float)g.invR;
+  const float rr2 = rr * rr * (1.0f + 4.0f * kWalkSlack);
+  uint32_t fb = 0, fl = 0, db = 0, dl = 0;
+  if (lane < nrows) row_windows<DIM>(g, p, rr2, lane, cs_f, cs_d, nf, fb, fl, db, dl);
+  const uint32_t len = fl + dl;
+  uint32_t incl = len;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  t.pre[wv][lane] = incl - len;
+  t.fb[wv][lane] = fb;
+  t.fl[wv][lane] = fl;
+  t.db[wv][lane] = db;
+  wave_lds_sync();
+  return __shfl(incl, 63, 64);
+}
+
+// Record of index idx < M of the layout (the row is the last one whose
+// prefix does not exceed idx; it is never an empty row).
+__device__ __forceinline__ uint32_t record_of(const RowTables &t, int nrows, uint32_t idx) {
+  const int wv = (int)(threadIdx.x >> 6);
+  int lo = 0, hi = nrows - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t.pre[wv][mid] <= idx) lo = mid;
+    else hi = mid - 1;
+  }
+  const uint32_t off = idx - t.pre[wv][lo];
+  return off < t.fl[wv][lo] ? t.fb[wv][lo] + off : t.db[wv][lo] + (off - t.fl[wv][lo]);
 }
 
 }  // namespace wb

@@ -341,7 +341,6 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
       if (FEAT) {
         S0f += wr * b1.w;  // W / W(dx) V
         S.qmin = fminf(S.qmin, s);
-        S.ndum += (j >= nf) ? 1u : 0u;
       }
     }
 #pragma unroll
@@ -375,7 +374,8 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
   coop_init(cw, g, active, (float)P.two_h, DIM);
   for (;;) {
     const bool fin =
-        coop_fill<DIM, kMList, kMBatch>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, load, near);
+        coop_fill<DIM, kMList, kMBatch, FEAT>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, S.ndum,
+                                         load, near);
     run_list(cnt);
     cnt = 0;
     if (fin) break;
@@ -414,58 +414,57 @@ hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, 
 
 // ------------------------------------------------------- scan-region pass
 
+// The scan-region test of the FP64 path (one wave per candidate) on
+// positions reconstructed in FP64 from cell and offset.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_scan_mixed(Phys P, Grid g, MixedRec rec, const uint32_t *__restrict__ cs_f,
                                                     const uint32_t *__restrict__ cs_d, uint32_t nf,
                                                     const uint32_t *__restrict__ list,
                                                     const uint32_t *__restrict__ count, Rates out, Scalars *sc) {
+  __shared__ RowTables tab;
   const uint32_t total = *count;
-  const double two_h2_scan = 2.0 * P.h * P.h;
-  const double h2 = P.h * P.h;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+  uint32_t nfs = 0;  // surface particles found by this wave (one atomic add at the end)
+  for (uint32_t k = gw; k < total; k += nw) {
     const uint32_t i = list[k];
     const float4 a = rec.r0[i];
     const uint32_t ci = __float_as_uint(a.w);
     const double px = pos_of(g.lo[0], g.R, cell_x(ci), a.x), py = pos_of(g.lo[1], g.R, cell_y(ci), a.y),
                  pz = DIM == 3 ? pos_of(g.lo[2], g.R, cell_z(ci), a.z) : 0.0;
-    const double n0 = out.nrm[0][i], n1 = out.nrm[1][i], n2 = DIM == 3 ? out.nrm[2][i] : 0.0;
-    const double T0 = px + P.h * n0, T1 = py + P.h * n1, T2 = DIM == 3 ? pz + P.h * n2 : 0.0;
-    RowWalker w;
-    walker_init_cell<DIM>(w, g, cell_x(ci), cell_y(ci), cell_z(ci), a.x, a.y, a.z, P.two_h);
+    const double n[3] = {out.nrm[0][i], out.nrm[1][i], DIM == 3 ? out.nrm[2][i] : 0.0};
+    const double T[3] = {px + P.h * n[0], py + P.h * n[1], DIM == 3 ? pz + P.h * n[2] : 0.0};
+    CellPos cp;
+    cp.cx = cell_x(ci);
+    cp.cy = cell_y(ci);
+    cp.cz = DIM == 3 ? cell_z(ci) : 0;
+    cp.ux = a.x * (float)g.invR;
+    cp.uy = a.y * (float)g.invR;
+    cp.uz = DIM == 3 ? a.z * (float)g.invR : 0.0f;
+    int nrows;
+    const uint32_t M = rows_layout<DIM>(tab, g, cp, (float)P.two_h, cs_f, cs_d, nf, nrows);
     bool covered = false;
-    while (!covered && walker_next<DIM>(w, g, cs_f, cs_d, nf)) {
-      for (uint32_t j = w.cur; j < w.end && !covered; ++j) {
-        if (j == i) continue;
-        const float4 b = rec.r0[j];
-        const uint32_t cj = __float_as_uint(b.w);
-        const double qx = pos_of(g.lo[0], g.R, cell_x(cj), b.x), qy = pos_of(g.lo[1], g.R, cell_y(cj), b.y),
-                     qz = DIM == 3 ? pos_of(g.lo[2], g.R, cell_z(cj), b.z) : 0.0;
-        const double s2 = (qx - px) * (qx - px) + (qy - py) * (qy - py) + (qz - pz) * (qz - pz);
-        if (s2 > P.two_h2) continue;
-        const double d0 = qx - T0, d1 = qy - T1, d2 = DIM == 3 ? qz - T2 : 0.0;
-        if (s2 >= two_h2_scan) {
-          covered = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
-        } else {
-          const double dn = n0 * d0 + n1 * d1 + n2 * d2;
-          const double e0 = d0 - dn * n0, e1 = d1 - dn * n1, e2 = d2 - dn * n2;
-          covered = fabs(dn) + sqrt(e0 * e0 + e1 * e1 + e2 * e2) < P.h;
+    for (uint32_t c0 = 0; c0 < M && !covered; c0 += 64u) {
+      bool cov = false;
+      const uint32_t idx = c0 + (uint32_t)lane;
+      if (idx < M) {
+        const uint32_t j = record_of(tab, nrows, idx);
+        if (j != i) {
+          const float4 b = rec.r0[j];
+          const uint32_t cj = __float_as_uint(b.w);
+          const double q[3] = {pos_of(g.lo[0], g.R, cell_x(cj), b.x), pos_of(g.lo[1], g.R, cell_y(cj), b.y),
+                               DIM == 3 ? pos_of(g.lo[2], g.R, cell_z(cj), b.z) : 0.0};
+          const double s2 = (q[0] - px) * (q[0] - px) + (q[1] - py) * (q[1] - py) + (q[2] - pz) * (q[2] - pz);
+          cov = s2 <= P.two_h2 && scan_covers<DIM>(P, q, T, n, s2);
         }
       }
+      covered = __ballot(cov) != 0ull;
     }
-    uint32_t fl = out.flags[i] | kFlagByScan;
-    if (!covered) {
-      fl |= kFlagFS;
-      if ((P.flags & SPH_F_FS_PROJECT) && (P.flags & SPH_F_PST)) {
-        double u0 = out.dus[0][i], u1 = out.dus[1][i], u2 = DIM == 3 ? out.dus[2][i] : 0.0;
-        double d = u0 * n0 + u1 * n1 + u2 * n2;
-        out.dus[0][i] = u0 - d * n0;
-        out.dus[1][i] = u1 - d * n1;
-        if (DIM == 3) out.dus[2][i] = u2 - d * n2;
-      }
-      atomicAdd(&sc->n_fs, 1u);
-    }
-    out.flags[i] = fl;
+    wave_lds_sync();  // the tables are rewritten for the next candidate
+    if (lane == 0) scan_finish<DIM>(P, out, i, n, covered);
+    nfs += covered ? 0u : 1u;
   }
+  if (lane == 0 && nfs) atomicAdd(&sc->n_fs, nfs);
 }
 
 hipError_t launch_scan_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,

@@ -187,7 +187,6 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
     if (FEAT) {
       S.S0 += (float)(wr * b1.w);  // W / W(dx) V
       S.qmin = fminf(S.qmin, (float)s);
-      S.ndum += (j >= nf) ? 1u : 0u;
     }
   };
   // consume the first cnt entries of this lane's list
@@ -231,7 +230,8 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
   coop_init(cw, g, active, (float)P.two_h, DIM);
   for (;;) {
     const bool fin =
-        coop_fill<DIM, kList, kBatch>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, load, near);
+        coop_fill<DIM, kList, kBatch, FEAT>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, S.ndum,
+                                         load, near);
     run_list(cnt);
     cnt = 0;
     if (fin) break;
@@ -360,54 +360,48 @@ hipError_t launch_features(const Phys &P, const Rates &out, const uint32_t *list
 // Candidates (lambda_lo < lambda <= lambda_hi) are on the free surface unless
 // a neighbour lies in the umbrella-shaped region around T = x_i + h n: beyond
 // sqrt(2) h from i within h of T, or closer than sqrt(2) h to i with
-// |n.(x_j - T)| + |tangential part| < h.  Grid-stride over the device-counted
+// |n.(x_j - T)| + |tangential part| < h.  One wave per candidate: the lanes
+// take the candidate's rows (one row each) and then its neighbour candidates
+// 64 at a time, until one covers it.  Grid-stride over the device-counted
 // list, so the launch does not depend on the count.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_scan_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
                                                   const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
                                                   uint32_t nf, const uint32_t *__restrict__ list,
                                                   const uint32_t *__restrict__ count, Rates out, Scalars *sc) {
+  __shared__ RowTables tab;
   const uint32_t total = *count;
-  const double two_h2_scan = 2.0 * P.h * P.h;
-  const double h2 = P.h * P.h;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint32_t gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+  uint32_t nfs = 0;  // surface particles found by this wave (one atomic add at the end)
+  for (uint32_t k = gw; k < total; k += nw) {
     const uint32_t i = list[k];
     const double4 a = rec0[i];
-    const double n0 = out.nrm[0][i], n1 = out.nrm[1][i], n2 = DIM == 3 ? out.nrm[2][i] : 0.0;
-    const double T0 = a.x + P.h * n0, T1 = a.y + P.h * n1, T2 = DIM == 3 ? a.z + P.h * n2 : 0.0;
-    RowWalker w;
-    walker_init<DIM>(w, g, a.x, a.y, a.z, P.two_h);
+    const double n[3] = {out.nrm[0][i], out.nrm[1][i], DIM == 3 ? out.nrm[2][i] : 0.0};
+    const double T[3] = {a.x + P.h * n[0], a.y + P.h * n[1], DIM == 3 ? a.z + P.h * n[2] : 0.0};
+    const CellPos cp = cellpos_of<DIM>(g, a.x, a.y, a.z);
+    int nrows;
+    const uint32_t M = rows_layout<DIM>(tab, g, cp, (float)P.two_h, cs_f, cs_d, nf, nrows);
     bool covered = false;
-    while (!covered && walker_next<DIM>(w, g, cs_f, cs_d, nf)) {
-      for (uint32_t j = w.cur; j < w.end && !covered; ++j) {
-        if (j == i) continue;
-        const double4 b = rec0[j];
-        const double s2 = dist2_exact<DIM>(b.x - a.x, b.y - a.y, b.z - a.z);
-        if (s2 > P.two_h2) continue;
-        const double d0 = b.x - T0, d1 = b.y - T1, d2 = DIM == 3 ? b.z - T2 : 0.0;
-        if (s2 >= two_h2_scan) {
-          covered = (d0 * d0 + d1 * d1 + d2 * d2) < h2;
-        } else {
-          const double dn = n0 * d0 + n1 * d1 + n2 * d2;
-          const double e0 = d0 - dn * n0, e1 = d1 - dn * n1, e2 = d2 - dn * n2;
-          covered = fabs(dn) + sqrt(e0 * e0 + e1 * e1 + e2 * e2) < P.h;
+    for (uint32_t c0 = 0; c0 < M && !covered; c0 += 64u) {
+      bool cov = false;
+      const uint32_t idx = c0 + (uint32_t)lane;
+      if (idx < M) {
+        const uint32_t j = record_of(tab, nrows, idx);
+        if (j != i) {
+          const double4 b = rec0[j];
+          const double q[3] = {b.x, b.y, DIM == 3 ? b.z : 0.0};
+          const double s2 = dist2_exact<DIM>(b.x - a.x, b.y - a.y, b.z - a.z);
+          cov = s2 <= P.two_h2 && scan_covers<DIM>(P, q, T, n, s2);
         }
       }
+      covered = __ballot(cov) != 0ull;
     }
-    uint32_t fl = out.flags[i] | kFlagByScan;
-    if (!covered) {
-      fl |= kFlagFS;
-      if ((P.flags & SPH_F_FS_PROJECT) && (P.flags & SPH_F_PST)) {
-        double u0 = out.dus[0][i], u1 = out.dus[1][i], u2 = DIM == 3 ? out.dus[2][i] : 0.0;
-        double d = u0 * n0 + u1 * n1 + u2 * n2;
-        out.dus[0][i] = u0 - d * n0;
-        out.dus[1][i] = u1 - d * n1;
-        if (DIM == 3) out.dus[2][i] = u2 - d * n2;
-      }
-      atomicAdd(&sc->n_fs, 1u);
-    }
-    out.flags[i] = fl;
+    wave_lds_sync();  // the tables are rewritten for the next candidate
+    if (lane == 0) scan_finish<DIM>(P, out, i, n, covered);
+    nfs += covered ? 0u : 1u;
   }
+  if (lane == 0 && nfs) atomicAdd(&sc->n_fs, nfs);
 }
 
 hipError_t launch_scan_f64(const Phys &P, const Grid &g, const double4 *rec0, const uint32_t *cs_f,

@@ -188,4 +188,36 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
   if ((threadIdx.x & 63) == 0 && tc) atomicAdd(&sc->tests, tc);
 }
 
+// Scan-region test of neighbour q (squared distance s2 <= (2h)^2) for a
+// candidate with normal n and T = x_i + h n.
+template <int DIM>
+__device__ __forceinline__ bool scan_covers(const Phys &P, const double q[3], const double T[3], const double n[3],
+                                            double s2) {
+  const double d0 = q[0] - T[0], d1 = q[1] - T[1], d2 = DIM == 3 ? q[2] - T[2] : 0.0;
+  if (s2 >= 2.0 * P.h * P.h) return (d0 * d0 + d1 * d1 + d2 * d2) < P.h * P.h;
+  const double dn = n[0] * d0 + n[1] * d1 + n[2] * d2;
+  const double e0 = d0 - dn * n[0], e1 = d1 - dn * n[1], e2 = d2 - dn * n[2];
+  return fabs(dn) + sqrt(e0 * e0 + e1 * e1 + e2 * e2) < P.h;
+}
+
+// Outcome of the scan-region test for candidate i: flags and the tangential
+// projection of the shifting velocity at the surface (the caller counts the
+// surface particles).
+template <int DIM>
+__device__ __forceinline__ void scan_finish(const Phys &P, const Rates &out, uint32_t i, const double n[3],
+                                            bool covered) {
+  uint32_t fl = out.flags[i] | kFlagByScan;
+  if (!covered) {
+    fl |= kFlagFS;
+    if ((P.flags & SPH_F_FS_PROJECT) && (P.flags & SPH_F_PST)) {
+      const double u0 = out.dus[0][i], u1 = out.dus[1][i], u2 = DIM == 3 ? out.dus[2][i] : 0.0;
+      const double d = u0 * n[0] + u1 * n[1] + u2 * n[2];
+      out.dus[0][i] = u0 - d * n[0];
+      out.dus[1][i] = u1 - d * n[1];
+      if (DIM == 3) out.dus[2][i] = u2 - d * n[2];
+    }
+  }
+  out.flags[i] = fl;
+}
+
 }  // namespace wb

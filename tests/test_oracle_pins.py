@@ -124,10 +124,13 @@ def test_cells_closed_form(orc):
 
 
 # ------------------------------------------------------------- eigenvalues
-def test_closed_form_eigenvalues_match_lapack(orc):
+def test_eigenvalues_match_lapack(orc):
+    """Eigenvalues of sym(L) (Sec. 3) equal LAPACK's to a few ulps of |S|,
+    also for repeated and nearly repeated eigenvalues (lattice rows by a wall
+    give L = diag(a, a, b) up to round-off), negative and zero spectra."""
     rng = np.random.default_rng(5)
     mats = []
-    for _ in range(200):
+    for _ in range(300):
         for d in (2, 3):
             A = rng.normal(size=(d, d))
             mats.append(A @ A.T)
@@ -136,11 +139,19 @@ def test_closed_form_eigenvalues_match_lapack(orc):
             ev = rng.normal(size=d)
             ev[-1] = ev[0]  # repeated eigenvalue
             mats.append(Q @ np.diag(ev) @ Q.T)
+            E = rng.normal(size=(d, d)) * 1e-16
+            a, b = 1.0 + 0.1 * rng.normal(), 0.7 + 0.1 * rng.normal()
+            mats.append(np.diag([a, a, b][:d]) + E + E.T)  # nearly repeated
+            mats.append(np.full((d, d), rng.normal()))  # rank one, zeros
     for S in mats:
         d = S.shape[0]
         ref = np.linalg.eigvalsh(S)
-        got = orc.eigvals(d, S)
-        assert np.allclose(np.sort(got), ref, atol=1e-12 * max(1.0, np.abs(ref).max()))
+        got = orc.eigvals(d, S)[:d]
+        assert np.all(np.diff(got) >= 0)
+        assert np.abs(got - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+    # asymmetric input: its symmetric part is what is diagonalised
+    S = rng.normal(size=(3, 3))
+    assert np.abs(orc.eigvals(3, S) - np.linalg.eigvalsh(0.5 * (S + S.T))).max() <= 1e-14 * 4
 
 
 # ---------------------------------------------- first-order consistency
@@ -435,3 +446,23 @@ def test_mirror_dummy_hand_built(orc):
     assert r["mir_phi"][2] == pytest.approx(2.0 + (-9.81) * (-0.005 - 0.01), abs=1e-15)
     assert np.allclose(r["mir_u"][2], [0.3, 0.0])
     assert r["mir_src"][3] == -1
+
+
+def test_sampled_rows_equal_full_evaluation(orc):
+    """Evaluating a sample of rows (lists built for those rows and the dummies
+    they touch) gives bit for bit the full evaluation's values on the sample:
+    the sampled mode used against the GPU at full size drops no term."""
+    case = wl.box3d(0.03, (0.6, 0.3, 0.45), (0.3, 0.3, 0.3))
+    case = wl.with_params(case, delta_sph=True, pst=True, tic=True, fs_mode="exact")
+    case = wl.random_velocity(wl.jitter(case, 0.05, 3), 0.05, 4)
+    full = orc.eval_rates(case)
+    f = np.nonzero(case["kind"] == 0)[0]
+    rng = np.random.default_rng(5)
+    top = f[np.argsort(case["x"][f, 2])[-20:]]
+    rows = np.unique(np.concatenate([rng.choice(f, 60, replace=False), top]))
+    sub = orc.eval_rates(case, rows=rows)
+    for k in ("acc", "dphi", "dushift", "lam", "normal", "fs", "tic", "nnb", "feat", "fs_margin"):
+        assert np.array_equal(sub[k][rows], full[k][rows]), k
+    assert full["fs"][top].any()
+    other = np.setdiff1d(f, rows)
+    assert not sub["nnb"][other].any()
