@@ -121,10 +121,13 @@ def run_path(case, label, steps, warmup, clf=None):
     prof = sim.profile_read()
     st = sim.stats()
     sim.profile(False)
-    pairs_rhs = st["pairs"]
-    tests_rhs = st["tests"]
+    kept = st["n_kept"] > 0
+    # pairs and candidate tests of the searching pass: the first stage's when
+    # the second runs from kept lists, else the last pass's (both stages search)
+    pairs_rhs = st["pairs_stage1"] if kept else st["pairs"]
+    tests_rhs = st["tests_stage1"] if kept else st["tests"]
     ms_step = ms_total / steps
-    pair_evals_per_step = 2.0 * pairs_rhs
+    pair_evals_per_step = st["pairs_stage1"] + st["pairs"]
     pair = prof["pair"]
     pair_ms = pair["ms"] / max(pair["launches"], 1)
     flops = pairs_rhs * FLOP_PER_PAIR_3D + tests_rhs * FLOP_PER_TEST_3D
@@ -136,12 +139,20 @@ def run_path(case, label, steps, warmup, clf=None):
         "candidate_tests_per_rhs": tests_rhs,
         "pair_pass_ms": pair_ms,
         "pair_pass_tflops": achieved,
+        "second_stages_from_kept_lists": st["n_kept"],
+        "second_stages_rebuilt": st["n_rebuilt"],
         "kernel_ms_per_step": {k: v["ms"] / steps for k, v in prof.items()},
         "t_end": st["t"],
         "umax_end": st["umax"],
         "fs_count": st["n_fs"],
         "fs_candidates": st["n_cand"],
     }
+    if kept:
+        kp = prof["pair_kept"]
+        kept_ms = kp["ms"] / max(kp["launches"], 1)
+        kflops = st["pairs"] * FLOP_PER_PAIR_3D + st["tests"] * FLOP_PER_TEST_3D
+        out["kept_pass"] = {"ms": kept_ms, "pairs": st["pairs"], "kept_candidates_tested": st["tests"],
+                            "tflops": kflops / (kept_ms * 1e-3) / 1e12}
     if clf is not None:
         out["fs_decided_by_mlp"] = st["n_mlp"]
         out["fs_fallback_exact"] = st["n_scan"]
@@ -316,6 +327,9 @@ def main():
     ap.add_argument("--cell", type=float, default=1.0,
                     help="background cell size in units of h (the paper's R = 2h is 2.0; R = h visits fewer "
                          "candidates for the same neighbour sets)")
+    ap.add_argument("--keep-cell", type=float, default=1.01,
+                    help="cell size in units of h when the first stage's candidate lists serve the second (room "
+                         "for a skin of (2 x keep-cell - 2) h); 0: no kept lists, cells of --cell h")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="fp64,mixed,mixed_learned",
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
@@ -349,13 +363,16 @@ def main():
         log("calibration copy: 1 GiB read + 1 GiB written")
         del src_t, dst_t
     results = {}
+    # every path keeps the first stage's candidate lists for the second (cells
+    # of keep_cell h, room for the skin) unless --keep-cell 0
+    run_case = case if args.keep_cell <= 0 else wl.with_params(case, cell_size=args.keep_cell * h, keep_lists=True)
     for path in args.paths.split(","):
         if path == "fp64":
-            results["fp64"] = run_path(case, "fp64", args.steps, args.warmup)
+            results["fp64"] = run_path(run_case, "fp64", args.steps, args.warmup)
         elif path == "mixed":
-            results["mixed"] = run_path(wl.with_params(case, precision="mixed"), "mixed", args.steps, args.warmup)
+            results["mixed"] = run_path(wl.with_params(run_case, precision="mixed"), "mixed", args.steps, args.warmup)
         elif path == "mixed_learned":
-            results["mixed_learned"] = run_path(wl.with_params(case, precision="mixed", fs_mode="learned"),
+            results["mixed_learned"] = run_path(wl.with_params(run_case, precision="mixed", fs_mode="learned"),
                                                 "mixed_learned", args.steps, args.warmup, clf=load_classifier())
         else:
             raise SystemExit(f"unknown path {path}")
@@ -379,7 +396,7 @@ def main():
                                  "peak": prof["valu_issue_peak"], "from": f"profiles/{key}_slosh3d_pmc.json"}
         return out
 
-    roof = roofline(head, "pair_f64", "k_pair_f64<3,false,true> (fused pair pass, FP64)")
+    roof = roofline(head, "pair_f64", "k_pair_f64<3,false,true,true> (search and pair pass of the first stage, keeping its candidates, FP64)")
     out = {
         "metric": METRIC, "value": head["pair_evals_per_s"], "unit": "pair-evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -387,7 +404,9 @@ def main():
         "data": "synthetic (seeded lattice tank, hydrostatic start, tank-frame forcing)",
         "config": {"workload": (f"3D sloshing tank 1.0x0.5x0.56 m, depth 0.28 m, dx={args.dx}: "
                                 f"{case['meta']['n_fluid']} fluid + {case['meta']['n_dummy']} dummies"),
-                   "path": "fp64", "cell_size_over_h": args.cell, "fs_mode": "exact",
+                   "path": "fp64", "fs_mode": "exact",
+                   "cell_size_over_h": args.keep_cell if args.keep_cell > 0 else args.cell,
+                   "second_stage": "kept candidate lists" if args.keep_cell > 0 else "rebuild and search",
                    "parallelism": "single GPU"},
         "roofline": roof,
         "paths": results,

@@ -66,6 +66,18 @@ typedef int32_t sph_status;
 #define SPH_F_FEATURES 32u   /* keep the 16 classifier features of every fluid  */
                              /* particle (without it, the learned mode computes */
                              /* them for free-surface candidates only)          */
+#define SPH_F_KEEP_LISTS 64u /* the first stage of a step keeps its candidate   */
+                             /* lists (radius 2h + s, s = 3 dt U_max plus a     */
+                             /* rounding margin: twice the bound on a           */
+                             /* particle's first-stage move), and the second    */
+                             /* stage runs from them                            */
+                             /* without a sort or a search; needs cells with    */
+                             /* room for s: ceil(2h/R) R - 2h > s.  A step that */
+                             /* lacks the room, or whose lists overflow 256     */
+                             /* entries per particle, rebuilds as without the   */
+                             /* flag.  Neighbour sets, and so results, are the  */
+                             /* same; about 1 KiB of workspace per fluid        */
+                             /* particle.                                       */
 
 typedef struct sph_params {
     int32_t dim;        /* 2 or 3; gravity usually along the last axis          */
@@ -142,7 +154,9 @@ sph_status sph_build_cells(sph_ctx *ctx);
  * the state at the start of each step, computed on the device.  Each stage:
  * rebuild cells, mirror dummies (Eq. phiBn, slip), fused pair pass and
  * epilogue (Eqs. renorm, parGrad, lfsover, sph; delta-SPH, shifting, TIC),
- * free-surface detection, stage update.  Asynchronous. */
+ * free-surface detection, stage update.  Asynchronous, except that with
+ * SPH_F_KEEP_LISTS each step waits once for its first stage (to choose how
+ * the second runs). */
 sph_status sph_step(sph_ctx *ctx, int32_t nsteps, double dt_override);
 
 /* One right-hand side at the current state and time (no integration):
@@ -189,13 +203,17 @@ sph_status sph_fields(sph_ctx *ctx, int32_t field, void *out, int32_t out_on_dev
  * [10] singular-L count, [11] sum of fluid neighbour counts of the last
  * right-hand side (ordered pairs), [12] free-surface candidates of the last
  * right-hand side, [13] candidate pairs the last pair pass tested (distance
- * computations).  Synchronises. */
-sph_status sph_stats(sph_ctx *ctx, double out[16]);
+ * computations), [14] second stages run from kept candidate lists
+ * (SPH_F_KEEP_LISTS), [15] second stages that rebuilt instead (no room for
+ * the skin, or a list overflow), [16] and [17] the values of [11] and [13]
+ * for the first stage of the last step, [18], [19] zero.  Synchronises. */
+sph_status sph_stats(sph_ctx *ctx, double out[20]);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
- * each launch group while enabled: [0] pair pass, [1] wall mirror, [2] grid
- * rebuild (hash, sort, reorder), [3] free-surface detection, [4] stage
- * updates and reductions.  sph_profile_read synchronises and writes
+ * each launch group while enabled: [0] pair pass with its own search, [1]
+ * wall mirror, [2] grid rebuild (hash, sort, reorder; or the record refresh of
+ * a second stage from kept lists), [3] free-surface detection, [4] stage
+ * updates and reductions, [5] pair pass from kept lists.  sph_profile_read synchronises and writes
  * out[2k] = total milliseconds and out[2k+1] = launch count of group k, then
  * clears the totals. */
 sph_status sph_profile(sph_ctx *ctx, int32_t enable);

@@ -62,6 +62,10 @@ struct sph_ctx {
   Rates r;
   uint32_t *cand, *fallback;
   float *cand_logit;
+  // candidate lists kept from a step's first stage (SPH_F_KEEP_LISTS)
+  uint32_t *kent;
+  uint32_t *kcnt, *knch;
+  double n_kept, n_rebuilt;  // second stages run from them / rebuilt instead
   Scalars *sc;
   unsigned char *stage;
   size_t stage_bytes;
@@ -134,7 +138,7 @@ bool params_ok(const sph_params *p, std::string *why) {
   if (ncell > 2.0e9) return bad("too many cells");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->gravity[a]) || !std::isfinite(p->forcing_amp[a])) return bad("non-finite body force");
-  if (p->flags & ~63u) return bad("unknown flag bits");
+  if (p->flags & ~127u) return bad("unknown flag bits");
   return true;
 }
 
@@ -186,6 +190,18 @@ void derive(const sph_params *p, Phys &P, Grid &g) {
   g.R = p->cell_size > 0 ? p->cell_size : 2.0 * p->h;
   g.invR = 1.0 / g.R;
   g.reach = (int32_t)std::ceil(2.0 * p->h / g.R);
+  P.win = P.two_h;
+  // cells of reach R cover a ball of radius reach R around any point; the
+  // kept lists need 2h + skin inside it (a small margin keeps the cut away
+  // from the rounding of cell indices)
+  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u;
+  P.skin_max = keep ? std::max(0.0, (double)g.reach * g.R - P.two_h - 1e-6 * g.R) : 0.0;
+  // absolute part of the skin: far above the rounding of FP64 positions; on
+  // the mixed path, above twice the rounding of the FP32 absolute positions
+  // and of the FP32 distance test
+  double xmax = 0.0;
+  for (int a = 0; a < p->dim; ++a) xmax = std::max(xmax, std::max(std::fabs(p->domain_lo[a]), std::fabs(p->domain_hi[a])));
+  P.skin_pad = p->precision == SPH_MIXED ? 1e-6 * xmax + 1e-5 * p->h : 1e-9 * p->h;
   g.ncell = 1;
   for (int a = 0; a < 3; ++a) {
     g.lo[a] = p->domain_lo[a];
@@ -291,6 +307,15 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   c->r.logit = cv.take<float>(nf);
   c->cand = cv.take<uint32_t>(nf);
   c->fallback = cv.take<uint32_t>(nf);
+  if (c->P.skin_max > 0.0) {
+    const int64_t np = (int64_t)grid_for(std::max<int64_t>(nf, 1)) * kBlock;
+    c->kent = cv.take<uint32_t>((int64_t)kKeepChunks * kPairList * np);
+    c->kcnt = cv.take<uint32_t>((int64_t)kKeepChunks * np);
+    c->knch = cv.take<uint32_t>(np);
+  } else {
+    c->kent = nullptr;
+    c->kcnt = c->knch = nullptr;
+  }
   c->cand_logit = c->p.fs_mode == SPH_FS_LEARNED ? cv.take<float>(nf) : nullptr;
   c->clf.w = cv.take<float>(kMlpParams);
   c->clf.mean = cv.take<float>(kNFeat);
@@ -359,28 +384,43 @@ sph_status rebuild(sph_ctx *c, int with_stage0) {
   return hip_check(c, e, "grid rebuild");
 }
 
-sph_status rhs(sph_ctx *c, int stage) {
+// Records of the current state in the current order (second stage from kept
+// lists: the cells and the order stay those of the first stage).
+sph_status refresh(sph_ctx *c) {
+  ProfScope ps(c, 2);
+  hipError_t e = c->mixed ? launch_refresh_mixed(c->P, c->g, c->mcur, c->nf, c->mrec, c->s)
+                          : launch_refresh_f64(c->P, c->cur, c->nf, c->rec0, c->rec1, c->s);
+  return hip_check(c, e, "record refresh");
+}
+
+// One right-hand side.  mode: the pair pass's kPairSearch / kPairSearchKeep /
+// kPairKept; win_extra widens the cell searches of the mirror and scan passes
+// (second stage over the first stage's cells: half the skin).
+sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra = 0.0) {
   hipError_t e = launch_stage_time(c->sc, stage, c->s);
   const bool feat = (c->p.flags & SPH_F_FEATURES) || c->p.fs_mode == SPH_FS_LEARNED;
+  Phys Pw = c->P;
+  Pw.win = c->P.two_h + win_extra;
   if (!c->mixed) {
     if (e == hipSuccess) {
       ProfScope ps(c, 1);
-      e = launch_mirror_f64(c->P, c->g, c->dm, c->nd, c->rec0, c->rec1, c->rec0 + c->nf, c->rec1 + c->nf, c->cs_f,
+      e = launch_mirror_f64(Pw, c->g, c->dm, c->nd, c->rec0, c->rec1, c->rec0 + c->nf, c->rec1 + c->nf, c->cs_f,
                             (uint32_t)c->nf, c->sc, c->s, c->cur.id);
     }
     if (e == hipSuccess) {
-      ProfScope ps(c, 0);
+      ProfScope ps(c, mode == kPairKept ? 5 : 0);
       e = launch_pair_f64(c->P, c->g, c->rec0, c->rec1, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat,
-                          c->s);
+                          mode, c->kent, c->kcnt, c->knch, c->s);
     }
   } else {
     if (e == hipSuccess) {
       ProfScope ps(c, 1);
-      e = launch_mirror_mixed(c->P, c->g, c->dm, c->nd, c->mrec, c->cs_f, (uint32_t)c->nf, c->sc, c->s, c->mcur.id);
+      e = launch_mirror_mixed(Pw, c->g, c->dm, c->nd, c->mrec, c->cs_f, (uint32_t)c->nf, c->sc, c->s, c->mcur.id);
     }
     if (e == hipSuccess) {
-      ProfScope ps(c, 0);
-      e = launch_pair_mixed(c->P, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat, c->s);
+      ProfScope ps(c, mode == kPairKept ? 5 : 0);
+      e = launch_pair_mixed(c->P, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat,
+                            mode, c->kent, c->kcnt, c->knch, c->s);
     }
   }
   ProfScope ps_fs(c, 3);
@@ -402,9 +442,9 @@ sph_status rhs(sph_ctx *c, int stage) {
     }
     if (e == hipSuccess) {
       if (!c->mixed)
-        e = launch_scan_f64(c->P, c->g, c->rec0, c->cs_f, c->cs_d, (uint32_t)c->nf, list, count, c->r, c->sc, c->s);
+        e = launch_scan_f64(Pw, c->g, c->rec0, c->cs_f, c->cs_d, (uint32_t)c->nf, list, count, c->r, c->sc, c->s);
       else
-        e = launch_scan_mixed(c->P, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, list, count, c->r, c->sc, c->s);
+        e = launch_scan_mixed(Pw, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, list, count, c->r, c->sc, c->s);
     }
   }
   c->rates_current = true;
@@ -538,6 +578,7 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   c->mixed = p->precision == SPH_MIXED;
   c->status = SPH_OK;
   c->has_clf = false;
+  c->n_kept = c->n_rebuilt = 0.0;
   c->profiling = false;
   c->ev_used = 0;
   for (int k = 0; k < 8; ++k) c->prof_ms[k] = c->prof_cnt[k] = 0.0;
@@ -724,17 +765,30 @@ sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
   for (int32_t k = 0; k < nsteps && st == SPH_OK; ++k) {
     st = umax_of_current(c);
     if (st == SPH_OK) st = hip_check(c, launch_dt(c->P, c->sc, dt_override, c->s), "time step");
+    const bool keep = c->kent != nullptr;
     if (st == SPH_OK) st = rebuild(c, 0);
-    if (st == SPH_OK) st = rhs(c, 1);
+    if (st == SPH_OK) st = rhs(c, 1, keep ? kPairSearchKeep : kPairSearch);
     if (st == SPH_OK) {
       ProfScope ps(c, 4);
       hipError_t e = c->mixed ? launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, 1, c->s)
                               : launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, 1, c->s);
       st = hip_check(c, e, "stage 1");
     }
+    // second stage from the kept lists when the step's skin fit the cells and
+    // no wave overflowed them (both known on the device once stage 1 ran)
+    bool kept = false;
+    double skin = 0.0;
+    if (st == SPH_OK && keep) {
+      Scalars h;
+      st = read_scalars(c, &h);
+      kept = st == SPH_OK && h.vok != 0u && h.vovf == 0u && h.err == 0u;
+      skin = h.skin;
+      if (kept) c->n_kept += 1.0;
+      else c->n_rebuilt += 1.0;
+    }
     if (st == SPH_OK) st = umax_of_current(c);
-    if (st == SPH_OK) st = rebuild(c, 1);
-    if (st == SPH_OK) st = rhs(c, 2);
+    if (st == SPH_OK) st = kept ? refresh(c) : rebuild(c, 1);
+    if (st == SPH_OK) st = kept ? rhs(c, 2, kPairKept, 0.5 * skin) : rhs(c, 2);
     if (st == SPH_OK) {
       ProfScope ps(c, 4);
       hipError_t e = c->mixed ? launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, 2, c->s)
@@ -761,12 +815,12 @@ sph_status sph_sync(sph_ctx *c) {
   return sync_errors(c);
 }
 
-sph_status sph_stats(sph_ctx *c, double out[16]) {
+sph_status sph_stats(sph_ctx *c, double out[20]) {
   if (!c || !out) return SPH_EINVAL;
   Scalars h;
   sph_status st = read_scalars(c, &h);
   if (st != SPH_OK) return st;
-  for (int k = 0; k < 16; ++k) out[k] = 0.0;
+  for (int k = 0; k < 20; ++k) out[k] = 0.0;
   out[0] = h.t;
   out[1] = h.dt;
   out[2] = h.steps;
@@ -781,6 +835,10 @@ sph_status sph_stats(sph_ctx *c, double out[16]) {
   out[11] = (double)h.pairs;
   out[12] = h.n_cand;
   out[13] = (double)h.tests;
+  out[14] = c->n_kept;
+  out[15] = c->n_rebuilt;
+  out[16] = (double)h.pairs1;
+  out[17] = (double)h.tests1;
   return c->status != SPH_OK ? c->status : SPH_OK;
 }
 

@@ -19,6 +19,14 @@ constexpr int kBlock = 256;   // threads per block for streaming kernels
 constexpr int kRecPad = 8;
 constexpr int kNFeat = 16;    // classifier features per particle
 constexpr int kMaxReach = 3;  // cells searched each side: ceil(2h / R) <= 3
+// Tag bit of a candidate-list entry kept for the second stage of a step that
+// is not a neighbour at the first (record indices stay below 2^31).
+constexpr uint32_t kSkinTag = 0x80000000u;
+// LDS list entries per lane of the pair passes; candidate lists kept from the
+// first stage to the second: chunks (one LDS list fill) per lane.
+constexpr int kPairList = 32;
+constexpr int kKeepChunks = 8;
+static_assert(kPairList % 8 == 0 && kPairList <= 255, "kept chunks are staged eight entries at a time");
 
 // error bits accumulated on the device
 enum : uint32_t {
@@ -103,6 +111,10 @@ struct Phys {
   double lambda_tic, lambda_lo, lambda_hi, lambda_sing;
   double grav[3], famp[3], fomega;
   double cfl, nu, gmax;   // gmax = max_t |G(t)|
+  double skin_max;        // room for a list skin: reach R - 2h (0: lists not kept)
+  double skin_pad;        // absolute part of the skin (rounding of the positions)
+  double win;             // window radius of the mirror and scan cell searches:
+                          // 2h, wider over the first stage's cells (second stage)
 };
 
 // Device-resident scalars (one instance in the workspace).
@@ -118,8 +130,12 @@ struct Scalars {
   uint32_t n_cand;   // candidates listed by the pair pass
   uint32_t n_scan;   // candidates sent to the scan pass
   uint32_t n_fs, n_cons, n_sing, n_mlp;
-  uint32_t pad_;
+  uint32_t vok;      // this step's first-stage candidate lists serve the second stage
   double steps;
+  double skin;       // their skin: twice the bound on a particle's first-stage move
+  uint32_t vovf;     // a wave's candidates exceeded the kept chunks
+  uint32_t pad2_;
+  unsigned long long pairs1, tests1;  // pairs and tests of the last step's first stage
 };
 
 // Fluid state, FP64 path, sorted by (cell, original index).

@@ -78,7 +78,6 @@ struct CoopWalk {
   bool mem;                 // lane in the group
   int c, ce;                // lane's cursor and end in the current window (record index)
   uint32_t dlo, dhi;        // lane's dummy window of the current row
-  int dmark;                // list count when the current dummy window began
   float rr2;
 };
 
@@ -93,7 +92,6 @@ __device__ __forceinline__ void coop_init(CoopWalk &w, const Grid &g, bool activ
   w.mem = false;
   w.c = w.ce = 0;  // no window yet
   w.dlo = w.dhi = 0;
-  w.dmark = 0;
   w.seg = 2;
 }
 
@@ -181,18 +179,18 @@ __device__ __forceinline__ bool coop_next_row(CoopWalk &w, const Grid &g, const 
 
 // Fills this wave's lists until one lane might overflow (returns false: the
 // caller consumes the lists and calls again) or the search ends (true).
-// load(j) returns record j's position, near(pos, j) the neighbour test.
+// load(j) returns record j's position; near(pos, j) classifies the candidate:
+// 0 rejected, 1 taken, 2 taken with kSkinTag set on its list entry (a
+// candidate kept for later that is not a neighbour now).
 // list_col points at this lane's column (entry k at list_col[k * stride]).
 // Loads run up to BATCH - 1 records past a window's end: the record arrays
 // carry that many padding records.  Requires 2 reach + 2 <= 64 (the union
 // span's cell starts fit one load).
-// COUNT_D: also count the neighbours taken from dummy windows into ndum (from
-// the list counts at the window's ends, nothing per candidate).
-template <int DIM, int LIST, int BATCH, bool COUNT_D, class LoadFn, class NearFn>
+template <int DIM, int LIST, int BATCH, class LoadFn, class NearFn>
 __device__ __forceinline__ bool coop_fill(CoopWalk &w, const Grid &g, const uint32_t *__restrict__ cs_f,
                                           const uint32_t *__restrict__ cs_d, uint32_t nf, const CellPos &p,
                                           uint32_t *list_col, int stride, int &cnt, uint32_t &ntest,
-                                          uint32_t &ndum, LoadFn load, NearFn near) {
+                                          LoadFn load, NearFn near) {
   for (;;) {
     // batches of the current windows (the hot loop: only the cursor and the
     // list count change here)
@@ -201,10 +199,6 @@ __device__ __forceinline__ bool coop_fill(CoopWalk &w, const Grid &g, const uint
     while (__ballot(c < ce)) {
       if (__ballot(cnt > LIST - BATCH)) {
         w.c = c;
-        if (COUNT_D && w.seg == 2) {  // the caller empties the list
-          ndum += (uint32_t)(cnt - w.dmark);
-          w.dmark = 0;
-        }
         return false;
       }
       // idle lanes load record 0 (always present)
@@ -217,9 +211,9 @@ __device__ __forceinline__ bool coop_fill(CoopWalk &w, const Grid &g, const uint
 #pragma unroll
       for (int k = 0; k < BATCH; ++k) {
         const uint32_t j = c0 + (uint32_t)k;
-        const bool take = k < n && near(b[k], j);
-        list_col[cnt * stride] = j;  // branch-free append (cnt <= LIST - BATCH)
-        cnt += take ? 1 : 0;
+        const uint32_t code = k < n ? near(b[k], j) : 0u;
+        list_col[cnt * stride] = j | ((code >> 1) * kSkinTag);  // branch-free append (cnt <= LIST - BATCH)
+        cnt += code != 0u ? 1 : 0;
       }
       ntest += (uint32_t)n;
       c += n;
@@ -229,11 +223,8 @@ __device__ __forceinline__ bool coop_fill(CoopWalk &w, const Grid &g, const uint
       w.seg = 2;
       w.c = (int)w.dlo;
       w.ce = (int)w.dhi;
-      if (COUNT_D) w.dmark = cnt;
       continue;
     }
-    if (COUNT_D) ndum += (uint32_t)(cnt - w.dmark);
-    w.dmark = cnt;  // (unused until the next dummy window)
     if (!coop_next_row<DIM>(w, g, cs_f, cs_d, nf, p)) return true;
   }
 }

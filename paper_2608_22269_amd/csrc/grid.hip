@@ -317,4 +317,29 @@ hipError_t launch_reorder_f64(const Phys &P, const uint32_t *perm, int64_t n, co
   return hipGetLastError();
 }
 
+// Neighbour-facing records of the FP64 state in its current order, without a
+// sort (second stage of a step that keeps the first stage's candidates).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_refresh_f64(Phys P, FluidF64 f, int64_t n, double4 *__restrict__ rec0,
+                                                     double4 *__restrict__ rec1) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double x = f.x[0][k], y = f.x[1][k], z = DIM == 3 ? f.x[2][k] : 0.0;
+  const double u = f.u[0][k], v = f.u[1][k], w = DIM == 3 ? f.u[2][k] : 0.0;
+  const double ph = f.phi[k];
+  const double V = f.m[k] / (P.rho0 * exp(ph * P.inv_c02));
+  rec0[k] = make_double4(x, y, z, ph);
+  rec1[k] = make_double4(u, v, w, V);
+}
+
+hipError_t launch_refresh_f64(const Phys &P, const FluidF64 &f, int64_t n, double4 *rec0, double4 *rec1,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_refresh_f64<2>, dim3(grid_for(n)), dim3(kBlock), 0, s, P, f, n, rec0, rec1);
+  else
+    hipLaunchKernelGGL(k_refresh_f64<3>, dim3(grid_for(n)), dim3(kBlock), 0, s, P, f, n, rec0, rec1);
+  return hipGetLastError();
+}
+
 }  // namespace wb

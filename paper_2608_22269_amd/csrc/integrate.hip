@@ -62,9 +62,20 @@ __global__ void k_dt(Phys P, Scalars *sc, double dt_override) {
   if (P.nu > 0.0) dt = fmin(dt, P.dx * P.dx / (2.0 * P.nu));
   if (P.gmax > 0.0) dt = fmin(dt, sqrt(2.0 * P.dx / P.gmax));
   dt *= P.cfl;
-  sc->dt = dt_override > 0.0 ? dt_override : dt;
+  dt = dt_override > 0.0 ? dt_override : dt;
+  sc->dt = dt;
   sc->umax = umax;
   sc->t_rhs = sc->t;
+  // Candidate lists of the first stage for the second: the first stage moves
+  // a particle by dt |U + dU| <= 1.5 dt U_max (|U| <= U_max, the shifting
+  // velocity is clamped to U_max / 2), so a pair within 2h after it was
+  // within 2h + 3 dt U_max before.  A relative margin above the rounding of
+  // this bound and of FP32 velocities, and an absolute one (P.skin_pad)
+  // above the rounding of the positions and of the distance tests.
+  const double skin = 3.0 * dt * umax * (1.0 + 1e-6) + P.skin_pad;
+  const bool ok = P.skin_max > 0.0 && skin <= P.skin_max;
+  sc->vok = ok ? 1u : 0u;
+  sc->skin = ok ? skin : 0.0;
 }
 
 hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t s) {
@@ -75,6 +86,10 @@ hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t
 // Stage bookkeeping: U_max of the stage and the time of its right-hand side
 // (stage 1 at t, stage 2 at t + dt); statistics counters restart.
 __global__ void k_stage_time(Scalars *sc, int stage) {
+  if (stage == 2) {
+    sc->pairs1 = sc->pairs;
+    sc->tests1 = sc->tests;
+  }
   sc->umax = sqrt(__longlong_as_double((long long)sc->umax2_bits));
   sc->t_rhs = stage == 2 ? sc->t + sc->dt : sc->t;
   sc->n_cand = 0;
@@ -85,6 +100,7 @@ __global__ void k_stage_time(Scalars *sc, int stage) {
   sc->n_mlp = 0;
   sc->pairs = 0ull;
   sc->tests = 0ull;
+  if (stage == 1) sc->vovf = 0u;
 }
 
 hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s) {

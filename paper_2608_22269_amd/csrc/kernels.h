@@ -15,6 +15,9 @@ hipError_t launch_sort_keys(const Grid &g, int dim, const double *x, const doubl
                             uint32_t *start, uint32_t *perm, Scalars *sc, hipStream_t s);
 hipError_t launch_reorder_f64(const Phys &P, const uint32_t *perm, int64_t n, const FluidF64 &src,
                               const FluidF64 &dst, double4 *rec0, double4 *rec1, int with_stage0, hipStream_t s);
+// records of the FP64 state in its current order (no sort)
+hipError_t launch_refresh_f64(const Phys &P, const FluidF64 &f, int64_t n, double4 *rec0, double4 *rec1,
+                              hipStream_t s);
 
 // Dummy wall particles (static, sorted once by cell).
 struct Dummies {
@@ -27,9 +30,15 @@ struct Dummies {
 hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const double4 *rec0,
                              const double4 *rec1, double4 *drec0, double4 *drec1, const uint32_t *cs_f,
                              uint32_t nf, const Scalars *sc, hipStream_t s, const uint32_t *fid);
+// pair pass modes: own search; own search keeping its candidate lists for the
+// step's second stage (kept lists kent / kcnt / knch, sized for
+// kKeepChunks list fills of kPairList entries per lane of the launch, their
+// counts and a chunk count per lane); second stage from the kept lists
+constexpr int kPairSearch = 0, kPairSearchKeep = 1, kPairKept = 2;
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
-                           uint32_t *cand, bool features, hipStream_t s);
+                           uint32_t *cand, bool features, int mode, uint32_t *kent, uint32_t *kcnt, uint32_t *knch,
+                           hipStream_t s);
 // classifier features from the raw sums of the pair-pass epilogue, for the
 // rows of a device-counted list (count != nullptr) or rows 0 .. n - 1
 hipError_t launch_features(const Phys &P, const Rates &out, const uint32_t *list, const uint32_t *count, uint32_t n,

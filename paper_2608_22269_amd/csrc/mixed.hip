@@ -37,7 +37,7 @@ namespace wb {
 #define WB_MIXED_WAVES_FEAT 4
 #endif
 #define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_MIXED_WAVES_FEAT : WB_MIXED_WAVES)))
-constexpr int kMList = 32;
+constexpr int kMList = kPairList;  // kept lists share the FP64 pass's layout
 constexpr int kMBatch = 4;
 static_assert(kMBatch <= kRecPad, "batched candidate loads run at most kRecPad records past a run");
 
@@ -154,6 +154,39 @@ hipError_t launch_reorder_mixed(const Phys &P, const Grid &g, const uint32_t *pe
   return hipGetLastError();
 }
 
+// Records of the mixed state in its current order, without a sort (second
+// stage of a step that keeps the first stage's candidates).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_refresh_mixed(Phys P, Grid g, FluidMixed f, int64_t n, MixedRec rec) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t c = f.cell[k];
+  float of[3] = {0.f, 0.f, 0.f}, uf[3] = {0.f, 0.f, 0.f};
+  for (int a = 0; a < DIM; ++a) {
+    of[a] = f.o[a][k];
+    uf[a] = f.u[a][k];
+  }
+  const double ph = f.phi[k];
+  const float V = (float)((double)f.m[k] / (P.rho0 * exp(ph * P.inv_c02)));
+  const int cc[3] = {cell_x(c), cell_y(c), cell_z(c)};
+  float xa[3] = {0.f, 0.f, 0.f};
+  for (int a = 0; a < DIM; ++a) xa[a] = (float)pos_of(g.lo[a], g.R, cc[a], of[a]);
+  rec.r0[k] = make_float4(of[0], of[1], of[2], __uint_as_float(c));
+  rec.r1[k] = make_float4(uf[0], uf[1], uf[2], V);
+  rec.phi[k] = ph;
+  rec.xa[k] = make_float4(xa[0], xa[1], xa[2], 0.f);
+}
+
+hipError_t launch_refresh_mixed(const Phys &P, const Grid &g, const FluidMixed &f, int64_t nf, const MixedRec &rec,
+                                hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_refresh_mixed<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, f, nf, rec);
+  else
+    hipLaunchKernelGGL(k_refresh_mixed<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, f, nf, rec);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- mirror
 
 // Dummy records of the mixed path (Sec. 2.4): nearest fluid particle within
@@ -170,7 +203,7 @@ __global__ void __launch_bounds__(256) k_mirror_mixed(Phys P, Grid g, Dummies d,
   const float xf = (float)xd, yf = (float)yd, zf = (float)zd;
   const float two_h2 = (float)P.two_h2;
   RowWalker w;
-  walker_init<DIM>(w, g, xd, yd, zd, P.two_h);
+  walker_init<DIM>(w, g, xd, yd, zd, P.win);
   int64_t best = -1;
   uint32_t best_id = 0;
   float best_r2 = 0.f;
@@ -237,11 +270,143 @@ hipError_t launch_mirror_mixed(const Phys &P, const Grid &g, const Dummies &d, i
 
 // -------------------------------------------------------------- pair pass
 
-// PST4: the shifting exponent is 4 (two squarings); otherwise powf().
+// The particle side of the mixed pair body.
+struct MixedI {
+  int cix, ciy, ciz;
+  double Rd, oxi, oyi, ozi, phii;
+  float4 a1;
+  float inv_h, kfac, alpha, w0inv, c0f, pst_n;
+};
+
+__device__ __forceinline__ MixedI mixed_i(const Phys &P, const Grid &g, const float4 &a0, const float4 &a1,
+                                          double phii) {
+  MixedI I;
+  const uint32_t ci = __float_as_uint(a0.w);
+  I.cix = cell_x(ci);
+  I.ciy = cell_y(ci);
+  I.ciz = cell_z(ci);
+  I.Rd = g.R;
+  I.oxi = a0.x;
+  I.oyi = a0.y;
+  I.ozi = a0.z;
+  I.phii = phii;
+  I.a1 = a1;
+  I.inv_h = (float)P.inv_h;
+  I.kfac = (float)P.kfac;
+  I.alpha = (float)P.alpha;
+  I.w0inv = (float)P.w0inv;
+  I.c0f = (float)P.c0;
+  I.pst_n = (float)P.pst_n;
+  return I;
+}
+
+// FP32 partial sums of one list chunk, flushed into the FP64 totals.
+struct MixedChunk {
+  float gsf[3], Nf[6], Pf[3], Df, S0f;
+};
+
+__device__ __forceinline__ void chunk_zero(MixedChunk &C) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) C.gsf[a] = C.Pf[a] = 0.f;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) C.Nf[a] = 0.f;
+  C.Df = C.S0f = 0.f;
+}
+
+__device__ __forceinline__ void chunk_flush(const MixedChunk &C, PairSums &S) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    S.gs[a] += C.gsf[a];
+    S.Ps[a] += C.Pf[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) S.N[a] += C.Nf[a];
+  S.Ds += C.Df;
+  S.S0 += C.S0f;
+}
+
+// Pair body of the mixed path for neighbour j (records b0, b1, phij).  PST4:
+// the shifting exponent is 4 (two squarings); otherwise powf().
 template <int DIM, bool FEAT, bool PST4>
+__device__ __forceinline__ void mixed_body(const MixedI &I, const float4 &b0, const float4 &b1, const double phij,
+                                           const uint32_t j, const uint32_t nf, MixedChunk &C, PairSums &S) {
+  const uint32_t cj = __float_as_uint(b0.w);
+  // r = (c_j - c_i) R + (o_j - o_i), formed in FP64 from the integer cell
+  // difference and the promoted offsets (one rounding): the same r enters
+  // L and S_R, and phi_j - phi_i of a linear potential equals G.r to FP64
+  // round-off.  Its FP32 rounding feeds the FP32 part of the body.
+  const double rxd = (double)(cell_x(cj) - I.cix) * I.Rd + ((double)b0.x - I.oxi);
+  const double ryd = (double)(cell_y(cj) - I.ciy) * I.Rd + ((double)b0.y - I.oyi);
+  const double rzd = DIM == 3 ? (double)(cell_z(cj) - I.ciz) * I.Rd + ((double)b0.z - I.ozi) : 0.0;
+  const float rx = (float)rxd, ry = (float)ryd, rz = (float)rzd;
+  const float r2 = rx * rx + ry * ry + rz * rz;
+  S.coincident |= (r2 == 0.f);
+  const float is = rsqrtf(r2);
+  const float s = r2 * is;
+  const float q = fminf(s * I.inv_h, 2.0f);
+  const float t = 1.0f - 0.5f * q;
+  const float t2 = t * t, t3 = t2 * t;
+  const float wv = I.kfac * t3 * b1.w;
+  const float gx = wv * rx, gy = wv * ry, gz = wv * rz;
+  // FP64: L, S_R, S_C from the same FP64 r and grad W V = wv r
+  const double wvd = wv;
+  const double gxd = wvd * rxd, gyd = wvd * ryd, gzd = wvd * rzd;
+  S.L[0] += rxd * gxd;
+  S.L[1] += ryd * gyd;
+  S.L[3] += rxd * gyd;
+  if (DIM == 3) {
+    S.L[2] += rzd * gzd;
+    S.L[4] += rxd * gzd;
+    S.L[5] += ryd * gzd;
+  }
+  const double dph = phij - I.phii;
+  const float dux = b1.x - I.a1.x, duy = b1.y - I.a1.y, duz = DIM == 3 ? b1.z - I.a1.z : 0.f;
+  const float dun = (dux * rx + duy * ry + duz * rz) * is;
+  const double c2 = dph - (double)(I.c0f * dun);
+  const double cs = phij + I.phii;
+  S.SR[0] += c2 * gxd;
+  S.SR[1] += c2 * gyd;
+  S.SC[0] += cs * gxd;
+  S.SC[1] += cs * gyd;
+  if (DIM == 3) {
+    S.SR[2] += c2 * gzd;
+    S.SC[2] += cs * gzd;
+  }
+  // FP32 chunk sums
+  C.gsf[0] += gx;
+  C.gsf[1] += gy;
+  if (DIM == 3) C.gsf[2] += gz;
+  C.Nf[0] += dux * gx;
+  C.Nf[1] += duy * gy;
+  C.Nf[3] += dux * gy + duy * gx;
+  if (DIM == 3) {
+    C.Nf[2] += duz * gz;
+    C.Nf[4] += dux * gz + duz * gx;
+    C.Nf[5] += duy * gz + duz * gy;
+  }
+  C.Df += wv * (float)dph;
+  const float W = I.alpha * t2 * t2 * (2.0f * q + 1.0f);
+  const float wr = W * I.w0inv;
+  const float wrn = PST4 ? (wr * wr) * (wr * wr) : powf(wr, I.pst_n);
+  // (W / W(dx))^n grad W V; the epilogue adds grad W V times 1 / R
+  C.Pf[0] += wrn * gx;
+  C.Pf[1] += wrn * gy;
+  if (DIM == 3) C.Pf[2] += wrn * gz;
+  if (FEAT) {
+    C.S0f += wr * b1.w;  // W / W(dx) V
+    S.qmin = fminf(S.qmin, s);
+    S.ndum += j >= nf ? 1u : 0u;
+  }
+}
+
+// The mixed pair pass with its own candidate search (FP32 test on the
+// absolute FP32 positions).  KEEP: as for the FP64 pass -- search radius
+// 2h + skin on the first stage of a step whose skin fits (sc->vok), tagged
+// skin candidates skipped by the body, non-empty list fills kept in kl.
+template <int DIM, bool FEAT, bool PST4, bool KEEP>
 __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     k_pair_mixed(Phys P, Grid g, MixedRec rec, const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
-                 uint32_t nf, Scalars *sc, Rates out, uint32_t *__restrict__ cand) {
+                 uint32_t nf, Scalars *sc, Rates out, uint32_t *__restrict__ cand, KeptLists kl) {
   __shared__ uint32_t list[kMList][kBlock];
   const int tid = threadIdx.x;
   const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + tid;
@@ -255,130 +420,124 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     axa = rec.xa[i];
     phii = rec.phi[i];
   }
-  const uint32_t ci = __float_as_uint(a0.w);
-  const int cix = cell_x(ci), ciy = cell_y(ci), ciz = cell_z(ci);
-
+  const MixedI I = mixed_i(P, g, a0, a1, phii);
   const float two_h2 = (float)P.two_h2;
-  const double Rd = g.R;
-  const double oxi = a0.x, oyi = a0.y, ozi = a0.z;
-  const float inv_h = (float)P.inv_h, kfac = (float)P.kfac, alpha = (float)P.alpha, w0inv = (float)P.w0inv;
-  const float c0f = (float)P.c0;
+  const bool keep = KEEP && sc->vok != 0u;
+  const double rho = keep ? P.two_h + sc->skin : P.two_h;
+  const float rho2 = keep ? (float)(rho * rho) : two_h2;
+  int chunk = 0;
 
   PairSums S;
   sums_zero(S);
 
   // dense pair body over the first cnt entries of this lane's list
   auto run_list = [&](int cnt) {
-    // FP32 partial sums of this chunk (flushed into the FP64 totals below)
-    float gsf[3] = {0.f, 0.f, 0.f}, Nf[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, Pf[3] = {0.f, 0.f, 0.f}, Df = 0.f;
-    float S0f = 0.f;
+    if (keep) {  // copy the fill for the second stage
+      const int kmax = wave_max_int(cnt);
+      const bool room = chunk < kKeepChunks;
+      uint32_t *dst = kl.ent + kept_entry(i, min(chunk, kKeepChunks - 1), 0);
+      for (int k = 0; k < kmax; ++k)
+        if (room && k < cnt) dst[(size_t)k * 64u] = list[k][tid];
+      if (cnt > 0) {
+        if (room) kl.cnt[kept_chunk(i, chunk)] = (uint32_t)cnt;
+        else sc->vovf = 1u;
+        ++chunk;
+      }
+    }
+    MixedChunk C;
+    chunk_zero(C);
     for (int k = 0; k < cnt; ++k) {
-      const uint32_t j = list[k][tid];
-      const float4 b0 = rec.r0[j], b1 = rec.r1[j];
-      const double phij = rec.phi[j];
-      const uint32_t cj = __float_as_uint(b0.w);
-      // r = (c_j - c_i) R + (o_j - o_i), formed in FP64 from the integer cell
-      // difference and the promoted offsets (one rounding): the same r enters
-      // L and S_R, and phi_j - phi_i of a linear potential equals G.r to FP64
-      // round-off.  Its FP32 rounding feeds the FP32 part of the body.
-      const double rxd = (double)(cell_x(cj) - cix) * Rd + ((double)b0.x - oxi);
-      const double ryd = (double)(cell_y(cj) - ciy) * Rd + ((double)b0.y - oyi);
-      const double rzd = DIM == 3 ? (double)(cell_z(cj) - ciz) * Rd + ((double)b0.z - ozi) : 0.0;
-      const float rx = (float)rxd, ry = (float)ryd, rz = (float)rzd;
-      const float r2 = rx * rx + ry * ry + rz * rz;
-      S.coincident |= (r2 == 0.f);
-      const float is = rsqrtf(r2);
-      const float s = r2 * is;
-      const float q = fminf(s * inv_h, 2.0f);
-      const float t = 1.0f - 0.5f * q;
-      const float t2 = t * t, t3 = t2 * t;
-      const float wv = kfac * t3 * b1.w;
-      const float gx = wv * rx, gy = wv * ry, gz = wv * rz;
-      // FP64: L, S_R, S_C from the same FP64 r and grad W V = wv r
-      const double wvd = wv;
-      const double gxd = wvd * rxd, gyd = wvd * ryd, gzd = wvd * rzd;
-      S.L[0] += rxd * gxd;
-      S.L[1] += ryd * gyd;
-      S.L[3] += rxd * gyd;
-      if (DIM == 3) {
-        S.L[2] += rzd * gzd;
-        S.L[4] += rxd * gzd;
-        S.L[5] += ryd * gzd;
-      }
-      const double dph = phij - phii;
-      const float dux = b1.x - a1.x, duy = b1.y - a1.y, duz = DIM == 3 ? b1.z - a1.z : 0.f;
-      const float dun = (dux * rx + duy * ry + duz * rz) * is;
-      const double c2 = dph - (double)(c0f * dun);
-      const double cs = phij + phii;
-      S.SR[0] += c2 * gxd;
-      S.SR[1] += c2 * gyd;
-      S.SC[0] += cs * gxd;
-      S.SC[1] += cs * gyd;
-      if (DIM == 3) {
-        S.SR[2] += c2 * gzd;
-        S.SC[2] += cs * gzd;
-      }
-      // FP32 chunk sums
-      gsf[0] += gx;
-      gsf[1] += gy;
-      if (DIM == 3) gsf[2] += gz;
-      Nf[0] += dux * gx;
-      Nf[1] += duy * gy;
-      Nf[3] += dux * gy + duy * gx;
-      if (DIM == 3) {
-        Nf[2] += duz * gz;
-        Nf[4] += dux * gz + duz * gx;
-        Nf[5] += duy * gz + duz * gy;
-      }
-      Df += wv * (float)dph;
-      const float W = alpha * t2 * t2 * (2.0f * q + 1.0f);
-      const float wr = W * w0inv;
-      const float wrn = PST4 ? (wr * wr) * (wr * wr) : powf(wr, (float)P.pst_n);
-      // (W / W(dx))^n grad W V; the epilogue adds grad W V times 1 / R
-      Pf[0] += wrn * gx;
-      Pf[1] += wrn * gy;
-      if (DIM == 3) Pf[2] += wrn * gz;
-      if (FEAT) {
-        S0f += wr * b1.w;  // W / W(dx) V
-        S.qmin = fminf(S.qmin, s);
-      }
+      const uint32_t e = list[k][tid];
+      if (KEEP && (e & kSkinTag)) continue;
+      const uint32_t j = e;
+      mixed_body<DIM, FEAT, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], j, nf, C, S);
+      if (KEEP) S.nnb += 1;
     }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      S.gs[a] += gsf[a];
-      S.Ps[a] += Pf[a];
-    }
-#pragma unroll
-    for (int a = 0; a < 6; ++a) S.N[a] += Nf[a];
-    S.Ds += Df;
-    S.S0 += S0f;
-    S.nnb += cnt;
+    chunk_flush(C, S);
+    if (!KEEP) S.nnb += cnt;
   };
 
   // candidate search with the rows walked in lockstep by the wave
   CellPos cp;
-  cp.cx = cix;
-  cp.cy = ciy;
-  cp.cz = DIM == 3 ? ciz : 0;
+  cp.cx = I.cix;
+  cp.cy = I.ciy;
+  cp.cz = DIM == 3 ? I.ciz : 0;
   cp.ux = a0.x * (float)g.invR;
   cp.uy = a0.y * (float)g.invR;
   cp.uz = DIM == 3 ? a0.z * (float)g.invR : 0.0f;
   auto load = [&](uint32_t j) { return rec.xa[j]; };
-  auto near = [&](const float4 &b, uint32_t j) {
+  auto near = [&](const float4 &b, uint32_t j) -> uint32_t {
     const float dx = b.x - axa.x, dy = b.y - axa.y, dz = DIM == 3 ? b.z - axa.z : 0.f;
     const float r2 = dx * dx + dy * dy + dz * dz;
-    return j != i && r2 <= two_h2;
+    if (!KEEP) return j != i && r2 <= two_h2 ? 1u : 0u;
+    return j != i && r2 <= rho2 ? (r2 <= two_h2 ? 1u : 2u) : 0u;
   };
   int cnt = 0;
   CoopWalk cw;
-  coop_init(cw, g, active, (float)P.two_h, DIM);
+  coop_init(cw, g, active, (float)rho, DIM);
   for (;;) {
     const bool fin =
-        coop_fill<DIM, kMList, kMBatch, FEAT>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, S.ndum,
-                                         load, near);
+        coop_fill<DIM, kMList, kMBatch>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, load, near);
     run_list(cnt);
     cnt = 0;
     if (fin) break;
+  }
+  if (keep) kl.nch[i] = (uint32_t)min(chunk, kKeepChunks);
+  pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
+}
+
+// Second stage of a step from the first stage's kept candidates: the same FP32
+// test as the search, on the refreshed records, then the same body, one FP32
+// chunk sum per kept chunk.
+template <int DIM, bool FEAT, bool PST4>
+__global__ void __launch_bounds__(256) WB_MIXED_ATTR
+    k_pair_kept_mixed(Phys P, Grid g, MixedRec rec, uint32_t nf, Scalars *sc, Rates out,
+                      uint32_t *__restrict__ cand, KeptLists kl) {
+  __shared__ uint32_t list[kMList][kBlock];
+  const int tid = threadIdx.x;
+  const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + tid;
+  const bool active = i < nf;
+  float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0, axa = a0;
+  double phii = 0.0;
+  if (active) {
+    a0 = rec.r0[i];
+    a1 = rec.r1[i];
+    axa = rec.xa[i];
+    phii = rec.phi[i];
+  }
+  const MixedI I = mixed_i(P, g, a0, a1, phii);
+  const float two_h2 = (float)P.two_h2;
+  PairSums S;
+  sums_zero(S);
+  const int nch = active ? (int)kl.nch[i] : 0;
+  const int wch = wave_max_int(nch);
+  for (int c = 0; c < wch; ++c) {
+    const int cnt = c < nch ? (int)kl.cnt[kept_chunk(i, c)] : 0;
+    const int kmax = wave_max_int(cnt);
+    // stage the chunk in this lane's LDS column, eight loads in flight at once
+    const uint32_t *src = kl.ent + kept_entry(i, c, 0);
+    for (int k0 = 0; k0 < kmax; k0 += 8) {
+      uint32_t e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = k0 + u < cnt ? src[(size_t)(k0 + u) * 64u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) list[k0 + u][tid] = e[u];
+    }
+    MixedChunk C;
+    chunk_zero(C);
+    uint32_t en = cnt > 0 ? list[0][tid] : 0u;
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t j = en & ~kSkinTag;
+      const float4 b = rec.xa[j];
+      if (k + 1 < cnt) en = list[k + 1][tid];
+      const float dx = b.x - axa.x, dy = b.y - axa.y, dz = DIM == 3 ? b.z - axa.z : 0.f;
+      if (dx * dx + dy * dy + dz * dz <= two_h2) {
+        mixed_body<DIM, FEAT, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], j, nf, C, S);
+        S.nnb += 1;
+      }
+    }
+    chunk_flush(C, S);
+    S.ntest += (uint32_t)cnt;
   }
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
 }
@@ -386,28 +545,47 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
 template <int DIM, bool FEAT>
 void launch_pair_mixed_inst(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                             const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
-                            hipStream_t s) {
+                            const KeptLists &kl, int mode, hipStream_t s) {
   dim3 gr(grid_for(nf)), bl(kBlock);
-  if (P.pst_n == 4.0)
-    hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
-  else
-    hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out, cand);
+  const bool p4 = P.pst_n == 4.0;
+  if (mode == kPairSearch) {
+    if (p4)
+      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
+                         cand, kl);
+    else
+      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
+                         cand, kl);
+  } else if (mode == kPairSearchKeep) {
+    if (p4)
+      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
+                         cand, kl);
+    else
+      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
+                         cand, kl);
+  } else {
+    if (p4)
+      hipLaunchKernelGGL((k_pair_kept_mixed<DIM, FEAT, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
+    else
+      hipLaunchKernelGGL((k_pair_kept_mixed<DIM, FEAT, false>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
+  }
 }
 
 hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                              const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
-                             bool features, hipStream_t s) {
+                             bool features, int mode, uint32_t *kent, uint32_t *kcnt, uint32_t *knch, hipStream_t s) {
   if (nf == 0) return hipSuccess;
+  if (mode != kPairSearch && (!kent || !kcnt || !knch)) return hipErrorInvalidValue;
+  KeptLists kl{kent, kcnt, knch};
   if (P.dim == 2) {
     if (features)
-      launch_pair_mixed_inst<2, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, s);
+      launch_pair_mixed_inst<2, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
     else
-      launch_pair_mixed_inst<2, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, s);
+      launch_pair_mixed_inst<2, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
   } else {
     if (features)
-      launch_pair_mixed_inst<3, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, s);
+      launch_pair_mixed_inst<3, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
     else
-      launch_pair_mixed_inst<3, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, s);
+      launch_pair_mixed_inst<3, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
   }
   return hipGetLastError();
 }
@@ -442,7 +620,7 @@ __global__ void __launch_bounds__(256) k_scan_mixed(Phys P, Grid g, MixedRec rec
     cp.uy = a.y * (float)g.invR;
     cp.uz = DIM == 3 ? a.z * (float)g.invR : 0.0f;
     int nrows;
-    const uint32_t M = rows_layout<DIM>(tab, g, cp, (float)P.two_h, cs_f, cs_d, nf, nrows);
+    const uint32_t M = rows_layout<DIM>(tab, g, cp, (float)P.win, cs_f, cs_d, nf, nrows);
     bool covered = false;
     for (uint32_t c0 = 0; c0 < M && !covered; c0 += 64u) {
       bool cov = false;

@@ -26,9 +26,6 @@ namespace wb {
 
 // Compile-time tuning of the pair pass (values chosen by measurement on the
 // 17.5M-particle sloshing tank; they change speed, never results).
-#ifndef WB_PAIR_LIST
-#define WB_PAIR_LIST 32
-#endif
 #ifndef WB_PAIR_BATCH
 #define WB_PAIR_BATCH 4
 #endif
@@ -44,7 +41,15 @@ namespace wb {
 #ifndef WB_PAIR_WAVES_FEAT
 #define WB_PAIR_WAVES_FEAT 4
 #endif
-constexpr int kList = WB_PAIR_LIST;    // LDS list entries per lane
+// pass from kept lists: records of the next neighbour requested before the
+// current one is evaluated (1) or not (0), and its waves per SIMD
+#ifndef WB_KEPT_PREFETCH
+#define WB_KEPT_PREFETCH 0
+#endif
+#ifndef WB_KEPT_WAVES
+#define WB_KEPT_WAVES 4
+#endif
+constexpr int kList = kPairList;       // LDS list entries per lane
 constexpr int kBatch = WB_PAIR_BATCH;  // candidates fetched per search iteration
 static_assert(kBatch <= kRecPad, "batched candidate loads run at most kRecPad records past a run");
 #define WB_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_PAIR_WAVES_FEAT : WB_PAIR_WAVES)))
@@ -62,7 +67,7 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
   if (k >= nd) return;
   double xd = d.x[0][k], yd = d.x[1][k], zd = DIM == 3 ? d.x[2][k] : 0.0;
   RowWalker w;
-  walker_init<DIM>(w, g, xd, yd, zd, P.two_h);
+  walker_init<DIM>(w, g, xd, yd, zd, P.win);
   int64_t best = -1;
   uint32_t best_id = 0;
   double best_r2 = 0.0;
@@ -106,13 +111,85 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
 
 // ----------------------------------------------------------- pair pass
 
-// PST4: the shifting exponent is 4 (the paper's value), evaluated as two
-// squarings; otherwise pow().
+// Dense pair body: every sum of Eq. (sph) for neighbour j (records b0, b1) of
+// particle i (records a0, a1).  PST4: the shifting exponent is 4 (the paper's
+// value), evaluated as two squarings; otherwise pow().
 template <int DIM, bool FEAT, bool PST4>
+__device__ __forceinline__ void pair_body_f64(const Phys &P, const double4 &a0, const double4 &a1, const double4 &b0,
+                                              const double4 &b1, const uint32_t j, const uint32_t nf, PairSums &S) {
+  const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
+  // membership was decided by the exact test; here |r| only feeds W and K
+  const double r2 = DIM == 3 ? fma(rx, rx, fma(ry, ry, rz * rz)) : fma(rx, rx, ry * ry);
+  S.coincident |= (r2 == 0.0);
+  const double is = rsqrt_pos(r2);
+  const double s = r2 * is;
+  const double t = fma(s, P.m_half_inv_h, 1.0);  // 1 - q/2
+  const double t2 = t * t, t3 = t2 * t;
+  const double wv = P.kfac * t3 * b1.w;  // |grad W| / |r| times V_j
+  const double gx = wv * rx, gy = wv * ry, gz = wv * rz;
+  // S.L = sum r (x) grad W V  (symmetric for the radial kernel)
+  S.L[0] += rx * gx;
+  S.L[1] += ry * gy;
+  S.L[3] += rx * gy;
+  if (DIM == 3) {
+    S.L[2] += rz * gz;
+    S.L[4] += rx * gz;
+    S.L[5] += ry * gz;
+  }
+  S.gs[0] += gx;
+  S.gs[1] += gy;
+  if (DIM == 3) S.gs[2] += gz;
+  const double dph = b0.w - a0.w;
+  const double dux = b1.x - a1.x, duy = b1.y - a1.y, duz = DIM == 3 ? b1.z - a1.z : 0.0;
+  const double dun = (dux * rx + duy * ry + duz * rz) * is;
+  const double c2 = dph - P.c0 * dun;  // 2 (phi*_ij - phi_i)
+  const double cs = b0.w + a0.w;        // conservative form
+  S.SR[0] += c2 * gx;
+  S.SR[1] += c2 * gy;
+  S.SC[0] += cs * gx;
+  S.SC[1] += cs * gy;
+  if (DIM == 3) {
+    S.SR[2] += c2 * gz;
+    S.SC[2] += cs * gz;
+  }
+  // symmetric part of N_ab = sum (U_j - U_i)_a (grad W V)_b: S.L^-1 is
+  // symmetric, so tr(S.L^-1 S.N) only sees S.N + S.N^T (packed xx yy zz xy xz yz,
+  // off-diagonals hold N_ab + N_ba)
+  S.N[0] += dux * gx;
+  S.N[1] += duy * gy;
+  S.N[3] += dux * gy + duy * gx;
+  if (DIM == 3) {
+    S.N[2] += duz * gz;
+    S.N[4] += dux * gz + duz * gx;
+    S.N[5] += duy * gz + duz * gy;
+  }
+  S.Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
+  // shifting: sum (W / W(dx))^n grad W V; the epilogue adds sum grad W V
+  // times 1 / R, i.e. P = sum [1 + R (W / W(dx))^n] grad W V
+  const double u = fma(s, P.two_inv_h, 1.0);  // 2q + 1
+  const double t4u = (t2 * t2) * u;
+  const double wr = P.aw0 * t4u;
+  const double wrn = PST4 ? (wr * wr) * (wr * wr) : pow(wr, P.pst_n);
+  S.Ps[0] += wrn * gx;
+  S.Ps[1] += wrn * gy;
+  if (DIM == 3) S.Ps[2] += wrn * gz;
+  if (FEAT) {
+    S.S0 += (float)(wr * b1.w);  // W / W(dx) V
+    S.qmin = fminf(S.qmin, (float)s);
+    S.ndum += j >= nf ? 1u : 0u;
+  }
+}
+
+// The pair pass with its own candidate search (Algorithm 1).  KEEP (first
+// stage of a step whose skin fits the cells, sc->vok): the search radius
+// grows to 2h + skin, candidates beyond 2h enter the LDS list tagged and are
+// skipped by the body, and every non-empty list fill is also copied to kl for
+// the second stage; a lane with more than kKeepChunks fills raises sc->vovf.
+template <int DIM, bool FEAT, bool PST4, bool KEEP>
 __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
                                                   const double4 *__restrict__ rec1, const uint32_t *__restrict__ cs_f,
                                                   const uint32_t *__restrict__ cs_d, uint32_t nf, Scalars *sc,
-                                                  Rates out, uint32_t *__restrict__ cand) {
+                                                  Rates out, uint32_t *__restrict__ cand, KeptLists kl) {
   __shared__ uint32_t list[kList][kBlock];
   const int tid = threadIdx.x;
   const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + tid;
@@ -125,146 +202,180 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
   }
   PairSums S;
   sums_zero(S);
+  const bool keep = KEEP && sc->vok != 0u;
+  const double rho = keep ? P.two_h + sc->skin : P.two_h;
+  const double rho2 = keep ? rho * rho : P.two_h2;
+  int chunk = 0;
 
-  // dense pair body: every sum of Eq. (sph) for neighbour j
-  auto body = [&](const double4 &b0, const double4 &b1, const uint32_t j) {
-    const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
-    // membership was decided by the exact test; here |r| only feeds W and K
-    const double r2 = DIM == 3 ? fma(rx, rx, fma(ry, ry, rz * rz)) : fma(rx, rx, ry * ry);
-    S.coincident |= (r2 == 0.0);
-    const double is = rsqrt_pos(r2);
-    const double s = r2 * is;
-    const double t = fma(s, P.m_half_inv_h, 1.0);  // 1 - q/2
-    const double t2 = t * t, t3 = t2 * t;
-    const double wv = P.kfac * t3 * b1.w;  // |grad W| / |r| times V_j
-    const double gx = wv * rx, gy = wv * ry, gz = wv * rz;
-    // S.L = sum r (x) grad W V  (symmetric for the radial kernel)
-    S.L[0] += rx * gx;
-    S.L[1] += ry * gy;
-    S.L[3] += rx * gy;
-    if (DIM == 3) {
-      S.L[2] += rz * gz;
-      S.L[4] += rx * gz;
-      S.L[5] += ry * gz;
-    }
-    S.gs[0] += gx;
-    S.gs[1] += gy;
-    if (DIM == 3) S.gs[2] += gz;
-    const double dph = b0.w - a0.w;
-    const double dux = b1.x - a1.x, duy = b1.y - a1.y, duz = DIM == 3 ? b1.z - a1.z : 0.0;
-    const double dun = (dux * rx + duy * ry + duz * rz) * is;
-    const double c2 = dph - P.c0 * dun;  // 2 (phi*_ij - phi_i)
-    const double cs = b0.w + a0.w;        // conservative form
-    S.SR[0] += c2 * gx;
-    S.SR[1] += c2 * gy;
-    S.SC[0] += cs * gx;
-    S.SC[1] += cs * gy;
-    if (DIM == 3) {
-      S.SR[2] += c2 * gz;
-      S.SC[2] += cs * gz;
-    }
-    // symmetric part of N_ab = sum (U_j - U_i)_a (grad W V)_b: S.L^-1 is
-    // symmetric, so tr(S.L^-1 S.N) only sees S.N + S.N^T (packed xx yy zz xy xz yz,
-    // off-diagonals hold N_ab + N_ba)
-    S.N[0] += dux * gx;
-    S.N[1] += duy * gy;
-    S.N[3] += dux * gy + duy * gx;
-    if (DIM == 3) {
-      S.N[2] += duz * gz;
-      S.N[4] += dux * gz + duz * gx;
-      S.N[5] += duy * gz + duz * gy;
-    }
-    S.Ds += wv * dph;  // Phi_ij . grad W V = 2 K (phi_j - phi_i) V_j (factor 2 in the epilogue)
-    // shifting: sum (W / W(dx))^n grad W V; the epilogue adds sum grad W V
-    // times 1 / R, i.e. P = sum [1 + R (W / W(dx))^n] grad W V
-    const double u = fma(s, P.two_inv_h, 1.0);  // 2q + 1
-    const double t4u = (t2 * t2) * u;
-    const double wr = P.aw0 * t4u;
-    const double wrn = PST4 ? (wr * wr) * (wr * wr) : pow(wr, P.pst_n);
-    S.Ps[0] += wrn * gx;
-    S.Ps[1] += wrn * gy;
-    if (DIM == 3) S.Ps[2] += wrn * gz;
-    if (FEAT) {
-      S.S0 += (float)(wr * b1.w);  // W / W(dx) V
-      S.qmin = fminf(S.qmin, (float)s);
-    }
-  };
   // consume the first cnt entries of this lane's list
   auto run_list = [&](int cnt) {
-#if WB_PAIR_UNROLL > 1
-    // two neighbours per iteration: both records in flight at once; the list
-    // entries of the next two are read one iteration ahead
-    int k = 0;
-    uint32_t ja = cnt > 0 ? list[0][tid] : 0u, jb = cnt > 1 ? list[1][tid] : 0u;
-    for (; k + 1 < cnt; k += 2) {
-      const double4 pa0 = rec0[ja], pa1 = rec1[ja], pb0 = rec0[jb], pb1 = rec1[jb];
-      const uint32_t ca = ja, cb = jb;
-      if (k + 2 < cnt) ja = list[k + 2][tid];
-      if (k + 3 < cnt) jb = list[k + 3][tid];
-      body(pa0, pa1, ca);
-      body(pb0, pb1, cb);
+    if (keep) {  // copy the fill for the second stage
+      const int kmax = wave_max_int(cnt);
+      const bool room = chunk < kKeepChunks;
+      uint32_t *dst = kl.ent + kept_entry(i, min(chunk, kKeepChunks - 1), 0);
+      for (int k = 0; k < kmax; ++k)
+        if (room && k < cnt) dst[(size_t)k * 64u] = list[k][tid];
+      if (cnt > 0) {
+        if (room) kl.cnt[kept_chunk(i, chunk)] = (uint32_t)cnt;
+        else sc->vovf = 1u;
+        ++chunk;
+      }
     }
-    if (k < cnt) body(rec0[ja], rec1[ja], ja);
-#else
     // one neighbour per iteration, the next list entry read one iteration ahead
-    uint32_t jn = cnt > 0 ? list[0][tid] : 0u;
+    uint32_t en = cnt > 0 ? list[0][tid] : 0u;
     for (int k = 0; k < cnt; ++k) {
-      const uint32_t j = jn;
+      const uint32_t e = en;
+      const uint32_t j = KEEP ? e & ~kSkinTag : e;
       const double4 b0 = rec0[j], b1 = rec1[j];
-      if (k + 1 < cnt) jn = list[k + 1][tid];
-      body(b0, b1, j);
+      if (k + 1 < cnt) en = list[k + 1][tid];
+      if (!KEEP || !(e & kSkinTag)) {
+        pair_body_f64<DIM, FEAT, PST4>(P, a0, a1, b0, b1, j, nf, S);
+        if (KEEP) S.nnb += 1;
+      }
     }
-#endif
-    S.nnb += cnt;
+    if (!KEEP) S.nnb += cnt;
   };
 
   // candidate search with the rows walked in lockstep by the wave
   const CellPos cp = cellpos_of<DIM>(g, a0.x, a0.y, a0.z);
   int cnt = 0;
   auto load = [&](uint32_t j) { return rec0[j]; };
-  auto near = [&](const double4 &b, uint32_t j) {
+  auto near = [&](const double4 &b, uint32_t j) -> uint32_t {
     const double r2 = dist2_exact<DIM>(b.x - a0.x, b.y - a0.y, DIM == 3 ? b.z - a0.z : 0.0);
-    return j != i && r2 <= P.two_h2;
+    if (!KEEP) return j != i && r2 <= P.two_h2 ? 1u : 0u;
+    return j != i && r2 <= rho2 ? (r2 <= P.two_h2 ? 1u : 2u) : 0u;
   };
   CoopWalk cw;
-  coop_init(cw, g, active, (float)P.two_h, DIM);
+  coop_init(cw, g, active, (float)rho, DIM);
   for (;;) {
-    const bool fin =
-        coop_fill<DIM, kList, kBatch, FEAT>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest, S.ndum,
-                                         load, near);
+    const bool fin = coop_fill<DIM, kList, kBatch>(cw, g, cs_f, cs_d, nf, cp, &list[0][tid], kBlock, cnt, S.ntest,
+                                                   load, near);
     run_list(cnt);
     cnt = 0;
     if (fin) break;
   }
+  if (keep) kl.nch[i] = (uint32_t)min(chunk, kKeepChunks);
 
+  pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
+}
+
+// Second stage of a step from the first stage's kept candidates (no search):
+// the records hold the second-stage state in the first stage's order, every
+// kept candidate is tested exactly against 2h and the neighbours run the same
+// body.  A pair within 2h now was within 2h + skin at the first stage, so the
+// neighbour sets are those of a fresh search.
+template <int DIM, bool FEAT, bool PST4>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WB_KEPT_WAVES))) k_pair_kept_f64(Phys P, const double4 *__restrict__ rec0,
+                                                                    const double4 *__restrict__ rec1, uint32_t nf,
+                                                                    Scalars *sc, Rates out,
+                                                                    uint32_t *__restrict__ cand, KeptLists kl) {
+  __shared__ uint32_t list[kList][kBlock];
+  const int tid = threadIdx.x;
+  const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * kBlock + tid;
+  const bool active = i < nf;
+  double4 a0 = make_double4(0.0, 0.0, 0.0, 0.0), a1 = a0;
+  if (active) {
+    a0 = rec0[i];
+    a1 = rec1[i];
+  }
+  PairSums S;
+  sums_zero(S);
+  const int nch = active ? (int)kl.nch[i] : 0;
+  const int wch = wave_max_int(nch);
+  for (int c = 0; c < wch; ++c) {
+    const int cnt = c < nch ? (int)kl.cnt[kept_chunk(i, c)] : 0;
+    const int kmax = wave_max_int(cnt);
+    // stage the chunk in this lane's LDS column, eight loads in flight at once
+    const uint32_t *src = kl.ent + kept_entry(i, c, 0);
+    for (int k0 = 0; k0 < kmax; k0 += 8) {
+      uint32_t e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = k0 + u < cnt ? src[(size_t)(k0 + u) * 64u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) list[k0 + u][tid] = e[u];
+    }
+#if WB_KEPT_PREFETCH
+    // one neighbour per iteration, the next one's records in flight meanwhile
+    if (cnt > 0) {
+      uint32_t jn = list[0][tid] & ~kSkinTag;
+      double4 n0 = rec0[jn], n1 = rec1[jn];
+      for (int k = 0; k < cnt; ++k) {
+        const uint32_t j = jn;
+        const double4 b0 = n0, b1 = n1;
+        if (k + 1 < cnt) {
+          jn = list[k + 1][tid] & ~kSkinTag;
+          n0 = rec0[jn];
+          n1 = rec1[jn];
+        }
+        if (dist2_exact<DIM>(b0.x - a0.x, b0.y - a0.y, DIM == 3 ? b0.z - a0.z : 0.0) <= P.two_h2) {
+          pair_body_f64<DIM, FEAT, PST4>(P, a0, a1, b0, b1, j, nf, S);
+          S.nnb += 1;
+        }
+      }
+    }
+#else
+    // one neighbour per iteration, the next list entry read one iteration ahead
+    uint32_t en = cnt > 0 ? list[0][tid] : 0u;
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t j = en & ~kSkinTag;
+      const double4 b0 = rec0[j], b1 = rec1[j];
+      if (k + 1 < cnt) en = list[k + 1][tid];
+      if (dist2_exact<DIM>(b0.x - a0.x, b0.y - a0.y, DIM == 3 ? b0.z - a0.z : 0.0) <= P.two_h2) {
+        pair_body_f64<DIM, FEAT, PST4>(P, a0, a1, b0, b1, j, nf, S);
+        S.nnb += 1;
+      }
+    }
+#endif
+    S.ntest += (uint32_t)cnt;
+  }
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
 }
 
 template <int DIM, bool FEAT>
 void launch_pair_f64_inst(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                           const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
-                          uint32_t *cand, hipStream_t s) {
+                          uint32_t *cand, const KeptLists &kl, int mode, hipStream_t s) {
   dim3 gr(grid_for(nf)), bl(kBlock);
-  if (P.pst_n == 4.0)
-    hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
-  else
-    hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand);
+  const bool p4 = P.pst_n == 4.0;
+  if (mode == kPairSearch) {
+    if (p4)
+      hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, true, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc,
+                         out, cand, kl);
+    else
+      hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, false, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc,
+                         out, cand, kl);
+  } else if (mode == kPairSearchKeep) {
+    if (p4)
+      hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, true, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc,
+                         out, cand, kl);
+    else
+      hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, false, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc,
+                         out, cand, kl);
+  } else {
+    if (p4)
+      hipLaunchKernelGGL((k_pair_kept_f64<DIM, FEAT, true>), gr, bl, 0, s, P, rec0, rec1, nf, sc, out, cand, kl);
+    else
+      hipLaunchKernelGGL((k_pair_kept_f64<DIM, FEAT, false>), gr, bl, 0, s, P, rec0, rec1, nf, sc, out, cand, kl);
+  }
 }
 
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
-                           uint32_t *cand, bool features, hipStream_t s) {
+                           uint32_t *cand, bool features, int mode, uint32_t *kent, uint32_t *kcnt, uint32_t *knch,
+                           hipStream_t s) {
   if (nf == 0) return hipSuccess;
+  if (mode != kPairSearch && (!kent || !kcnt || !knch)) return hipErrorInvalidValue;
+  KeptLists kl{kent, kcnt, knch};
   if (P.dim == 2) {
     if (features)
-      launch_pair_f64_inst<2, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
+      launch_pair_f64_inst<2, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
     else
-      launch_pair_f64_inst<2, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
+      launch_pair_f64_inst<2, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
   } else {
     if (features)
-      launch_pair_f64_inst<3, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
+      launch_pair_f64_inst<3, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
     else
-      launch_pair_f64_inst<3, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, s);
+      launch_pair_f64_inst<3, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
   }
   return hipGetLastError();
 }
@@ -381,7 +492,7 @@ __global__ void __launch_bounds__(256) k_scan_f64(Phys P, Grid g, const double4 
     const double T[3] = {a.x + P.h * n[0], a.y + P.h * n[1], DIM == 3 ? a.z + P.h * n[2] : 0.0};
     const CellPos cp = cellpos_of<DIM>(g, a.x, a.y, a.z);
     int nrows;
-    const uint32_t M = rows_layout<DIM>(tab, g, cp, (float)P.two_h, cs_f, cs_d, nf, nrows);
+    const uint32_t M = rows_layout<DIM>(tab, g, cp, (float)P.win, cs_f, cs_d, nf, nrows);
     bool covered = false;
     for (uint32_t c0 = 0; c0 < M && !covered; c0 += 64u) {
       bool cov = false;

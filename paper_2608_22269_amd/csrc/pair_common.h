@@ -28,6 +28,26 @@ __device__ __forceinline__ void wave_count(uint32_t *counter, bool pred) {
     atomicAdd(counter, (uint32_t)__popcll(mask));
 }
 
+// Candidate lists kept from a step's first stage for its second.  A lane's
+// list is stored chunk by chunk, one chunk per non-empty LDS list fill of the
+// pair pass (the lanes of a cell row fill together, so their chunk indices
+// agree and the stores coalesce).  Each wave owns one contiguous block (few
+// pages per wave): entry k of chunk c of lane l of wave w at
+// ent[((w kKeepChunks + c) kPairList + k) 64 + l], the chunk's entry count at
+// cnt[(w kKeepChunks + c) 64 + l], the lane's chunk count at nch[64 w + l].
+struct KeptLists {
+  uint32_t *ent;
+  uint32_t *cnt;
+  uint32_t *nch;
+};
+
+__device__ __forceinline__ size_t kept_chunk(uint32_t i, int c) {
+  return ((size_t)(i >> 6) * kKeepChunks + (size_t)c) * 64u + (i & 63u);
+}
+__device__ __forceinline__ size_t kept_entry(uint32_t i, int c, int k) {
+  return (((size_t)(i >> 6) * kKeepChunks + (size_t)c) * kPairList + (size_t)k) * 64u + (i & 63u);
+}
+
 // Neighbour sums of one particle (FP64).  L and N are symmetric and packed
 // as (xx, yy, zz, xy, xz, yz); N holds N_ab + N_ba off the diagonal.  Ps is
 // sum (W / W(dx))^n grad W V (the shifting sum is gs + R Ps).  S0 (sum of

@@ -123,10 +123,10 @@ class Simulation:
         return out_tensor
 
     def stats(self):
-        out = np.zeros(16)
+        out = np.zeros(20)
         _check(L.lib().sph_stats(self.ctx, out.ctypes.data_as(C.c_void_p)), "sph_stats", self.ctx)
         keys = ["t", "dt", "steps", "umax", "n_fluid", "n_dummy", "n_fs", "n_cons", "n_scan", "n_mlp",
-                "n_singular", "pairs", "n_cand", "tests"]
+                "n_singular", "pairs", "n_cand", "tests", "n_kept", "n_rebuilt", "pairs_stage1", "tests_stage1"]
         return {k: float(out[i]) for i, k in enumerate(keys)}
 
     def profile(self, enable=True):
@@ -135,7 +135,7 @@ class Simulation:
     def profile_read(self):
         out = np.zeros(16)
         _check(L.lib().sph_profile_read(self.ctx, out.ctypes.data_as(C.c_void_p)), "sph_profile_read", self.ctx)
-        names = ["pair", "mirror", "rebuild", "fs_detect", "stage"]
+        names = ["pair", "mirror", "rebuild", "fs_detect", "stage", "pair_kept"]
         return {k: {"ms": float(out[2 * i]), "launches": int(out[2 * i + 1])} for i, k in enumerate(names)}
 
     def neighbors(self):

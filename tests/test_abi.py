@@ -49,6 +49,33 @@ def test_validate_and_workspace(L):
     q = L.params_from_dict(c["params"])
     q.cell_size = 0.5 * q.h  # reach 4 > 3
     assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+    q = L.params_from_dict(c["params"])
+    q.flags |= 128  # no such flag
+    assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+
+
+def test_kept_lists_workspace(L):
+    """SPH_F_KEEP_LISTS adds about 1 KiB per fluid particle (8 chunks of 32
+    entries per lane, counts and chunk counts) when the cells have room for a
+    skin (either precision), nothing otherwise."""
+    lib = L.lib()
+    c = wl.tank2d()
+    h = c["params"]["h"]
+    nf, nd = 5000, 678
+    lanes = -(-nf // 256) * 256
+
+    def ws(**kw):
+        q = L.params_from_dict(wl.with_params(c, **kw)["params"])
+        assert lib.sph_validate(C.byref(q)) == L.SPH_OK
+        return lib.sph_workspace_bytes(C.byref(q), nf, nd)
+
+    base = ws(cell_size=2.1 * h)
+    kept = ws(cell_size=2.1 * h, keep_lists=True)
+    extra = 8 * 32 * lanes * 4 + 8 * lanes * 4 + lanes * 4
+    assert extra <= kept - base <= extra + 3 * 256
+    assert ws(cell_size=2.0 * h, keep_lists=True) == ws(cell_size=2.0 * h)  # reach R - 2h = 0: no room
+    mixed = ws(cell_size=2.1 * h, keep_lists=True, precision="mixed") - ws(cell_size=2.1 * h, precision="mixed")
+    assert extra <= mixed <= extra + 3 * 256
 
 
 def _init(L, case, x=None, u=None, phi=None, kind=None, normal=None, ws=256, ws_bytes=1 << 40):
