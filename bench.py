@@ -34,13 +34,12 @@ FLOP_PER_PAIR_3D = 95
 FLOP_PER_TEST_3D = 8
 # sources of the profiled pair kernels (the committed counter summaries hold
 # their hash; the traffic is reported only while it matches)
-PAIR_SOURCES = {
-    "pair_f64": ["paper_2608_22269_amd/csrc/pair.hip", "paper_2608_22269_amd/csrc/common.h",
-                 "paper_2608_22269_amd/csrc/coop.h", "paper_2608_22269_amd/csrc/pair_common.h"],
-    "pair_mixed": ["paper_2608_22269_amd/csrc/mixed.hip", "paper_2608_22269_amd/csrc/common.h",
-                   "paper_2608_22269_amd/csrc/coop.h", "paper_2608_22269_amd/csrc/pair_common.h",
-                   "paper_2608_22269_amd/csrc/mixed.h"],
-}
+_F64_SRC = ["paper_2608_22269_amd/csrc/pair.hip", "paper_2608_22269_amd/csrc/common.h",
+            "paper_2608_22269_amd/csrc/coop.h", "paper_2608_22269_amd/csrc/pair_common.h"]
+_MIXED_SRC = ["paper_2608_22269_amd/csrc/mixed.hip", "paper_2608_22269_amd/csrc/common.h",
+              "paper_2608_22269_amd/csrc/coop.h", "paper_2608_22269_amd/csrc/pair_common.h",
+              "paper_2608_22269_amd/csrc/mixed.h"]
+PAIR_SOURCES = {"pair_f64": _F64_SRC, "pair_kept_f64": _F64_SRC, "pair_mixed": _MIXED_SRC, "pair_kept_mixed": _MIXED_SRC}
 
 
 def log(msg):
@@ -378,25 +377,34 @@ def main():
             raise SystemExit(f"unknown path {path}")
     head = results["fp64"]
 
-    def roofline(res, key, kernel):
+    def roofline(res, key, kernel, kept=False):
         src = PAIR_SOURCES[key]
         prof = profile_summary(f"{key}_slosh3d")
+        if kept:  # the second stage's pass from the kept lists
+            k = res["kept_pass"]
+            tflops, ms = k["tflops"], k["ms"]
+            flops = k["pairs"] * FLOP_PER_PAIR_3D + k["kept_candidates_tested"] * FLOP_PER_TEST_3D
+        else:
+            tflops, ms = res["pair_pass_tflops"], res["pair_pass_ms"]
+            flops = res["pairs_per_rhs"] * FLOP_PER_PAIR_3D + res["candidate_tests_per_rhs"] * FLOP_PER_TEST_3D
         out = {
-            "bound": "alu", "achieved": res["pair_pass_tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": res["pair_pass_tflops"] / PEAK_FP64_TFLOPS,
+            "bound": "alu", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": tflops / PEAK_FP64_TFLOPS,
             "traffic": prof["hbm_bytes_per_launch"] if prof else None,
-            "kernel": kernel, "pair_pass_ms": res["pair_pass_ms"],
-            "flop_per_launch": res["pairs_per_rhs"] * FLOP_PER_PAIR_3D
-            + res["candidate_tests_per_rhs"] * FLOP_PER_TEST_3D,
+            "kernel": kernel, "pair_pass_ms": ms, "flop_per_launch": flops,
             "source_sha": source_sha(src),
         }
         if prof and "valu_issue_frac" in prof:
-            # the binding roof: VALU instruction issue (counted by the SQ)
+            # VALU instruction issue (counted by the SQ)
             out["valu_issue"] = {"frac": prof["valu_issue_frac"], "lane_instr_per_s": prof["valu_lane_instr_per_s"],
                                  "peak": prof["valu_issue_peak"], "from": f"profiles/{key}_slosh3d_pmc.json"}
+        if prof and "ta_busy_frac" in prof:
+            # the texture addresser (vector memory address unit): the record gathers
+            out["ta_busy"] = {"frac": prof["ta_busy_frac"], "from": f"profiles/{key}_slosh3d_pmc.json"}
         return out
 
-    roof = roofline(head, "pair_f64", "k_pair_f64<3,false,true,true> (search and pair pass of the first stage, keeping its candidates, FP64)")
+    roof = roofline(head, "pair_f64", "k_pair_f64<3,false,true,true> (search and pair pass of the first stage, "
+                    "keeping its candidates, FP64)")
     out = {
         "metric": METRIC, "value": head["pair_evals_per_s"], "unit": "pair-evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -411,10 +419,17 @@ def main():
         "roofline": roof,
         "paths": results,
     }
+    if "kept_pass" in head:
+        out["roofline_kept"] = roofline(head, "pair_kept_f64", "k_pair_kept_f64<3,false,true> (second stage from the "
+                                        "kept lists, FP64)", kept=True)
     if "mixed" in results:
         # non-packed FP32 issues at the FP64 rate on this chip: same peak
         out["roofline_mixed"] = roofline(results["mixed"], "pair_mixed",
-                                         "k_pair_mixed<3,false,true> (fused pair pass, FP32 body + FP64 sums)")
+                                         "k_pair_mixed<3,false,true,true> (first-stage pass, FP32 body + FP64 sums)")
+        if "kept_pass" in results["mixed"]:
+            out["roofline_kept_mixed"] = roofline(results["mixed"], "pair_kept_mixed",
+                                                  "k_pair_kept_mixed<3,false,true> (second stage from the kept lists)",
+                                                  kept=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.dx)
     for k in ("mixed", "mixed_learned"):
