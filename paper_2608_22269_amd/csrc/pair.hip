@@ -41,11 +41,8 @@ namespace wb {
 #ifndef WB_PAIR_WAVES_FEAT
 #define WB_PAIR_WAVES_FEAT 4
 #endif
-// pass from kept lists: records of the next neighbour requested before the
-// current one is evaluated (1) or not (0), and its waves per SIMD
-#ifndef WB_KEPT_PREFETCH
-#define WB_KEPT_PREFETCH 0
-#endif
+// waves per SIMD of the pass from kept lists (2, 3 and 4 measured equal: its
+// record gathers bound it, not latency)
 #ifndef WB_KEPT_WAVES
 #define WB_KEPT_WAVES 4
 #endif
@@ -294,26 +291,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WB_KEP
 #pragma unroll
       for (int u = 0; u < 8; ++u) list[k0 + u][tid] = e[u];
     }
-#if WB_KEPT_PREFETCH
-    // one neighbour per iteration, the next one's records in flight meanwhile
-    if (cnt > 0) {
-      uint32_t jn = list[0][tid] & ~kSkinTag;
-      double4 n0 = rec0[jn], n1 = rec1[jn];
-      for (int k = 0; k < cnt; ++k) {
-        const uint32_t j = jn;
-        const double4 b0 = n0, b1 = n1;
-        if (k + 1 < cnt) {
-          jn = list[k + 1][tid] & ~kSkinTag;
-          n0 = rec0[jn];
-          n1 = rec1[jn];
-        }
-        if (dist2_exact<DIM>(b0.x - a0.x, b0.y - a0.y, DIM == 3 ? b0.z - a0.z : 0.0) <= P.two_h2) {
-          pair_body_f64<DIM, FEAT, PST4>(P, a0, a1, b0, b1, j, nf, S);
-          S.nnb += 1;
-        }
-      }
-    }
-#else
     // one neighbour per iteration, the next list entry read one iteration ahead
     uint32_t en = cnt > 0 ? list[0][tid] : 0u;
     for (int k = 0; k < cnt; ++k) {
@@ -325,7 +302,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WB_KEP
         S.nnb += 1;
       }
     }
-#endif
     S.ntest += (uint32_t)cnt;
   }
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
