@@ -64,7 +64,7 @@ struct sph_ctx {
   float *cand_logit;
   // candidate lists kept from a step's first stage (SPH_F_KEEP_LISTS)
   uint32_t *kent;
-  uint32_t *kcnt, *knch;
+  unsigned long long *kcnt;
   double n_kept, n_rebuilt;  // second stages run from them / rebuilt instead
   Scalars *sc;
   unsigned char *stage;
@@ -310,11 +310,10 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   if (c->P.skin_max > 0.0) {
     const int64_t np = (int64_t)grid_for(std::max<int64_t>(nf, 1)) * kBlock;
     c->kent = cv.take<uint32_t>((int64_t)kKeepChunks * kPairList * np);
-    c->kcnt = cv.take<uint32_t>((int64_t)kKeepChunks * np);
-    c->knch = cv.take<uint32_t>(np);
+    c->kcnt = cv.take<unsigned long long>(np);
   } else {
     c->kent = nullptr;
-    c->kcnt = c->knch = nullptr;
+    c->kcnt = nullptr;
   }
   c->cand_logit = c->p.fs_mode == SPH_FS_LEARNED ? cv.take<float>(nf) : nullptr;
   c->clf.w = cv.take<float>(kMlpParams);
@@ -410,7 +409,7 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
     if (e == hipSuccess) {
       ProfScope ps(c, mode == kPairKept ? 5 : 0);
       e = launch_pair_f64(c->P, c->g, c->rec0, c->rec1, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat,
-                          mode, c->kent, c->kcnt, c->knch, c->s);
+                          mode, c->kent, c->kcnt, c->s);
     }
   } else {
     if (e == hipSuccess) {
@@ -420,7 +419,7 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
     if (e == hipSuccess) {
       ProfScope ps(c, mode == kPairKept ? 5 : 0);
       e = launch_pair_mixed(c->P, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat,
-                            mode, c->kent, c->kcnt, c->knch, c->s);
+                            mode, c->kent, c->kcnt, c->s);
     }
   }
   ProfScope ps_fs(c, 3);

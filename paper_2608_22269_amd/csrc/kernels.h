@@ -31,13 +31,13 @@ hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int
                              const double4 *rec1, double4 *drec0, double4 *drec1, const uint32_t *cs_f,
                              uint32_t nf, const Scalars *sc, hipStream_t s, const uint32_t *fid);
 // pair pass modes: own search; own search keeping its candidate lists for the
-// step's second stage (kept lists kent / kcnt / knch, sized for
-// kKeepChunks list fills of kPairList entries per lane of the launch, their
-// counts and a chunk count per lane); second stage from the kept lists
+// step's second stage (kept lists kent, sized for kKeepChunks list fills of
+// kPairList entries per lane of the launch, and kcnt, one word of packed
+// chunk counts per lane); second stage from the kept lists
 constexpr int kPairSearch = 0, kPairSearchKeep = 1, kPairKept = 2;
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
-                           uint32_t *cand, bool features, int mode, uint32_t *kent, uint32_t *kcnt, uint32_t *knch,
+                           uint32_t *cand, bool features, int mode, uint32_t *kent, unsigned long long *kcnt,
                            hipStream_t s);
 // classifier features from the raw sums of the pair-pass epilogue, for the
 // rows of a device-counted list (count != nullptr) or rows 0 .. n - 1

@@ -203,6 +203,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
   const double rho = keep ? P.two_h + sc->skin : P.two_h;
   const double rho2 = keep ? rho * rho : P.two_h2;
   int chunk = 0;
+  unsigned long long counts = 0ull;  // this lane's packed chunk counts
 
   // consume the first cnt entries of this lane's list
   auto run_list = [&](int cnt) {
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
       for (int k = 0; k < kmax; ++k)
         if (room && k < cnt) dst[(size_t)k * 64u] = list[k][tid];
       if (cnt > 0) {
-        if (room) kl.cnt[kept_chunk(i, chunk)] = (uint32_t)cnt;
+        if (room) counts |= (unsigned long long)cnt << (6 * chunk);
         else sc->vovf = 1u;
         ++chunk;
       }
@@ -251,7 +252,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
     cnt = 0;
     if (fin) break;
   }
-  if (keep) kl.nch[i] = (uint32_t)min(chunk, kKeepChunks);
+  if (keep) kl.cnt[i] = counts | ((unsigned long long)min(chunk, kKeepChunks) << kKeptNchShift);
 
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
 }
@@ -277,10 +278,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WB_KEP
   }
   PairSums S;
   sums_zero(S);
-  const int nch = active ? (int)kl.nch[i] : 0;
+  const unsigned long long counts = active ? kl.cnt[i] : 0ull;
+  const int nch = (int)(counts >> kKeptNchShift);
   const int wch = wave_max_int(nch);
   for (int c = 0; c < wch; ++c) {
-    const int cnt = c < nch ? (int)kl.cnt[kept_chunk(i, c)] : 0;
+    const int cnt = c < nch ? kept_count(counts, c) : 0;
     const int kmax = wave_max_int(cnt);
     // stage the chunk in this lane's LDS column, eight loads in flight at once
     const uint32_t *src = kl.ent + kept_entry(i, c, 0);
@@ -337,11 +339,11 @@ void launch_pair_f64_inst(const Phys &P, const Grid &g, const double4 *rec0, con
 
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
-                           uint32_t *cand, bool features, int mode, uint32_t *kent, uint32_t *kcnt, uint32_t *knch,
+                           uint32_t *cand, bool features, int mode, uint32_t *kent, unsigned long long *kcnt,
                            hipStream_t s) {
   if (nf == 0) return hipSuccess;
-  if (mode != kPairSearch && (!kent || !kcnt || !knch)) return hipErrorInvalidValue;
-  KeptLists kl{kent, kcnt, knch};
+  if (mode != kPairSearch && (!kent || !kcnt)) return hipErrorInvalidValue;
+  KeptLists kl{kent, kcnt};
   if (P.dim == 2) {
     if (features)
       launch_pair_f64_inst<2, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);

@@ -31,18 +31,21 @@ __device__ __forceinline__ void wave_count(uint32_t *counter, bool pred) {
 // Candidate lists kept from a step's first stage for its second.  A lane's
 // list is stored chunk by chunk, one chunk per non-empty LDS list fill of the
 // pair pass (the lanes of a cell row fill together, so their chunk indices
-// agree and the stores coalesce).  Each wave owns one contiguous block (few
-// pages per wave): entry k of chunk c of lane l of wave w at
-// ent[((w kKeepChunks + c) kPairList + k) 64 + l], the chunk's entry count at
-// cnt[(w kKeepChunks + c) 64 + l], the lane's chunk count at nch[64 w + l].
+// agree and the stores coalesce).  Each wave owns one contiguous block:
+// entry k of chunk c of lane l of wave w at
+// ent[((w kKeepChunks + c) kPairList + k) 64 + l].  The lane's chunk counts
+// are packed into one word written once at the end of the pass, cnt[64 w + l]:
+// 6 bits per chunk (c at bit 6c), the number of chunks at bit 48.
 struct KeptLists {
   uint32_t *ent;
-  uint32_t *cnt;
-  uint32_t *nch;
+  unsigned long long *cnt;
 };
 
-__device__ __forceinline__ size_t kept_chunk(uint32_t i, int c) {
-  return ((size_t)(i >> 6) * kKeepChunks + (size_t)c) * 64u + (i & 63u);
+constexpr int kKeptNchShift = 6 * kKeepChunks;
+static_assert(kPairList < 64 && kKeptNchShift + 4 <= 64, "packed chunk counts");
+
+__device__ __forceinline__ int kept_count(unsigned long long packed, int c) {
+  return (int)((packed >> (6 * c)) & 63ull);
 }
 __device__ __forceinline__ size_t kept_entry(uint32_t i, int c, int k) {
   return (((size_t)(i >> 6) * kKeepChunks + (size_t)c) * kPairList + (size_t)k) * 64u + (i & 63u);

@@ -71,7 +71,7 @@ def test_kept_lists_workspace(L):
 
     base = ws(cell_size=2.1 * h)
     kept = ws(cell_size=2.1 * h, keep_lists=True)
-    extra = 8 * 32 * lanes * 4 + 8 * lanes * 4 + lanes * 4
+    extra = 8 * 32 * lanes * 4 + lanes * 8
     assert extra <= kept - base <= extra + 3 * 256
     assert ws(cell_size=2.0 * h, keep_lists=True) == ws(cell_size=2.0 * h)  # reach R - 2h = 0: no room
     mixed = ws(cell_size=2.1 * h, keep_lists=True, precision="mixed") - ws(cell_size=2.1 * h, precision="mixed")
