@@ -121,16 +121,16 @@ def run_path(case, label, steps, warmup, clf=None):
     st = sim.stats()
     sim.profile(False)
     kept = st["n_kept"] > 0
-    # pairs and candidate tests of the searching pass: the first stage's when
-    # the second runs from kept lists, else the last pass's (both stages search)
-    pairs_rhs = st["pairs_stage1"] if kept else st["pairs"]
-    tests_rhs = st["tests_stage1"] if kept else st["tests"]
+    # pairs and candidate tests of the last searching pass and of the last
+    # pass from kept lists
+    pairs_rhs = st["pairs_search"]
+    tests_rhs = st["tests_search"]
     ms_step = ms_total / steps
-    pair_evals_per_step = st["pairs_stage1"] + st["pairs"]
+    pair_evals_per_step = (st["pairs_search"] + st["pairs_kept"]) if kept else 2.0 * pairs_rhs
     pair = prof["pair"]
     pair_ms = pair["ms"] / max(pair["launches"], 1)
     flops = pairs_rhs * FLOP_PER_PAIR_3D + tests_rhs * FLOP_PER_TEST_3D
-    achieved = flops / (pair_ms * 1e-3) / 1e12
+    achieved = flops / (pair_ms * 1e-3) / 1e12 if pair_ms > 0 else None
     out = {
         "ms_per_step": ms_step,
         "pair_evals_per_s": pair_evals_per_step / (ms_step * 1e-3),
@@ -138,8 +138,9 @@ def run_path(case, label, steps, warmup, clf=None):
         "candidate_tests_per_rhs": tests_rhs,
         "pair_pass_ms": pair_ms,
         "pair_pass_tflops": achieved,
-        "second_stages_from_kept_lists": st["n_kept"],
-        "second_stages_rebuilt": st["n_rebuilt"],
+        "rhs_from_kept_lists": st["n_kept"],
+        "rhs_sorted": st["n_rebuilt"],
+        "searching_passes_per_step": pair["launches"] / steps,
         "kernel_ms_per_step": {k: v["ms"] / steps for k, v in prof.items()},
         "t_end": st["t"],
         "umax_end": st["umax"],
@@ -149,14 +150,14 @@ def run_path(case, label, steps, warmup, clf=None):
     if kept:
         kp = prof["pair_kept"]
         kept_ms = kp["ms"] / max(kp["launches"], 1)
-        kflops = st["pairs"] * FLOP_PER_PAIR_3D + st["tests"] * FLOP_PER_TEST_3D
-        out["kept_pass"] = {"ms": kept_ms, "pairs": st["pairs"], "kept_candidates_tested": st["tests"],
-                            "tflops": kflops / (kept_ms * 1e-3) / 1e12}
+        kflops = st["pairs_kept"] * FLOP_PER_PAIR_3D + st["tests_kept"] * FLOP_PER_TEST_3D
+        out["kept_pass"] = {"ms": kept_ms, "pairs": st["pairs_kept"], "kept_candidates_tested": st["tests_kept"],
+                            "tflops": kflops / (kept_ms * 1e-3) / 1e12, "launches_per_step": kp["launches"] / steps}
     if clf is not None:
         out["fs_decided_by_mlp"] = st["n_mlp"]
         out["fs_fallback_exact"] = st["n_scan"]
     log(f"{label}: {ms_step:.2f} ms/step, {out['pair_evals_per_s']:.3e} pair-evals/s, "
-        f"pair pass {pair_ms:.2f} ms ({achieved:.1f} TFLOP/s)")
+        f"searching pair pass {pair_ms:.2f} ms x {pair['launches'] / steps:.2f} per step")
     if clf is not None:
         out["misclassification"] = misclassification(sim, case, clf)
         log(f"{label}: free-surface misclassification {out['misclassification']}")
@@ -330,6 +331,11 @@ def main():
                     help="cell size in units of h when the first stage's candidate lists serve the second (room "
                          "for a skin of (2 x keep-cell - 2) h); 0: no kept lists, cells of --cell h")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-across-steps", action="store_true",
+                    help="skip the runs with the candidate lists kept across steps")
+    ap.add_argument("--across-cell", type=float, default=1.03,
+                    help="cell size in units of h of the runs with the lists kept across steps (more room: longer "
+                         "lived lists, slightly more candidates)")
     ap.add_argument("--paths", default="fp64,mixed,mixed_learned",
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
                          "mixed_learned: mixed precision with the trained classifier and exact fallback")
@@ -435,6 +441,20 @@ def main():
     for k in ("mixed", "mixed_learned"):
         if k in results:
             out[f"{k}_over_fp64_step_rate"] = results["fp64"]["ms_per_step"] / results[k]["ms_per_step"]
+    if args.keep_cell > 0 and not args.no_across_steps:
+        # the lists kept across steps as well (SPH_F_KEEP_ACROSS_STEPS): from
+        # the bench's start (a state near rest: one build serves many steps)
+        # and from a moving state (seeded random velocities, |U| up to about
+        # 0.3 m/s), where the bound on the particles' moves runs out sooner
+        xs = wl.with_params(case, cell_size=args.across_cell * h, keep_lists=True, keep_across_steps=True)
+        moving = wl.random_velocity(xs, 0.05, 21)
+        out["keep_across_steps"] = {
+            "cell_size_over_h": args.across_cell,
+            "from_rest": run_path(xs, "fp64 across steps (near rest)", args.steps, args.warmup),
+            "moving": run_path(moving, "fp64 across steps (moving, |U| <= ~0.3 m/s)", args.steps, args.warmup),
+            "moving_within_step": run_path(wl.with_params(moving, keep_across_steps=False),
+                                           "fp64 within steps (moving)", args.steps, args.warmup),
+        }
     out["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:
         out["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)

@@ -67,17 +67,21 @@ typedef int32_t sph_status;
                              /* particle (without it, the learned mode computes */
                              /* them for free-surface candidates only)          */
 #define SPH_F_KEEP_LISTS 64u /* the first stage of a step keeps its candidate   */
-                             /* lists (radius 2h + s, s = 3 dt U_max plus a     */
-                             /* rounding margin: twice the bound on a           */
-                             /* particle's first-stage move), and the second    */
-                             /* stage runs from them                            */
-                             /* without a sort or a search; needs cells with    */
-                             /* room for s: ceil(2h/R) R - 2h > s.  A step that */
-                             /* lacks the room, or whose lists overflow 256     */
-                             /* entries per particle, rebuilds as without the   */
-                             /* flag.  Neighbour sets, and so results, are the  */
-                             /* same; about 1 KiB of workspace per fluid        */
-                             /* particle.                                       */
+                             /* lists (radius 2h + s, s the cells' room         */
+                             /* ceil(2h/R) R - 2h) and the second stage runs    */
+                             /* from them, without a sort or a search, when     */
+                             /* twice the bound on any particle's move since    */
+                             /* (1.5 dt U_max per first stage, 0.75 dt (U_max0  */
+                             /* + U_max1) per second) plus a rounding pad fits  */
+                             /* s; otherwise, or after a list overflow (more    */
+                             /* than 256 candidates for a particle), it sorts   */
+                             /* and searches.  Needs cells with room (R a       */
+                             /* little above 2h / ceil(2h/R)).  Neighbour sets, */
+                             /* and so results, are the same; about 1 KiB of    */
+                             /* workspace per fluid particle.                   */
+#define SPH_F_KEEP_ACROSS_STEPS 128u /* with SPH_F_KEEP_LISTS: the lists    */
+                             /* also serve later steps under the same bound     */
+                             /* (a step then sorts only when they run out)      */
 
 typedef struct sph_params {
     int32_t dim;        /* 2 or 3; gravity usually along the last axis          */
@@ -155,8 +159,8 @@ sph_status sph_build_cells(sph_ctx *ctx);
  * rebuild cells, mirror dummies (Eq. phiBn, slip), fused pair pass and
  * epilogue (Eqs. renorm, parGrad, lfsover, sph; delta-SPH, shifting, TIC),
  * free-surface detection, stage update.  Asynchronous, except that with
- * SPH_F_KEEP_LISTS each step waits once for its first stage (to choose how
- * the second runs). */
+ * SPH_F_KEEP_LISTS each stage first waits for the previous one (to choose
+ * between the kept lists and a rebuild). */
 sph_status sph_step(sph_ctx *ctx, int32_t nsteps, double dt_override);
 
 /* One right-hand side at the current state and time (no integration):
@@ -203,10 +207,11 @@ sph_status sph_fields(sph_ctx *ctx, int32_t field, void *out, int32_t out_on_dev
  * [10] singular-L count, [11] sum of fluid neighbour counts of the last
  * right-hand side (ordered pairs), [12] free-surface candidates of the last
  * right-hand side, [13] candidate pairs the last pair pass tested (distance
- * computations), [14] second stages run from kept candidate lists
- * (SPH_F_KEEP_LISTS), [15] second stages that rebuilt instead (no room for
- * the skin, or a list overflow), [16] and [17] the values of [11] and [13]
- * for the first stage of the last step, [18], [19] zero.  Synchronises. */
+ * computations), [14] right-hand sides of sph_step run from kept candidate
+ * lists (SPH_F_KEEP_LISTS), [15] right-hand sides of sph_step that sorted
+ * (and, with the flag, built new lists), [16] and [17] the values of [11] and
+ * [13] for the last right-hand side that searched, [18] and [19] for the last
+ * one that ran from kept lists (tests: kept candidates).  Synchronises. */
 sph_status sph_stats(sph_ctx *ctx, double out[20]);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around

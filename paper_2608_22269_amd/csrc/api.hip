@@ -84,6 +84,7 @@ struct sph_ctx {
   std::string err;
   bool cells_current;  // grid/order match the current positions
   bool rates_current;  // rates align with the current order
+  bool lists_valid;    // kept lists match the current order (no sort since their build)
   bool mixed;
 };
 
@@ -138,7 +139,9 @@ bool params_ok(const sph_params *p, std::string *why) {
   if (ncell > 2.0e9) return bad("too many cells");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->gravity[a]) || !std::isfinite(p->forcing_amp[a])) return bad("non-finite body force");
-  if (p->flags & ~127u) return bad("unknown flag bits");
+  if (p->flags & ~255u) return bad("unknown flag bits");
+  if ((p->flags & SPH_F_KEEP_ACROSS_STEPS) && !(p->flags & SPH_F_KEEP_LISTS))
+    return bad("SPH_F_KEEP_ACROSS_STEPS needs SPH_F_KEEP_LISTS");
   return true;
 }
 
@@ -380,11 +383,12 @@ sph_status rebuild(sph_ctx *c, int with_stage0) {
   }
   c->cells_current = true;
   c->rates_current = false;
+  c->lists_valid = false;  // indices of the kept lists refer to the old order
   return hip_check(c, e, "grid rebuild");
 }
 
-// Records of the current state in the current order (second stage from kept
-// lists: the cells and the order stay those of the first stage).
+// Records of the current state in the current order (a right-hand side from
+// kept lists: the cells and the order stay those of their build).
 sph_status refresh(sph_ctx *c) {
   ProfScope ps(c, 2);
   hipError_t e = c->mixed ? launch_refresh_mixed(c->P, c->g, c->mcur, c->nf, c->mrec, c->s)
@@ -394,9 +398,10 @@ sph_status refresh(sph_ctx *c) {
 
 // One right-hand side.  mode: the pair pass's kPairSearch / kPairSearchKeep /
 // kPairKept; win_extra widens the cell searches of the mirror and scan passes
-// (second stage over the first stage's cells: half the skin).
+// (over the cells of the kept lists' build: the bound on any particle's move
+// since).
 sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra = 0.0) {
-  hipError_t e = launch_stage_time(c->sc, stage, c->s);
+  hipError_t e = launch_stage_time(c->sc, stage, c->s, mode);
   const bool feat = (c->p.flags & SPH_F_FEATURES) || c->p.fs_mode == SPH_FS_LEARNED;
   Phys Pw = c->P;
   Pw.win = c->P.two_h + win_extra;
@@ -578,6 +583,7 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   c->status = SPH_OK;
   c->has_clf = false;
   c->n_kept = c->n_rebuilt = 0.0;
+  c->lists_valid = false;
   c->profiling = false;
   c->ev_used = 0;
   for (int k = 0; k < 8; ++k) c->prof_ms[k] = c->prof_cnt[k] = 0.0;
@@ -757,6 +763,39 @@ sph_status sph_eval_rates(sph_ctx *c) {
   return st;
 }
 
+// The right-hand side of one stage of a step.  With SPH_F_KEEP_LISTS the
+// kept lists serve the second stage (and with SPH_F_KEEP_ACROSS_STEPS any
+// stage) while they are valid (no sort since their build, no overflow) and
+// twice the bound on any particle's move since their build, plus the
+// rounding pad, fits their skin: a pair within 2h now was within 2h + skin
+// at the build.  The bound lives on the device; reading it costs one
+// synchronisation.  Otherwise the stage sorts, searches and builds new lists.
+sph_status stage_rhs(sph_ctx *c, int stage) {
+  if (!c->kent) {
+    sph_status st = rebuild(c, stage == 2);
+    return st == SPH_OK ? rhs(c, stage) : st;
+  }
+  bool reuse = false;
+  double disp = 0.0;
+  if (c->lists_valid && (stage == 2 || (c->p.flags & SPH_F_KEEP_ACROSS_STEPS))) {
+    Scalars h;
+    sph_status st = read_scalars(c, &h);
+    if (st != SPH_OK) return st;
+    disp = h.disp;
+    reuse = h.vovf == 0u && h.err == 0u && 2.0 * disp + c->P.skin_pad <= c->P.skin_max;
+  }
+  if (reuse) {
+    c->n_kept += 1.0;
+    sph_status st = refresh(c);
+    return st == SPH_OK ? rhs(c, stage, kPairKept, disp) : st;
+  }
+  c->n_rebuilt += 1.0;
+  sph_status st = rebuild(c, stage == 2);
+  if (st == SPH_OK) st = rhs(c, stage, kPairSearchKeep);
+  if (st == SPH_OK) c->lists_valid = true;
+  return st;
+}
+
 sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
   sph_status st = usable(c);
   if (st != SPH_OK) return st;
@@ -764,34 +803,21 @@ sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
   for (int32_t k = 0; k < nsteps && st == SPH_OK; ++k) {
     st = umax_of_current(c);
     if (st == SPH_OK) st = hip_check(c, launch_dt(c->P, c->sc, dt_override, c->s), "time step");
-    const bool keep = c->kent != nullptr;
-    if (st == SPH_OK) st = rebuild(c, 0);
-    if (st == SPH_OK) st = rhs(c, 1, keep ? kPairSearchKeep : kPairSearch);
+    if (st == SPH_OK) st = stage_rhs(c, 1);
     if (st == SPH_OK) {
       ProfScope ps(c, 4);
       hipError_t e = c->mixed ? launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, 1, c->s)
                               : launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, 1, c->s);
+      if (e == hipSuccess && c->kent) e = launch_disp_add(c->sc, 1, c->s);
       st = hip_check(c, e, "stage 1");
     }
-    // second stage from the kept lists when the step's skin fit the cells and
-    // no wave overflowed them (both known on the device once stage 1 ran)
-    bool kept = false;
-    double skin = 0.0;
-    if (st == SPH_OK && keep) {
-      Scalars h;
-      st = read_scalars(c, &h);
-      kept = st == SPH_OK && h.vok != 0u && h.vovf == 0u && h.err == 0u;
-      skin = h.skin;
-      if (kept) c->n_kept += 1.0;
-      else c->n_rebuilt += 1.0;
-    }
     if (st == SPH_OK) st = umax_of_current(c);
-    if (st == SPH_OK) st = kept ? refresh(c) : rebuild(c, 1);
-    if (st == SPH_OK) st = kept ? rhs(c, 2, kPairKept, 0.5 * skin) : rhs(c, 2);
+    if (st == SPH_OK) st = stage_rhs(c, 2);
     if (st == SPH_OK) {
       ProfScope ps(c, 4);
       hipError_t e = c->mixed ? launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, 2, c->s)
                               : launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, 2, c->s);
+      if (e == hipSuccess && c->kent) e = launch_disp_add(c->sc, 2, c->s);
       if (e == hipSuccess) e = launch_advance_time(c->sc, c->s);
       if (e == hipSuccess && !c->mixed) e = launch_check_state(c->dim, c->cur, c->nf, c->sc, c->s);
       st = hip_check(c, e, "stage 2");
@@ -836,8 +862,11 @@ sph_status sph_stats(sph_ctx *c, double out[20]) {
   out[13] = (double)h.tests;
   out[14] = c->n_kept;
   out[15] = c->n_rebuilt;
-  out[16] = (double)h.pairs1;
-  out[17] = (double)h.tests1;
+  const bool last_kept = h.mode == (uint32_t)kPairKept;
+  out[16] = (double)(last_kept ? h.pairs_s : h.pairs);
+  out[17] = (double)(last_kept ? h.tests_s : h.tests);
+  out[18] = (double)(last_kept ? h.pairs : h.pairs_k);
+  out[19] = (double)(last_kept ? h.tests : h.tests_k);
   return c->status != SPH_OK ? c->status : SPH_OK;
 }
 

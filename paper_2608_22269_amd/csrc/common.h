@@ -111,8 +111,8 @@ struct Phys {
   double lambda_tic, lambda_lo, lambda_hi, lambda_sing;
   double grav[3], famp[3], fomega;
   double cfl, nu, gmax;   // gmax = max_t |G(t)|
-  double skin_max;        // room for a list skin: reach R - 2h (0: lists not kept)
-  double skin_pad;        // absolute part of the skin (rounding of the positions)
+  double skin_max;        // skin of kept lists: the cells' room reach R - 2h (0: none)
+  double skin_pad;        // part of the skin reserved for the rounding of positions
   double win;             // window radius of the mirror and scan cell searches:
                           // 2h, wider over the first stage's cells (second stage)
 };
@@ -130,12 +130,15 @@ struct Scalars {
   uint32_t n_cand;   // candidates listed by the pair pass
   uint32_t n_scan;   // candidates sent to the scan pass
   uint32_t n_fs, n_cons, n_sing, n_mlp;
-  uint32_t vok;      // this step's first-stage candidate lists serve the second stage
+  uint32_t pad_;
   double steps;
-  double skin;       // their skin: twice the bound on a particle's first-stage move
-  uint32_t vovf;     // a wave's candidates exceeded the kept chunks
-  uint32_t pad2_;
-  unsigned long long pairs1, tests1;  // pairs and tests of the last step's first stage
+  double disp;       // bound on any particle's move since the kept lists were built
+  double umax1;      // U_max of the current step's first stage
+  uint32_t vovf;     // a lane's candidates exceeded the kept chunks at the last build
+  uint32_t mode;     // pair-pass mode of the last right-hand side (kPairSearch...)
+  // pairs and tests of the last right-hand side that searched (s) and of the
+  // last one that ran from kept lists (k), before the current one
+  unsigned long long pairs_s, tests_s, pairs_k, tests_k;
 };
 
 // Fluid state, FP64 path, sorted by (cell, original index).

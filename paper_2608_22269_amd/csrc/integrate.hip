@@ -62,20 +62,9 @@ __global__ void k_dt(Phys P, Scalars *sc, double dt_override) {
   if (P.nu > 0.0) dt = fmin(dt, P.dx * P.dx / (2.0 * P.nu));
   if (P.gmax > 0.0) dt = fmin(dt, sqrt(2.0 * P.dx / P.gmax));
   dt *= P.cfl;
-  dt = dt_override > 0.0 ? dt_override : dt;
-  sc->dt = dt;
+  sc->dt = dt_override > 0.0 ? dt_override : dt;
   sc->umax = umax;
   sc->t_rhs = sc->t;
-  // Candidate lists of the first stage for the second: the first stage moves
-  // a particle by dt |U + dU| <= 1.5 dt U_max (|U| <= U_max, the shifting
-  // velocity is clamped to U_max / 2), so a pair within 2h after it was
-  // within 2h + 3 dt U_max before.  A relative margin above the rounding of
-  // this bound and of FP32 velocities, and an absolute one (P.skin_pad)
-  // above the rounding of the positions and of the distance tests.
-  const double skin = 3.0 * dt * umax * (1.0 + 1e-6) + P.skin_pad;
-  const bool ok = P.skin_max > 0.0 && skin <= P.skin_max;
-  sc->vok = ok ? 1u : 0u;
-  sc->skin = ok ? skin : 0.0;
 }
 
 hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t s) {
@@ -85,10 +74,18 @@ hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t
 
 // Stage bookkeeping: U_max of the stage and the time of its right-hand side
 // (stage 1 at t, stage 2 at t + dt); statistics counters restart.
-__global__ void k_stage_time(Scalars *sc, int stage) {
-  if (stage == 2) {
-    sc->pairs1 = sc->pairs;
-    sc->tests1 = sc->tests;
+__global__ void k_stage_time(Scalars *sc, int stage, int mode) {
+  if (sc->mode == (uint32_t)kPairKept) {  // statistics of the previous right-hand side by kind
+    sc->pairs_k = sc->pairs;
+    sc->tests_k = sc->tests;
+  } else {
+    sc->pairs_s = sc->pairs;
+    sc->tests_s = sc->tests;
+  }
+  sc->mode = (uint32_t)mode;
+  if (mode == kPairSearchKeep) {  // this right-hand side builds new kept lists
+    sc->disp = 0.0;
+    sc->vovf = 0u;
   }
   sc->umax = sqrt(__longlong_as_double((long long)sc->umax2_bits));
   sc->t_rhs = stage == 2 ? sc->t + sc->dt : sc->t;
@@ -100,11 +97,31 @@ __global__ void k_stage_time(Scalars *sc, int stage) {
   sc->n_mlp = 0;
   sc->pairs = 0ull;
   sc->tests = 0ull;
-  if (stage == 1) sc->vovf = 0u;
 }
 
-hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s) {
-  hipLaunchKernelGGL(k_stage_time, dim3(1), dim3(1), 0, s, sc, stage);
+hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s, int mode) {
+  hipLaunchKernelGGL(k_stage_time, dim3(1), dim3(1), 0, s, sc, stage, mode);
+  return hipGetLastError();
+}
+
+// Bound on the move of every particle by the stage update just made (Sec.
+// 2.3), added to sc->disp.  Stage 1: x1 - x0 = dt (U0 + dU0), |U0| <= U_max0
+// and the shifting velocity is clamped to U_max0 / 2, so |x1 - x0| <= 1.5 dt
+// U_max0.  Stage 2: x2 - x1 = (dt (U1 + dU1) - dt (U0 + dU0)) / 2, so
+// |x2 - x1| <= 0.75 dt (U_max0 + U_max1).  The relative margin covers the
+// rounding of the bound and of FP32 velocities.
+__global__ void k_disp_add(Scalars *sc, int stage) {
+  const double dt = sc->dt;
+  if (stage == 1) {
+    sc->umax1 = sc->umax;
+    sc->disp += 1.5 * dt * sc->umax * (1.0 + 1e-6);
+  } else {
+    sc->disp += 0.75 * dt * (sc->umax1 + sc->umax) * (1.0 + 1e-6);
+  }
+}
+
+hipError_t launch_disp_add(Scalars *sc, int stage, hipStream_t s) {
+  hipLaunchKernelGGL(k_disp_add, dim3(1), dim3(1), 0, s, sc, stage);
   return hipGetLastError();
 }
 

@@ -58,7 +58,11 @@ hipError_t launch_sort_rows(const uint32_t *off, int64_t r0, int64_t r1, int32_t
 hipError_t launch_umax(int dim, const double *const u[3], const float *const uf[3], int64_t nf, Scalars *sc,
                        hipStream_t s);
 hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t s);
-hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s);
+// stage bookkeeping; mode: the right-hand side's pair-pass mode (kPairSearch,
+// kPairSearchKeep: it builds new kept lists, kPairKept)
+hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s, int mode = 0);
+// adds the bound on a particle's move by the stage update just made to sc->disp
+hipError_t launch_disp_add(Scalars *sc, int stage, hipStream_t s);
 hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, const Scalars *sc,
                             int stage, hipStream_t s);
 hipError_t launch_advance_time(Scalars *sc, hipStream_t s);

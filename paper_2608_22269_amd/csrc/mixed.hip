@@ -401,8 +401,8 @@ __device__ __forceinline__ void mixed_body(const MixedI &I, const float4 &b0, co
 
 // The mixed pair pass with its own candidate search (FP32 test on the
 // absolute FP32 positions).  KEEP: as for the FP64 pass -- search radius
-// 2h + skin on the first stage of a step whose skin fits (sc->vok), tagged
-// skin candidates skipped by the body, non-empty list fills kept in kl.
+// 2h + skin, tagged skin candidates skipped by the body, non-empty list
+// fills kept in kl.
 template <int DIM, bool FEAT, bool PST4, bool KEEP>
 __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     k_pair_mixed(Phys P, Grid g, MixedRec rec, const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
@@ -422,27 +422,33 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
   }
   const MixedI I = mixed_i(P, g, a0, a1, phii);
   const float two_h2 = (float)P.two_h2;
-  const bool keep = KEEP && sc->vok != 0u;
-  const double rho = keep ? P.two_h + sc->skin : P.two_h;
+  const bool keep = KEEP && P.skin_max > 0.0;
+  const double rho = keep ? P.two_h + P.skin_max : P.two_h;
   const float rho2 = keep ? (float)(rho * rho) : two_h2;
-  int chunk = 0;
-  unsigned long long counts = 0ull;  // this lane's packed chunk counts
+  // this lane's kept-list bookkeeping in LDS (packed chunk counts, chunks
+  // so far at bit kKeptNchShift, saturating at 15): touched once per fill,
+  // it holds no registers through the search
+  __shared__ unsigned long long kbook[KEEP ? kBlock : 1];
+  if (KEEP) kbook[tid] = 0ull;
 
   PairSums S;
   sums_zero(S);
 
   // dense pair body over the first cnt entries of this lane's list
   auto run_list = [&](int cnt) {
-    if (keep) {  // copy the fill for the second stage
+    if (keep) {  // copy the fill for the later right-hand sides
       const int kmax = wave_max_int(cnt);
+      unsigned long long book = kbook[tid];
+      const int chunk = (int)(book >> kKeptNchShift);
       const bool room = chunk < kKeepChunks;
       uint32_t *dst = kl.ent + kept_entry(i, min(chunk, kKeepChunks - 1), 0);
       for (int k = 0; k < kmax; ++k)
         if (room && k < cnt) dst[(size_t)k * 64u] = list[k][tid];
       if (cnt > 0) {
-        if (room) counts |= (unsigned long long)cnt << (6 * chunk);
+        if (room) book |= (unsigned long long)cnt << (6 * chunk);
         else sc->vovf = 1u;
-        ++chunk;
+        book = (book & ((1ull << kKeptNchShift) - 1ull)) | ((unsigned long long)min(chunk + 1, 15) << kKeptNchShift);
+        kbook[tid] = book;
       }
     }
     MixedChunk C;
@@ -483,13 +489,17 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     cnt = 0;
     if (fin) break;
   }
-  if (keep) kl.cnt[i] = counts | ((unsigned long long)min(chunk, kKeepChunks) << kKeptNchShift);
+  if (keep) {
+    const unsigned long long book = kbook[tid];
+    const int nch = min((int)(book >> kKeptNchShift), kKeepChunks);
+    kl.cnt[i] = (book & ((1ull << kKeptNchShift) - 1ull)) | ((unsigned long long)nch << kKeptNchShift);
+  }
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
 }
 
-// Second stage of a step from the first stage's kept candidates: the same FP32
-// test as the search, on the refreshed records, then the same body, one FP32
-// chunk sum per kept chunk.
+// A right-hand side from kept candidates: the same FP32 test as the search,
+// on the refreshed records, then the same body, one FP32 chunk sum per kept
+// chunk.
 template <int DIM, bool FEAT, bool PST4>
 __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     k_pair_kept_mixed(Phys P, Grid g, MixedRec rec, uint32_t nf, Scalars *sc, Rates out,

@@ -177,11 +177,12 @@ __device__ __forceinline__ void pair_body_f64(const Phys &P, const double4 &a0, 
   }
 }
 
-// The pair pass with its own candidate search (Algorithm 1).  KEEP (first
-// stage of a step whose skin fits the cells, sc->vok): the search radius
-// grows to 2h + skin, candidates beyond 2h enter the LDS list tagged and are
-// skipped by the body, and every non-empty list fill is also copied to kl for
-// the second stage; a lane with more than kKeepChunks fills raises sc->vovf.
+// The pair pass with its own candidate search (Algorithm 1).  KEEP (the
+// right-hand side that builds kept lists): the search radius grows to
+// 2h + skin (P.skin_max), candidates beyond 2h enter the LDS list tagged and
+// are skipped by the body, and every non-empty list fill is also copied to kl
+// for the later right-hand sides; a lane with more than kKeepChunks fills
+// raises sc->vovf.
 template <int DIM, bool FEAT, bool PST4, bool KEEP>
 __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
                                                   const double4 *__restrict__ rec1, const uint32_t *__restrict__ cs_f,
@@ -199,24 +200,30 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
   }
   PairSums S;
   sums_zero(S);
-  const bool keep = KEEP && sc->vok != 0u;
-  const double rho = keep ? P.two_h + sc->skin : P.two_h;
+  const bool keep = KEEP && P.skin_max > 0.0;
+  const double rho = keep ? P.two_h + P.skin_max : P.two_h;
   const double rho2 = keep ? rho * rho : P.two_h2;
-  int chunk = 0;
-  unsigned long long counts = 0ull;  // this lane's packed chunk counts
+  // this lane's kept-list bookkeeping in LDS (packed chunk counts, chunks
+  // so far at bit kKeptNchShift, saturating at 15): touched once per fill,
+  // it holds no registers through the search
+  __shared__ unsigned long long kbook[KEEP ? kBlock : 1];
+  if (KEEP) kbook[tid] = 0ull;
 
   // consume the first cnt entries of this lane's list
   auto run_list = [&](int cnt) {
-    if (keep) {  // copy the fill for the second stage
+    if (keep) {  // copy the fill for the later right-hand sides
       const int kmax = wave_max_int(cnt);
+      unsigned long long book = kbook[tid];
+      const int chunk = (int)(book >> kKeptNchShift);
       const bool room = chunk < kKeepChunks;
       uint32_t *dst = kl.ent + kept_entry(i, min(chunk, kKeepChunks - 1), 0);
       for (int k = 0; k < kmax; ++k)
         if (room && k < cnt) dst[(size_t)k * 64u] = list[k][tid];
       if (cnt > 0) {
-        if (room) counts |= (unsigned long long)cnt << (6 * chunk);
+        if (room) book |= (unsigned long long)cnt << (6 * chunk);
         else sc->vovf = 1u;
-        ++chunk;
+        book = (book & ((1ull << kKeptNchShift) - 1ull)) | ((unsigned long long)min(chunk + 1, 15) << kKeptNchShift);
+        kbook[tid] = book;
       }
     }
     // one neighbour per iteration, the next list entry read one iteration ahead
@@ -252,15 +259,20 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
     cnt = 0;
     if (fin) break;
   }
-  if (keep) kl.cnt[i] = counts | ((unsigned long long)min(chunk, kKeepChunks) << kKeptNchShift);
+  if (keep) {
+    const unsigned long long book = kbook[tid];
+    const int nch = min((int)(book >> kKeptNchShift), kKeepChunks);
+    kl.cnt[i] = (book & ((1ull << kKeptNchShift) - 1ull)) | ((unsigned long long)nch << kKeptNchShift);
+  }
 
   pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
 }
 
-// Second stage of a step from the first stage's kept candidates (no search):
-// the records hold the second-stage state in the first stage's order, every
-// kept candidate is tested exactly against 2h and the neighbours run the same
-// body.  A pair within 2h now was within 2h + skin at the first stage, so the
+// A right-hand side from kept candidates (no search): the records hold the
+// current state in the order of the build, every kept candidate is tested
+// exactly against 2h and the neighbours run the same body.  The caller uses
+// the lists only while twice the bound on any particle's move since the build
+// fits the skin: a pair within 2h now was within 2h + skin then, so the
 // neighbour sets are those of a fresh search.
 template <int DIM, bool FEAT, bool PST4>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WB_KEPT_WAVES))) k_pair_kept_f64(Phys P, const double4 *__restrict__ rec0,

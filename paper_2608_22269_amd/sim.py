@@ -126,7 +126,8 @@ class Simulation:
         out = np.zeros(20)
         _check(L.lib().sph_stats(self.ctx, out.ctypes.data_as(C.c_void_p)), "sph_stats", self.ctx)
         keys = ["t", "dt", "steps", "umax", "n_fluid", "n_dummy", "n_fs", "n_cons", "n_scan", "n_mlp",
-                "n_singular", "pairs", "n_cand", "tests", "n_kept", "n_rebuilt", "pairs_stage1", "tests_stage1"]
+                "n_singular", "pairs", "n_cand", "tests", "n_kept", "n_rebuilt", "pairs_search", "tests_search",
+                "pairs_kept", "tests_kept"]
         return {k: float(out[i]) for i, k in enumerate(keys)}
 
     def profile(self, enable=True):

@@ -50,8 +50,13 @@ def test_validate_and_workspace(L):
     q.cell_size = 0.5 * q.h  # reach 4 > 3
     assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
     q = L.params_from_dict(c["params"])
-    q.flags |= 128  # no such flag
+    q.flags |= 256  # no such flag
     assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+    q = L.params_from_dict(c["params"])
+    q.flags |= L.SPH_F_KEEP_ACROSS_STEPS  # needs SPH_F_KEEP_LISTS
+    assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+    q.flags |= L.SPH_F_KEEP_LISTS
+    assert lib.sph_validate(C.byref(q)) == L.SPH_OK
 
 
 def test_kept_lists_workspace(L):
