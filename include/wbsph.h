@@ -81,7 +81,9 @@ typedef int32_t sph_status;
                              /* workspace per fluid particle.                   */
 #define SPH_F_KEEP_ACROSS_STEPS 128u /* with SPH_F_KEEP_LISTS: the lists    */
                              /* also serve later steps under the same bound     */
-                             /* (a step then sorts only when they run out)      */
+                             /* (a step then sorts only when they run out; a    */
+                             /* particle that leaves the domain is reported at  */
+                             /* the next sort)                                  */
 
 typedef struct sph_params {
     int32_t dim;        /* 2 or 3; gravity usually along the last axis          */

@@ -85,6 +85,8 @@ struct sph_ctx {
   bool cells_current;  // grid/order match the current positions
   bool rates_current;  // rates align with the current order
   bool lists_valid;    // kept lists match the current order (no sort since their build)
+  bool umax_fresh;     // sc->umax2_bits holds max |U|^2 of the current state
+  bool recs_fresh;     // the neighbour records hold the current state
   bool mixed;
 };
 
@@ -384,12 +386,15 @@ sph_status rebuild(sph_ctx *c, int with_stage0) {
   c->cells_current = true;
   c->rates_current = false;
   c->lists_valid = false;  // indices of the kept lists refer to the old order
+  c->recs_fresh = true;    // the reorder wrote them
   return hip_check(c, e, "grid rebuild");
 }
 
 // Records of the current state in the current order (a right-hand side from
 // kept lists: the cells and the order stay those of their build).
 sph_status refresh(sph_ctx *c) {
+  if (c->recs_fresh) return SPH_OK;  // the stage update wrote them
+  c->recs_fresh = true;
   ProfScope ps(c, 2);
   hipError_t e = c->mixed ? launch_refresh_mixed(c->P, c->g, c->mcur, c->nf, c->mrec, c->s)
                           : launch_refresh_f64(c->P, c->cur, c->nf, c->rec0, c->rec1, c->s);
@@ -456,6 +461,8 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
 }
 
 sph_status umax_of_current(sph_ctx *c) {
+  if (c->umax_fresh) return SPH_OK;  // the stage update computed it
+  c->umax_fresh = true;
   ProfScope ps(c, 4);
   hipError_t e;
   if (!c->mixed) {
@@ -584,6 +591,7 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   c->has_clf = false;
   c->n_kept = c->n_rebuilt = 0.0;
   c->lists_valid = false;
+  c->umax_fresh = c->recs_fresh = false;
   c->profiling = false;
   c->ev_used = 0;
   for (int k = 0; k < 8; ++k) c->prof_ms[k] = c->prof_cnt[k] = 0.0;
@@ -796,6 +804,29 @@ sph_status stage_rhs(sph_ctx *c, int stage) {
   return st;
 }
 
+// The stage update of SSP-RK2.  The FP64 update also computes max |U| of the
+// new state (for the next right-hand side or step), checks it for
+// finiteness after the second stage, and writes the neighbour records when
+// the next right-hand side may run from kept lists (it then needs no
+// refresh).
+sph_status stage_update(sph_ctx *c, int stage) {
+  ProfScope ps(c, 4);
+  hipError_t e;
+  if (c->mixed) {
+    e = launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, stage, c->s);
+    c->umax_fresh = c->recs_fresh = false;
+  } else {
+    const bool recs = c->kent && c->lists_valid && (stage == 1 || (c->p.flags & SPH_F_KEEP_ACROSS_STEPS));
+    e = launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, stage, c->s, recs ? c->rec0 : nullptr,
+                         recs ? c->rec1 : nullptr, stage == 2 ? 1 : 0);
+    c->umax_fresh = true;
+    c->recs_fresh = recs;
+  }
+  if (e == hipSuccess && c->kent) e = launch_disp_add(c->sc, stage, c->s);
+  if (e == hipSuccess && stage == 2) e = launch_advance_time(c->sc, c->s);
+  return hip_check(c, e, stage == 1 ? "stage 1" : "stage 2");
+}
+
 sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
   sph_status st = usable(c);
   if (st != SPH_OK) return st;
@@ -804,24 +835,10 @@ sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
     st = umax_of_current(c);
     if (st == SPH_OK) st = hip_check(c, launch_dt(c->P, c->sc, dt_override, c->s), "time step");
     if (st == SPH_OK) st = stage_rhs(c, 1);
-    if (st == SPH_OK) {
-      ProfScope ps(c, 4);
-      hipError_t e = c->mixed ? launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, 1, c->s)
-                              : launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, 1, c->s);
-      if (e == hipSuccess && c->kent) e = launch_disp_add(c->sc, 1, c->s);
-      st = hip_check(c, e, "stage 1");
-    }
+    if (st == SPH_OK) st = stage_update(c, 1);
     if (st == SPH_OK) st = umax_of_current(c);
     if (st == SPH_OK) st = stage_rhs(c, 2);
-    if (st == SPH_OK) {
-      ProfScope ps(c, 4);
-      hipError_t e = c->mixed ? launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, 2, c->s)
-                              : launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, 2, c->s);
-      if (e == hipSuccess && c->kent) e = launch_disp_add(c->sc, 2, c->s);
-      if (e == hipSuccess) e = launch_advance_time(c->sc, c->s);
-      if (e == hipSuccess && !c->mixed) e = launch_check_state(c->dim, c->cur, c->nf, c->sc, c->s);
-      st = hip_check(c, e, "stage 2");
-    }
+    if (st == SPH_OK) st = stage_update(c, 2);
     c->cells_current = false;
   }
   return st;

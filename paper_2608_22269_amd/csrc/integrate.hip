@@ -148,44 +148,82 @@ hipError_t launch_advance_time(Scalars *sc, hipStream_t s) {
 // ------------------------------------------------------------ SSP-RK2, FP64
 // Stage 1: phi1 = phi + dt Dphi, U1 = U + dt a, x1 = x + dt (U + dU).
 // Stage 2: q = 1/2 q0 + 1/2 (q1 + dt rate(q1)) for phi, U and x.
-// Written without contraction, as the equations are printed.
+// Written without contraction, as the equations are printed.  The kernel
+// also folds max |U|^2 of the new state into sc->umax2_bits (reset by the
+// caller), checks the new phi and U for finiteness when asked, and writes the
+// neighbour records of the new state (rec0 = (x, phi), rec1 = (U, V), as the
+// reorder writes them) when rec0 is given.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_stage_f64(FluidF64 f, Rates r, int64_t n, const Scalars *__restrict__ sc,
-                                                   int stage) {
+__global__ void __launch_bounds__(256) k_stage_f64(Phys P, FluidF64 f, Rates r, int64_t n, Scalars *sc, int stage,
+                                                   double4 *__restrict__ rec0, double4 *__restrict__ rec1,
+                                                   int check) {
 #pragma clang fp contract(off)
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double dt = sc->dt;
-  if (stage == 1) {
-    double ph = f.phi[i];
-    f.phi0[i] = ph;
-    f.phi[i] = ph + dt * r.dphi[i];
+  __shared__ double sh[kBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double u2 = 0.0;
+  if (i < n) {
+    const double dt = sc->dt;
+    double xn[3] = {0.0, 0.0, 0.0}, un[3] = {0.0, 0.0, 0.0}, pn;
+    if (stage == 1) {
+      const double ph = f.phi[i];
+      f.phi0[i] = ph;
+      pn = ph + dt * r.dphi[i];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double x = f.x[a][i], u = f.u[a][i];
+        f.x0[a][i] = x;
+        f.u0[a][i] = u;
+        un[a] = u + dt * r.acc[a][i];
+        xn[a] = x + dt * (u + r.dus[a][i]);
+      }
+    } else {
+      pn = 0.5 * f.phi0[i] + 0.5 * (f.phi[i] + dt * r.dphi[i]);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double u1 = f.u[a][i];
+        un[a] = 0.5 * f.u0[a][i] + 0.5 * (u1 + dt * r.acc[a][i]);
+        xn[a] = 0.5 * f.x0[a][i] + 0.5 * (f.x[a][i] + dt * (u1 + r.dus[a][i]));
+      }
+    }
+    f.phi[i] = pn;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      double x = f.x[a][i], u = f.u[a][i];
-      f.x0[a][i] = x;
-      f.u0[a][i] = u;
-      f.u[a][i] = u + dt * r.acc[a][i];
-      f.x[a][i] = x + dt * (u + r.dus[a][i]);
+      f.u[a][i] = un[a];
+      f.x[a][i] = xn[a];
     }
-  } else {
-    f.phi[i] = 0.5 * f.phi0[i] + 0.5 * (f.phi[i] + dt * r.dphi[i]);
+    u2 = un[0] * un[0] + un[1] * un[1] + un[2] * un[2];
+    if (check) {
+      bool ok = isfinite(pn);
+      for (int a = 0; a < DIM; ++a) ok = ok && isfinite(un[a]);
+      if (!ok) atomicOr(&sc->err, kErrNonFinite);
+    }
+    if (rec0) {
+      const double V = f.m[i] / (P.rho0 * exp(pn * P.inv_c02));
+      rec0[i] = make_double4(xn[0], xn[1], xn[2], pn);
+      rec1[i] = make_double4(un[0], un[1], un[2], V);
+    }
+  }
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      double u1 = f.u[a][i];
-      f.u[a][i] = 0.5 * f.u0[a][i] + 0.5 * (u1 + dt * r.acc[a][i]);
-      f.x[a][i] = 0.5 * f.x0[a][i] + 0.5 * (f.x[a][i] + dt * (u1 + r.dus[a][i]));
-    }
+  for (int o = 32; o > 0; o >>= 1) u2 = fmax(u2, __shfl_xor(u2, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = u2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = sh[0];
+    for (int w = 1; w < kBlock / 64; ++w) b = fmax(b, sh[w]);
+    atomicMax(&sc->umax2_bits, (unsigned long long)__double_as_longlong(b));
   }
 }
 
-hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, const Scalars *sc,
-                            int stage, hipStream_t s) {
-  if (nf <= 0) return hipSuccess;
+hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, Scalars *sc, int stage,
+                            hipStream_t s, double4 *rec0, double4 *rec1, int check) {
+  hipLaunchKernelGGL(k_reset_umax, dim3(1), dim3(1), 0, s, sc);
+  if (nf <= 0) return hipGetLastError();
   if (P.dim == 2)
-    hipLaunchKernelGGL(k_stage_f64<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, f, r, nf, sc, stage);
+    hipLaunchKernelGGL(k_stage_f64<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, f, r, nf, sc, stage, rec0, rec1,
+                       check);
   else
-    hipLaunchKernelGGL(k_stage_f64<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, f, r, nf, sc, stage);
+    hipLaunchKernelGGL(k_stage_f64<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, f, r, nf, sc, stage, rec0, rec1,
+                       check);
   return hipGetLastError();
 }
 
@@ -423,26 +461,6 @@ __global__ void k_gather_dummies(const uint32_t *__restrict__ perm, int64_t nd, 
 hipError_t launch_gather_dummies(const uint32_t *perm, int64_t nd, Dummies src, Dummies dst, int dim, hipStream_t s) {
   if (nd <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_dummies, dim3(grid_for(nd)), dim3(kBlock), 0, s, perm, nd, src, dst, dim);
-  return hipGetLastError();
-}
-
-// Non-finite state check (velocity and potential); positions are checked by
-// the hash kernel.
-template <int DIM>
-__global__ void k_check_state(FluidF64 f, int64_t n, Scalars *sc) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  bool ok = isfinite(f.phi[i]);
-  for (int a = 0; a < DIM; ++a) ok = ok && isfinite(f.u[a][i]);
-  if (!ok) atomicOr(&sc->err, kErrNonFinite);
-}
-
-hipError_t launch_check_state(int dim, const FluidF64 &f, int64_t nf, Scalars *sc, hipStream_t s) {
-  if (nf <= 0) return hipSuccess;
-  if (dim == 2)
-    hipLaunchKernelGGL(k_check_state<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, f, nf, sc);
-  else
-    hipLaunchKernelGGL(k_check_state<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, f, nf, sc);
   return hipGetLastError();
 }
 

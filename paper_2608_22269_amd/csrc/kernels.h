@@ -63,8 +63,11 @@ hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t
 hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s, int mode = 0);
 // adds the bound on a particle's move by the stage update just made to sc->disp
 hipError_t launch_disp_add(Scalars *sc, int stage, hipStream_t s);
-hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, const Scalars *sc,
-                            int stage, hipStream_t s);
+// SSP-RK2 stage update (FP64); also max |U|^2 of the new state into
+// sc->umax2_bits (reset here), a finiteness check of phi and U (check != 0)
+// and the neighbour records of the new state (rec0 != nullptr)
+hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, Scalars *sc, int stage,
+                            hipStream_t s, double4 *rec0 = nullptr, double4 *rec1 = nullptr, int check = 0);
 hipError_t launch_advance_time(Scalars *sc, hipStream_t s);
 hipError_t launch_set_time(Scalars *sc, double t, hipStream_t s);
 hipError_t launch_gather_f64(const double *src, const uint32_t *id, int64_t n, double *dst, int stride, int comp,
@@ -96,6 +99,5 @@ hipError_t launch_kind_flags(const uint8_t *kind, int64_t n, uint32_t *is_fluid,
                              hipStream_t s);
 hipError_t launch_gather_dummies(const uint32_t *perm, int64_t nd, Dummies src, Dummies dst, int dim,
                                  hipStream_t s);
-hipError_t launch_check_state(int dim, const FluidF64 &f, int64_t nf, Scalars *sc, hipStream_t s);
 
 }  // namespace wb
