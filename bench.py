@@ -4,11 +4,16 @@ Workload (default): 3D sloshing tank 1.0 x 0.5 x 0.56 m, water depth 0.28 m,
 dx = 0.002 m -> 17,500,000 fluid + 2,047,296 wall dummies, horizontal tank
 forcing (A = 5 mm, period 1.2x the first natural period), delta-SPH,
 shifting, TIC and free-surface detection on.  A step is one full SSP-RK2 step:
-two right-hand sides, each with grid rebuild, wall mirror, fused pair pass,
-free-surface detection and stage update, plus the device-side dt reduction.
+two right-hand sides, each with wall mirror, fused pair pass, free-surface
+detection and stage update, plus the device-side dt reduction; the first
+sorts the particles into cells (hash, counting sort, reorder) and keeps its
+candidate lists, the second runs from them (cells of 1.01 h leave room for
+the lists' skin; --keep-cell 0 sorts and searches at both right-hand sides).
 
 Prints one JSON line (metric, value = pair evaluations per second of the
-headline path, ms/step, roofline of the pair pass, CPU oracle baseline).
+headline path, ms/step, rooflines of the pair passes, CPU oracle baseline,
+the mixed and learned paths, the lists kept across steps, MLP inference,
+spurious velocities).
 """
 from __future__ import annotations
 

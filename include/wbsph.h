@@ -219,8 +219,9 @@ sph_status sph_stats(sph_ctx *ctx, double out[20]);
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * each launch group while enabled: [0] pair pass with its own search, [1]
  * wall mirror, [2] grid rebuild (hash, sort, reorder; or the record refresh of
- * a second stage from kept lists), [3] free-surface detection, [4] stage
- * updates and reductions, [5] pair pass from kept lists.  sph_profile_read synchronises and writes
+ * a right-hand side from kept lists), [3] free-surface detection, [4] stage
+ * updates and reductions, [5] pair pass from kept lists.  sph_profile_read
+ * synchronises and writes
  * out[2k] = total milliseconds and out[2k+1] = launch count of group k, then
  * clears the totals. */
 sph_status sph_profile(sph_ctx *ctx, int32_t enable);

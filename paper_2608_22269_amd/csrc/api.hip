@@ -804,24 +804,22 @@ sph_status stage_rhs(sph_ctx *c, int stage) {
   return st;
 }
 
-// The stage update of SSP-RK2.  The FP64 update also computes max |U| of the
-// new state (for the next right-hand side or step), checks it for
-// finiteness after the second stage, and writes the neighbour records when
+// The stage update of SSP-RK2.  It also computes max |U| of the new state
+// (for the next right-hand side or step), writes the neighbour records when
 // the next right-hand side may run from kept lists (it then needs no
-// refresh).
+// refresh), and on the FP64 path checks the state for finiteness after the
+// second stage.
 sph_status stage_update(sph_ctx *c, int stage) {
   ProfScope ps(c, 4);
   hipError_t e;
-  if (c->mixed) {
-    e = launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, stage, c->s);
-    c->umax_fresh = c->recs_fresh = false;
-  } else {
-    const bool recs = c->kent && c->lists_valid && (stage == 1 || (c->p.flags & SPH_F_KEEP_ACROSS_STEPS));
+  const bool recs = c->kent && c->lists_valid && (stage == 1 || (c->p.flags & SPH_F_KEEP_ACROSS_STEPS));
+  if (c->mixed)
+    e = launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, stage, c->s, recs ? &c->mrec : nullptr);
+  else
     e = launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, stage, c->s, recs ? c->rec0 : nullptr,
                          recs ? c->rec1 : nullptr, stage == 2 ? 1 : 0);
-    c->umax_fresh = true;
-    c->recs_fresh = recs;
-  }
+  c->umax_fresh = true;
+  c->recs_fresh = recs;
   if (e == hipSuccess && c->kent) e = launch_disp_add(c->sc, stage, c->s);
   if (e == hipSuccess && stage == 2) e = launch_advance_time(c->sc, c->s);
   return hip_check(c, e, stage == 1 ? "stage 1" : "stage 2");

@@ -114,7 +114,7 @@ struct Phys {
   double skin_max;        // skin of kept lists: the cells' room reach R - 2h (0: none)
   double skin_pad;        // part of the skin reserved for the rounding of positions
   double win;             // window radius of the mirror and scan cell searches:
-                          // 2h, wider over the first stage's cells (second stage)
+                          // 2h, wider over the cells of a kept-list build
 };
 
 // Device-resident scalars (one instance in the workspace).

@@ -33,6 +33,11 @@ __global__ void __launch_bounds__(256) k_umax(const T *__restrict__ u0, const T 
 
 __global__ void k_reset_umax(Scalars *sc) { sc->umax2_bits = 0ull; }
 
+hipError_t launch_reset_umax(Scalars *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_umax, dim3(1), dim3(1), 0, s, sc);
+  return hipGetLastError();
+}
+
 hipError_t launch_umax(int dim, const double *const u[3], const float *const uf[3], int64_t nf, Scalars *sc,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_reset_umax, dim3(1), dim3(1), 0, s, sc);

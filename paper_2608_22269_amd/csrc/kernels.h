@@ -33,7 +33,7 @@ hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int
 // pair pass modes: own search; own search keeping its candidate lists for the
 // step's second stage (kept lists kent, sized for kKeepChunks list fills of
 // kPairList entries per lane of the launch, and kcnt, one word of packed
-// chunk counts per lane); second stage from the kept lists
+// chunk counts per lane); a right-hand side from the kept lists
 constexpr int kPairSearch = 0, kPairSearchKeep = 1, kPairKept = 2;
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
@@ -63,6 +63,8 @@ hipError_t launch_dt(const Phys &P, Scalars *sc, double dt_override, hipStream_t
 hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s, int mode = 0);
 // adds the bound on a particle's move by the stage update just made to sc->disp
 hipError_t launch_disp_add(Scalars *sc, int stage, hipStream_t s);
+// clears sc->umax2_bits (before a kernel that folds max |U|^2 into it)
+hipError_t launch_reset_umax(Scalars *sc, hipStream_t s);
 // SSP-RK2 stage update (FP64); also max |U|^2 of the new state into
 // sc->umax2_bits (reset here), a finiteness check of phi and U (check != 0)
 // and the neighbour records of the new state (rec0 != nullptr)

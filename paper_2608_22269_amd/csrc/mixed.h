@@ -34,8 +34,11 @@ hipError_t launch_refresh_mixed(const Phys &P, const Grid &g, const FluidMixed &
 hipError_t launch_scan_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                              const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
                              const Rates &out, Scalars *sc, hipStream_t s);
+// SSP-RK2 stage update of the mixed state; also max |U|^2 of the new state
+// into sc->umax2_bits (reset here) and, when rec is given, the neighbour
+// records of the new state
 hipError_t launch_stage_mixed(const Phys &P, const Grid &g, const FluidMixed &f, const Rates &r, int64_t nf,
-                              const Scalars *sc, int stage, hipStream_t s);
+                              Scalars *sc, int stage, hipStream_t s, const MixedRec *rec = nullptr);
 // state fields of the fluid rows (x, u, phi, rho, p, mass, cell) in original order
 hipError_t launch_fields_mixed(const Phys &P, const Grid &g, const FluidMixed &f, int64_t nf, int field, void *dst,
                                hipStream_t s, uint32_t nout);

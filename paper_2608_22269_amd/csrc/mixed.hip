@@ -675,59 +675,92 @@ hipError_t launch_scan_mixed(const Phys &P, const Grid &g, const MixedRec &rec, 
 // ------------------------------------------------------------ integration
 
 template <int DIM>
-__global__ void __launch_bounds__(256) k_stage_mixed(Grid g, FluidMixed f, Rates r, int64_t n,
-                                                     const Scalars *__restrict__ sc, int stage) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double dt = sc->dt;
-  uint32_t c = f.cell[i];
-  int cc[3] = {cell_x(c), cell_y(c), cell_z(c)};
-  for (int a = 0; a < DIM; ++a) {
-    float o = f.o[a][i], oc = f.oc[a][i], u = f.u[a][i], uc = f.uc[a][i];
-    // position first (uses the stage's velocity), then velocity
-    const double vx = ((double)u - (double)uc + r.dus[a][i]) * dt;
-    const double va = r.acc[a][i] * dt;
+__global__ void __launch_bounds__(256) k_stage_mixed(Phys P, Grid g, FluidMixed f, Rates r, int64_t n,
+                                                     Scalars *sc, int stage, MixedRec rec, int write_rec) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double u2 = 0.0;
+  if (i < n) {
+    const double dt = sc->dt;
+    uint32_t c = f.cell[i];
+    int cc[3] = {cell_x(c), cell_y(c), cell_z(c)};
+    float of[3] = {0.f, 0.f, 0.f}, uf[3] = {0.f, 0.f, 0.f};
+    for (int a = 0; a < DIM; ++a) {
+      float o = f.o[a][i], oc = f.oc[a][i], u = f.u[a][i], uc = f.uc[a][i];
+      // position first (uses the stage's velocity), then velocity
+      const double vx = ((double)u - (double)uc + r.dus[a][i]) * dt;
+      const double va = r.acc[a][i] * dt;
+      if (stage == 1) {
+        kahan_add(o, oc, vx);
+        kahan_add(u, uc, va);
+        f.dx1[a][i] = (float)vx;
+        f.du1[a][i] = (float)va;
+      } else {
+        kahan_add(o, oc, 0.5 * (vx - (double)f.dx1[a][i]));
+        kahan_add(u, uc, 0.5 * (va - (double)f.du1[a][i]));
+      }
+      // keep the offset inside its cell: move whole cells, subtract k R exactly
+      const double ov = (double)o - (double)oc;
+      const int kc = (int)floor(ov / g.R);
+      if (kc != 0) {
+        cc[a] += kc;
+        kahan_add(o, oc, -(double)kc * g.R);
+      }
+      f.o[a][i] = o;
+      f.oc[a][i] = oc;
+      f.u[a][i] = u;
+      f.uc[a][i] = uc;
+      of[a] = o;
+      uf[a] = u;
+      u2 += (double)u * (double)u;
+    }
+    // cells outside the grid are caught by the next hash (domain error); keep
+    // the packed fields from wrapping meanwhile
+    for (int a = 0; a < 3; ++a) cc[a] = min(max(cc[a], 0), a == 2 ? 1023 : 2047);
+    c = pack_cell(cc[0], cc[1], cc[2]);
+    f.cell[i] = c;
+    const double dp = r.dphi[i] * dt;
+    double ph = f.phi[i];
     if (stage == 1) {
-      kahan_add(o, oc, vx);
-      kahan_add(u, uc, va);
-      f.dx1[a][i] = (float)vx;
-      f.du1[a][i] = (float)va;
+      ph += dp;
+      f.dphi1[i] = dp;
     } else {
-      kahan_add(o, oc, 0.5 * (vx - (double)f.dx1[a][i]));
-      kahan_add(u, uc, 0.5 * (va - (double)f.du1[a][i]));
+      ph += 0.5 * (dp - f.dphi1[i]);
     }
-    // keep the offset inside its cell: move whole cells, subtract k R exactly
-    const double ov = (double)o - (double)oc;
-    const int kc = (int)floor(ov / g.R);
-    if (kc != 0) {
-      cc[a] += kc;
-      kahan_add(o, oc, -(double)kc * g.R);
+    f.phi[i] = ph;
+    if (write_rec) {  // the records of the new state, as the reorder writes them
+      const float V = (float)((double)f.m[i] / (P.rho0 * exp(ph * P.inv_c02)));
+      float xa[3] = {0.f, 0.f, 0.f};
+      for (int a = 0; a < DIM; ++a) xa[a] = (float)pos_of(g.lo[a], g.R, cc[a], of[a]);
+      rec.r0[i] = make_float4(of[0], of[1], of[2], __uint_as_float(c));
+      rec.r1[i] = make_float4(uf[0], uf[1], uf[2], V);
+      rec.phi[i] = ph;
+      rec.xa[i] = make_float4(xa[0], xa[1], xa[2], 0.f);
     }
-    f.o[a][i] = o;
-    f.oc[a][i] = oc;
-    f.u[a][i] = u;
-    f.uc[a][i] = uc;
   }
-  // cells outside the grid are caught by the next hash (domain error); keep
-  // the packed fields from wrapping meanwhile
-  for (int a = 0; a < 3; ++a) cc[a] = min(max(cc[a], 0), a == 2 ? 1023 : 2047);
-  f.cell[i] = pack_cell(cc[0], cc[1], cc[2]);
-  const double dp = r.dphi[i] * dt;
-  if (stage == 1) {
-    f.phi[i] += dp;
-    f.dphi1[i] = dp;
-  } else {
-    f.phi[i] += 0.5 * (dp - f.dphi1[i]);
+  // max |U|^2 of the new state (the FP32 velocities, as the max-|U| kernel reads them)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) u2 = fmax(u2, __shfl_xor(u2, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = u2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = sh[0];
+    for (int w = 1; w < kBlock / 64; ++w) b = fmax(b, sh[w]);
+    atomicMax(&sc->umax2_bits, (unsigned long long)__double_as_longlong(b));
   }
 }
 
 hipError_t launch_stage_mixed(const Phys &P, const Grid &g, const FluidMixed &f, const Rates &r, int64_t nf,
-                              const Scalars *sc, int stage, hipStream_t s) {
-  if (nf <= 0) return hipSuccess;
+                              Scalars *sc, int stage, hipStream_t s, const MixedRec *rec) {
+  hipError_t e = launch_reset_umax(sc, s);
+  if (e != hipSuccess || nf <= 0) return e;
+  const MixedRec rr = rec ? *rec : MixedRec{nullptr, nullptr, nullptr, nullptr};
   if (P.dim == 2)
-    hipLaunchKernelGGL(k_stage_mixed<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, g, f, r, nf, sc, stage);
+    hipLaunchKernelGGL(k_stage_mixed<2>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, f, r, nf, sc, stage, rr,
+                       rec ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_stage_mixed<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, g, f, r, nf, sc, stage);
+    hipLaunchKernelGGL(k_stage_mixed<3>, dim3(grid_for(nf)), dim3(kBlock), 0, s, P, g, f, r, nf, sc, stage, rr,
+                       rec ? 1 : 0);
   return hipGetLastError();
 }
 
