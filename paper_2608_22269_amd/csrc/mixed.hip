@@ -422,6 +422,8 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
   }
   const MixedI I = mixed_i(P, g, a0, a1, phii);
   const float two_h2 = (float)P.two_h2;
+  // the kept-list work behind a run-time test (launches in this mode always
+  // have a skin): compiled unconditionally it costs spilled registers
   const bool keep = KEEP && P.skin_max > 0.0;
   const double rho = keep ? P.two_h + P.skin_max : P.two_h;
   const float rho2 = keep ? (float)(rho * rho) : two_h2;

@@ -200,6 +200,8 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
   }
   PairSums S;
   sums_zero(S);
+  // the kept-list work behind a run-time test (launches in this mode always
+  // have a skin): compiled unconditionally it costs spilled registers
   const bool keep = KEEP && P.skin_max > 0.0;
   const double rho = keep ? P.two_h + P.skin_max : P.two_h;
   const double rho2 = keep ? rho * rho : P.two_h2;
