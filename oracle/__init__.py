@@ -51,6 +51,8 @@ class Params(C.Structure):
         ("lambda_singular", C.c_double),
         ("gravity", C.c_double * 3), ("forcing_amp", C.c_double * 3), ("forcing_omega", C.c_double),
         ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3), ("cell_size", C.c_double),
+        ("body_pieces", C.c_int32), ("pad2_", C.c_int32),
+        ("body_t", C.c_double * 5), ("body_a", C.c_double * 12), ("body_b", C.c_double * 12),
     ]
 
 
@@ -86,6 +88,8 @@ def lib():
         L.orc_dt.argtypes = [P, C.c_int64, vp, vp]
         L.orc_step.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_double),
                                C.c_int32, C.c_double, C.c_int, C.POINTER(C.c_double)]
+        L.orc_body_motion.argtypes = [P, C.c_double, vp, vp]
+        L.orc_body_motion.restype = None
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_set_num_threads.restype = None
@@ -121,6 +125,17 @@ def make_params(pd: dict) -> Params:
     for k in ("gravity", "forcing_amp", "domain_lo", "domain_hi"):
         v = list(pd.get(k, [0.0, 0.0, 0.0])) + [0.0] * 3
         setattr(p, k, (C.c_double * 3)(*[float(a) for a in v[:3]]))
+    bt = list(pd.get("body_t", []))
+    if bt:
+        k = len(bt) - 1
+        if not 1 <= k <= 4:
+            raise ValueError("body motion needs 1 to 4 pieces")
+        p.body_pieces = k
+        p.body_t = (C.c_double * 5)(*([float(v) for v in bt] + [0.0] * (5 - len(bt))))
+        for name in ("body_a", "body_b"):
+            rows = [list(r) + [0.0] * 3 for r in pd[name]]
+            flat = [float(r[c]) for r in rows[:k] for c in range(3)]
+            setattr(p, name, (C.c_double * 12)(*(flat + [0.0] * (12 - len(flat)))))
     return p
 
 
@@ -221,6 +236,16 @@ def eval_rates(case, t=None, mode="cells", rows=None):
     return out
 
 
+def body_motion(pd, t):
+    """Displacement since T_0 and velocity at t of the prescribed body
+    motion (both (3,) arrays)."""
+    p = make_params(pd)
+    D = np.zeros(3)
+    U = np.zeros(3)
+    lib().orc_body_motion(C.byref(p), float(t), _ptr(D), _ptr(U))
+    return D, U
+
+
 def dt(case):
     dim, n, x, u, phi, m, kind, nd = _state(case)
     p = make_params(case["params"])
@@ -229,7 +254,8 @@ def dt(case):
 
 def step(case, nsteps=1, dt_override=0.0, mode="cells"):
     """SSP-RK2 steps from the case state; returns a new case dict holding the
-    advanced x, u, phi, t, the (fixed) particle masses and ``dt`` (last step)."""
+    advanced x, u, phi, t, the (fixed) particle masses and ``dt`` (last step).
+    Rows of the moving body keep their positions of time T_0."""
     dim, n, x, u, phi, m, kind, nd = _state(case)
     x, u, phi = x.copy(), u.copy(), phi.copy()
     p = make_params(case["params"])

@@ -17,6 +17,8 @@
  *   final system    Sec. 2.3, Eq. (sph)
  *   integrator      Sec. 2.3, SSP-RK2 stages and the three-way time step rule
  *   walls           Sec. 2.4, Eq. (phiBn) and the slip mirror
+ *   moving walls    Sec. 4 (aircraft ditching): a body moving along a
+ *                   prescribed velocity history U(T) given piecewise
  *   neighbours      Sec. 3, Eqs. (hashid), (ixyz), Algorithm 1
  *   eigenvalues     Sec. 3 (minimum eigenvalue of L), by Jacobi rotations
  * Readings of passages that are silent or garbled are noted where they are
@@ -56,6 +58,11 @@ typedef struct {
     double lambda_tic, lambda_fs_lo, lambda_fs_hi, lambda_singular;
     double gravity[3], forcing_amp[3], forcing_omega;
     double domain_lo[3], domain_hi[3], cell_size;
+    /* prescribed body motion: U(t) = a_k + b_k t on piece k, T_k <= t <=
+     * T_{k+1} (k = 0..body_pieces-1, the lower piece at a shared breakpoint),
+     * zero outside [T_0, T_K]; body_a / body_b hold 3 components per piece */
+    int32_t body_pieces, pad2_;
+    double body_t[5], body_a[12], body_b[12];
 } orc_params;
 
 /* Outputs of one right-hand-side evaluation, one row per particle in the
@@ -109,6 +116,30 @@ static void body_force(const orc_params *p, double t, double G[3]) {
     double s = sin(p->forcing_omega * t);
     for (int a = 0; a < 3; ++a)
         G[a] = p->gravity[a] + p->forcing_amp[a] * p->forcing_omega * p->forcing_omega * s;
+}
+
+/* Prescribed motion of the body (kind 2 dummies).  The ditching case of
+ * Sec. 4 gives the body's velocity as a piecewise function of time; here a
+ * piece is affine in t.  U is the velocity at t; D the displacement since
+ * T_0, the integral of U from T_0 to t, piece by piece:
+ *   int_{T_k}^{tau} (a + b s) ds = a (tau - T_k) + b (tau^2 - T_k^2) / 2.
+ * Reading: the body is given at its position of time T_0 (D = 0), and it
+ * only translates. */
+void orc_body_motion(const orc_params *p, double t, double D[3], double U[3]) {
+    for (int a = 0; a < 3; ++a) D[a] = U[a] = 0.0;
+    int found = 0;
+    for (int k = 0; k < p->body_pieces; ++k) {
+        double t0 = p->body_t[k], t1 = p->body_t[k + 1];
+        if (!found && t >= t0 && t <= t1) {
+            for (int a = 0; a < 3; ++a) U[a] = p->body_a[3 * k + a] + p->body_b[3 * k + a] * t;
+            found = 1;
+        }
+        if (t > t0) {
+            double tau = t < t1 ? t : t1;
+            for (int a = 0; a < 3; ++a)
+                D[a] += p->body_a[3 * k + a] * (tau - t0) + p->body_b[3 * k + a] * (tau * tau - t0 * t0) / 2.0;
+        }
+    }
 }
 
 static double body_force_max(const orc_params *p) {
@@ -509,15 +540,20 @@ static double volume_of(const orc_params *p, double m, double phi) {
 
 /* Mirror for the dummy wall particles (Sec. 2.4): nearest fluid particle f
  * within 2h (ties -> lower index); phi_d = phi_f + G.(x_d - x_f) (Eq. phiBn);
- * slip velocity U_d = U_f - (U_f.n_d) n_d.  No fluid within 2h -> inactive. */
+ * slip velocity U_d = U_f - (U_f.n_d) n_d.  No fluid within 2h -> inactive.
+ * Reading for a moving body (kind 2, wall velocity Uw): the slip condition
+ * holds relative to the wall, U_d = U_f - ((U_f - Uw).n_d) n_d, so that the
+ * dummy carries the wall's normal velocity and the fluid's tangential one
+ * (Sec. 2.4 gives the no-slip form 2 Uw - U_f with the wall velocity, and
+ * the slip form for fixed walls); Eq. (phiBn) is kept as printed. */
 static void mirror_dummies(const orc_params *p, int64_t n, const double *x, const double *u,
                            const double *phi, const uint8_t *kind, const double *nd, const double *G,
-                           const int64_t *off, const int32_t *ids, double *mphi, double *mu,
-                           int32_t *msrc) {
+                           const double *Uw, const int64_t *off, const int32_t *ids, double *mphi,
+                           double *mu, int32_t *msrc) {
     int dim = p->dim;
 #pragma omp parallel for schedule(static)
     for (int64_t d = 0; d < n; ++d) {
-        if (kind[d] != 1) continue;
+        if (kind[d] == 0) continue;
         int64_t best = -1;
         double bestr2 = 0.0;
         for (int64_t k = off[d]; k < off[d + 1]; ++k) {
@@ -539,7 +575,10 @@ static void mirror_dummies(const orc_params *p, int64_t n, const double *x, cons
         for (int a = 0; a < dim; ++a) gp += G[a] * (x[d * dim + a] - x[best * dim + a]);
         mphi[d] = phi[best] + gp;
         double un = 0.0;
-        for (int a = 0; a < dim; ++a) un += u[best * dim + a] * nd[d * dim + a];
+        for (int a = 0; a < dim; ++a) {
+            double rel = u[best * dim + a] - (kind[d] == 2 ? Uw[a] : 0.0);
+            un += rel * nd[d * dim + a];
+        }
         for (int a = 0; a < dim; ++a) mu[d * dim + a] = u[best * dim + a] - un * nd[d * dim + a];
     }
 }
@@ -595,13 +634,22 @@ static int scan_region(const orc_params *p, int64_t i, const double *x, const do
 /* One evaluation of the semi-discrete system, Eq. (sph), at time t.  With
  * only != NULL the rates are computed for the fluid particles with only[i]
  * != 0 alone (the others are left zero), from neighbour lists of those
- * particles and of the dummies among their neighbours (cells mode). */
-int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double *u,
+ * particles and of the dummies among their neighbours (cells mode).  Rows of
+ * kind 2 (the moving body) hold the body at T_0; they take part at their
+ * position of time t, x + D(t). */
+int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const double *u,
                    const double *phi, const double *mass, const uint8_t *kind, const double *nd,
                    double t, int nbr_mode, const uint8_t *only, orc_rates *out) {
     int dim = p->dim;
     if (dim != 2 && dim != 3) return ORC_EINVAL;
     if (only && nbr_mode == 0) return ORC_EINVAL;
+    double Db[3], Uw[3];
+    orc_body_motion(p, t, Db, Uw);
+    double *xw = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * dim);
+    if (!xw) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < dim; ++a) xw[i * dim + a] = x_in[i * dim + a] + (kind[i] == 2 ? Db[a] : 0.0);
+    const double *x = xw;
     int64_t *off = NULL;
     int32_t *ids = NULL;
     int st;
@@ -611,14 +659,17 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
         /* rows: the sampled fluid particles, then also the dummies in their
          * neighbour lists (the wall mirror needs their lists) */
         uint8_t *rows = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
-        if (!rows) return ORC_ENOMEM;
+        if (!rows) {
+            free(xw);
+            return ORC_ENOMEM;
+        }
         for (int64_t i = 0; i < n; ++i) rows[i] = (uint8_t)(only[i] && kind[i] == 0);
         st = build_csr_rows(p, n, x, rows, &off, &ids);
         if (st == ORC_OK) {
             for (int64_t i = 0; i < n; ++i) {
                 if (!(only[i] && kind[i] == 0)) continue;
                 for (int64_t k = off[i]; k < off[i + 1]; ++k)
-                    if (kind[ids[k]] == 1) rows[ids[k]] = 1;
+                    if (kind[ids[k]] != 0) rows[ids[k]] = 1;
             }
             free(off);
             free(ids);
@@ -628,7 +679,10 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
         }
         free(rows);
     }
-    if (st != ORC_OK) return st;
+    if (st != ORC_OK) {
+        free(xw);
+        return st;
+    }
 
     double G[3];
     body_force(p, t, G);
@@ -640,15 +694,15 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
     double *V = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     int32_t *src = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     if (!phiv || !uv || !V || !src) {
-        free(off); free(ids); free(phiv); free(uv); free(V); free(src);
+        free(off); free(ids); free(phiv); free(uv); free(V); free(src); free(xw);
         return ORC_ENOMEM;
     }
     for (int64_t i = 0; i < n; ++i) src[i] = -1;
     memcpy(phiv, phi, sizeof(double) * (size_t)n);
     memcpy(uv, u, sizeof(double) * (size_t)n * dim);
-    mirror_dummies(p, n, x, u, phi, kind, nd, G, off, ids, phiv, uv, src);
+    mirror_dummies(p, n, x, u, phi, kind, nd, G, Uw, off, ids, phiv, uv, src);
     for (int64_t i = 0; i < n; ++i) {
-        if (kind[i] == 1 && src[i] < 0) V[i] = 0.0;
+        if (kind[i] != 0 && src[i] < 0) V[i] = 0.0;
         else V[i] = volume_of(p, mass[i], phiv[i]);
     }
 
@@ -731,7 +785,7 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
             /* classifier inputs: kernel sum, closest neighbour, dummies */
             S0 += Wq * Vj;
             if (q < qmin) qmin = q;
-            if (kind[j] == 1) nd_count++;
+            if (kind[j] != 0) nd_count++;
         }
 
         /* eigenvalues of the (symmetric) correction matrix */
@@ -866,7 +920,7 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x, const double
         out->scal[2] = t;
         out->scal[3] = nsing;
     }
-    free(off); free(ids); free(phiv); free(uv); free(V); free(src);
+    free(off); free(ids); free(phiv); free(uv); free(V); free(src); free(xw);
     return ORC_OK;
 }
 
@@ -926,9 +980,10 @@ static void free_rates(orc_rates *r) {
     memset(r, 0, sizeof(*r));
 }
 
-/* SSP-RK2 (Sec. 2.3), dummies fixed.  dt from U at t^n (dt_override > 0
- * replaces the rule).  Stage 1 at t^n, stage 2 at t^n + dt.  On return x, u,
- * phi hold t^{n+nsteps} (dummy rows untouched); *t advanced; *dt_last set. */
+/* SSP-RK2 (Sec. 2.3).  dt from U at t^n (dt_override > 0 replaces the
+ * rule).  Stage 1 at t^n, stage 2 at t^n + dt (the body, kind 2, at its
+ * positions of those times).  On return x, u, phi hold t^{n+nsteps} (dummy
+ * rows untouched); *t advanced; *dt_last set. */
 int orc_step(const orc_params *p, int64_t n, double *x, double *u, double *phi, const double *mass,
              const uint8_t *kind, const double *nd, double *t, int32_t nsteps, double dt_override,
              int nbr_mode, double *dt_last) {

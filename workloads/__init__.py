@@ -9,7 +9,8 @@ Every case is a dict:
     params : dict of physical / numerical parameters (see ``base_params``)
     x, u   : (n, dim) float64      positions, velocities
     phi    : (n,) float64          auxiliary potential
-    kind   : (n,) uint8            0 fluid, 1 fixed wall dummy
+    kind   : (n,) uint8            0 fluid, 1 fixed wall dummy, 2 dummy of the
+                                   moving body (position at its reference time)
     normal : (n, dim) float64      unit wall normal (dummies; zero for fluid)
     mass   : None                  (each side derives m = rho(phi) dx^d)
     t      : float                 initial time
@@ -260,6 +261,85 @@ def with_params(case, **kw):
     p = dict(case["params"])
     p.update(kw)
     c["params"] = p
+    return c
+
+
+def ditching_motion():
+    """The body velocity history of the paper's aircraft-ditching case (Sec. 4):
+    U = -5 m/s for T <= 0.8 s, then 5/2 (T - 3) m/s up to T = 2.8 s, along x;
+    as pieces a_k + b_k T for the parameter keys body_t / body_a / body_b."""
+    return {"body_t": [0.0, 0.8, 2.8],
+            "body_a": [[-5.0, 0.0, 0.0], [-7.5, 0.0, 0.0]],
+            "body_b": [[0.0, 0.0, 0.0], [2.5, 0.0, 0.0]]}
+
+
+def _body_box(dim, lo, hi, dx, layers):
+    """Dummy lattice points of a solid box [lo, hi] (corners on multiples of
+    dx): the points within `layers` spacings of its surface, each with the
+    outward normal of its nearest face(s) (corners: the normalised sum)."""
+    lo = np.asarray(lo[:dim], dtype=np.float64)
+    hi = np.asarray(hi[:dim], dtype=np.float64)
+    n = [int(round((b - a) / dx)) for a, b in zip(lo, hi)]
+    pts = _lattice([0] * dim, n, dx) + lo
+    dlo, dhi = pts - lo, hi - pts
+    dmin = np.minimum(dlo, dhi)
+    m = dmin.min(axis=1)
+    keep = m < layers * dx
+    pts, dlo, dhi, dmin, m = pts[keep], dlo[keep], dhi[keep], dmin[keep], m[keep]
+    nrm = np.zeros_like(pts)
+    near = dmin <= m[:, None] + 1e-9 * dx
+    nrm[near & (dlo < dhi)] = -1.0
+    nrm[near & (dhi < dlo)] = 1.0
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return pts, nrm
+
+
+def with_body(case, lo, hi, motion, layers=3):
+    """Copy of `case` with a solid box body [lo, hi] of kind-2 dummies moving
+    with the prescribed velocity history `motion` (keys body_t, body_a,
+    body_b, pieces a_k + b_k t); fluid particles inside the box are removed.
+    The box is given at its position of time body_t[0]."""
+    pd = dict(case["params"])
+    dim = pd["dim"]
+    dx = pd["dx"]
+    xb, nb = _body_box(dim, lo, hi, dx, layers)
+    x = case["x"]
+    lo_a = np.asarray(lo[:dim]) - 0.25 * dx
+    hi_a = np.asarray(hi[:dim]) + 0.25 * dx
+    inside = (case["kind"] == 0) & np.all((x > lo_a) & (x < hi_a), axis=1)
+    keep = ~inside
+    G = np.asarray(pd["gravity"][:dim], dtype=np.float64)
+    gmag = float(np.linalg.norm(pd["gravity"]))
+    H = case["meta"]["H"]
+    c = dict(case)
+    c["x"] = np.concatenate([x[keep], xb])
+    c["u"] = np.concatenate([case["u"][keep], np.zeros_like(xb)])
+    c["phi"] = np.concatenate([case["phi"][keep], xb @ G + H * gmag])
+    c["kind"] = np.concatenate([case["kind"][keep], np.full(len(xb), 2, np.uint8)])
+    c["normal"] = np.concatenate([case["normal"][keep], nb])
+    pd.update({k: [list(map(float, r)) if isinstance(r, (list, tuple)) else float(r) for r in motion[k]]
+               for k in ("body_t", "body_a", "body_b")})
+    c["params"] = pd
+    meta = dict(case["meta"])
+    meta.update({"n_fluid": int(((c["kind"] == 0)).sum()), "n_dummy": int((c["kind"] != 0).sum()),
+                 "n_body": int(len(xb))})
+    c["meta"] = meta
+    return c
+
+
+def entry2d(dx=0.01, width=0.6, depth=0.3, body=(0.25, 0.35, 0.27, 0.33), speed=(-0.5, -1.0), **kw):
+    """2D tank with a rectangular body (x0, x1, y0, y1) cutting the free
+    surface, moving with `speed` for 0.1 s and then decelerating linearly to
+    rest at 0.3 s (a ditching-style history: a constant piece, then an affine
+    one)."""
+    case = tank2d(dx=dx, width=width, depth=depth, wall_height=depth + 0.2, **kw)
+    vx, vy = speed
+    motion = {"body_t": [0.0, 0.1, 0.3],
+              "body_a": [[vx, vy, 0.0], [1.5 * vx, 1.5 * vy, 0.0]],
+              "body_b": [[0.0, 0.0, 0.0], [-5.0 * vx, -5.0 * vy, 0.0]]}
+    c = with_body(case, (body[0], body[2]), (body[1], body[3]), motion)
+    c["meta"]["name"] = "entry2d"
+    c["meta"]["desc"] = f"2D tank {width}x{depth} m with a body {body} moving at {speed} m/s, dx={dx}"
     return c
 
 
