@@ -12,8 +12,8 @@ the lists' skin; --keep-cell 0 sorts and searches at both right-hand sides).
 
 Prints one JSON line (metric, value = pair evaluations per second of the
 headline path, ms/step, rooflines of the pair passes, CPU oracle baseline,
-the mixed and learned paths, the lists kept across steps, MLP inference,
-spurious velocities).
+the mixed and learned paths, the lists kept across steps, a body moving
+along the ditching velocity history, MLP inference, spurious velocities).
 """
 from __future__ import annotations
 
@@ -323,6 +323,26 @@ def bump_history(steps, every):
     return out
 
 
+def moving_body(dx, steps, warmup):
+    """3D tank with a box body cutting the free surface and moving along the
+    paper's ditching velocity history (5 m/s along x): FP64 and mixed, and
+    FP64 with the same body at rest (the difference is the cost of moving
+    and re-sorting the dummies at every right-hand side)."""
+    import workloads as wl
+    case = wl.ditch3d(dx=dx)
+    h = case["params"]["h"]
+    case = wl.with_params(case, cell_size=h)
+    at_rest = dict(case)
+    at_rest["params"] = {k: v for k, v in case["params"].items() if not k.startswith("body_")}
+    res = {"workload": case["meta"]["desc"], "n_fluid": case["meta"]["n_fluid"],
+           "n_dummy": case["meta"]["n_dummy"], "n_body": case["meta"]["n_body"], "cell_size_over_h": 1.0}
+    res["fp64"] = run_path(case, "ditch3d moving body (fp64)", steps, warmup)
+    res["fp64_body_at_rest"] = run_path(at_rest, "ditch3d body at rest (fp64)", steps, warmup)
+    res["mixed"] = run_path(wl.with_params(case, precision="mixed"), "ditch3d moving body (mixed)", steps, warmup)
+    res["motion_cost_ms_per_step"] = res["fp64"]["ms_per_step"] - res["fp64_body_at_rest"]["ms_per_step"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +368,8 @@ def main():
                     help="steps of the 3D dam break before the exact / learned detection comparison (0: skip)")
     ap.add_argument("--bump-steps", type=int, default=10000,
                     help="steps of the 2D Gaussian-bump spurious-velocity history (0: skip)")
+    ap.add_argument("--body-dx", type=float, default=0.005,
+                    help="particle spacing of the 3D moving-body run (3.82M fluid at 0.005; 0: skip)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -460,6 +482,8 @@ def main():
             "moving_within_step": run_path(wl.with_params(moving, keep_across_steps=False),
                                            "fp64 within steps (moving)", args.steps, args.warmup),
         }
+    if args.body_dx > 0:
+        out["moving_body"] = moving_body(args.body_dx, args.steps, args.warmup)
     out["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:
         out["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)

@@ -108,6 +108,22 @@ typedef struct sph_params {
     double domain_lo[3], domain_hi[3]; /* hashed box; particles must stay inside */
     double cell_size;       /* background cell R (0 -> 2h); >= 2h/3: the search
                                spans ceil(2h/R) cells on each side                */
+    /* Prescribed motion of a body made of wall dummies of kind 2 (the
+     * aircraft-ditching case of Sec. 4 prescribes the body's velocity as a
+     * piecewise function of time).  Velocity U(t) = body_a[k] + body_b[k] t
+     * on piece k, body_t[k] <= t <= body_t[k+1] (the lower piece at a shared
+     * breakpoint), zero before body_t[0] and after body_t[body_pieces].  The
+     * body translates rigidly: a kind-2 dummy given at x sits at x + D(t),
+     * D(t) the integral of U from body_t[0] to t, at every right-hand side;
+     * its mirrored velocity keeps the wall's normal velocity, U_d = U_f -
+     * ((U_f - U(t)).n_d) n_d.  body_pieces = 0: no motion (kind-2 dummies act
+     * as fixed walls).  With a moving body the dummies are re-sorted at every
+     * right-hand side and SPH_F_KEEP_LISTS has no effect.                    */
+    int32_t body_pieces;    /* 0..4                                               */
+    int32_t body_pad_;
+    double body_t[5];       /* breakpoints, strictly increasing                   */
+    double body_a[4][3];
+    double body_b[4][3];
 } sph_params;
 
 typedef struct sph_ctx sph_ctx;
@@ -128,8 +144,9 @@ const char *sph_status_string(sph_status s);
 /* Creates a context holding n particles in the caller's ("original") order.
  * x, u: n*dim doubles; phi: n doubles; mass: n doubles or NULL, in which case
  * m = rho0 exp(phi/C0^2) dx^dim (Sec. 2.2.1); kind: n bytes, 0 fluid, 1 fixed
- * dummy wall particle (Sec. 2.4); normal: n*dim doubles, the unit wall normal
- * of each dummy (fluid rows ignored).  inputs_on_device selects whether the
+ * dummy wall particle (Sec. 2.4), 2 dummy of the moving body (its position
+ * of time body_t[0]); normal: n*dim doubles, the unit wall normal of each
+ * dummy (fluid rows ignored).  inputs_on_device selects whether the
  * six arrays are device (1) or host (0) pointers; they are copied and may be
  * released after the call.  workspace: a device buffer of ws_bytes >=
  * sph_workspace_bytes(), 256-byte aligned.  hip_stream: the stream all work
@@ -178,7 +195,8 @@ sph_status sph_sync(sph_ctx *ctx);
 
 /* field selectors for sph_fields: all per-particle fields are returned for the
  * n particles in ORIGINAL order.  Rows of dummies hold their mirrored phi / U
- * and zero rates. */
+ * and zero rates; rows of the moving body hold its positions of the last
+ * right-hand side (of sph_init before any). */
 #define SPH_FIELD_X 0          /* n*dim double                                   */
 #define SPH_FIELD_U 1          /* n*dim double                                   */
 #define SPH_FIELD_PHI 2        /* n double                                       */

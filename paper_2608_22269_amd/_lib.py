@@ -46,6 +46,8 @@ class SphParams(C.Structure):
         ("lambda_singular", C.c_double),
         ("gravity", C.c_double * 3), ("forcing_amp", C.c_double * 3), ("forcing_omega", C.c_double),
         ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3), ("cell_size", C.c_double),
+        ("body_pieces", C.c_int32), ("body_pad_", C.c_int32), ("body_t", C.c_double * 5),
+        ("body_a", (C.c_double * 3) * 4), ("body_b", (C.c_double * 3) * 4),
     ]
 
 
@@ -135,6 +137,16 @@ def params_from_dict(pd: dict) -> SphParams:
     for k in ("gravity", "forcing_amp", "domain_lo", "domain_hi"):
         v = list(pd.get(k, [0.0, 0.0, 0.0])) + [0.0] * 3
         setattr(p, k, (C.c_double * 3)(*[float(a) for a in v[:3]]))
+    bt = list(pd.get("body_t", []))
+    if bt:
+        p.body_pieces = len(bt) - 1
+        for k, v in enumerate(bt[:5]):
+            p.body_t[k] = float(v)
+        for name in ("body_a", "body_b"):
+            arr = getattr(p, name)
+            for k, row in enumerate(list(pd[name])[:4]):
+                for c, v in enumerate(list(row)[:3]):
+                    arr[k][c] = float(v)
     return p
 
 

@@ -59,6 +59,9 @@ struct sph_ctx {
   uint32_t *perm;
   SortScratch ss;
   Dummies dm;
+  Dummies dm2;  // moving body: the dummies' second buffer for their re-sort
+  bool has_body;
+  Body body;
   Rates r;
   uint32_t *cand, *fallback;
   float *cand_logit;
@@ -144,6 +147,13 @@ bool params_ok(const sph_params *p, std::string *why) {
   if (p->flags & ~255u) return bad("unknown flag bits");
   if ((p->flags & SPH_F_KEEP_ACROSS_STEPS) && !(p->flags & SPH_F_KEEP_LISTS))
     return bad("SPH_F_KEEP_ACROSS_STEPS needs SPH_F_KEEP_LISTS");
+  if (p->body_pieces < 0 || p->body_pieces > 4) return bad("body_pieces must be 0..4");
+  for (int k = 0; k < p->body_pieces; ++k) {
+    if (!std::isfinite(p->body_t[k]) || !std::isfinite(p->body_t[k + 1]) || !(p->body_t[k + 1] > p->body_t[k]))
+      return bad("body breakpoints must be finite and strictly increasing");
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->body_a[k][a]) || !std::isfinite(p->body_b[k][a])) return bad("non-finite body motion");
+  }
   return true;
 }
 
@@ -199,7 +209,8 @@ void derive(const sph_params *p, Phys &P, Grid &g) {
   // cells of reach R cover a ball of radius reach R around any point; the
   // kept lists need 2h + skin inside it (a small margin keeps the cut away
   // from the rounding of cell indices)
-  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u;
+  // (a moving body re-sorts the dummies at every right-hand side: no lists)
+  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u && p->body_pieces == 0;
   P.skin_max = keep ? std::max(0.0, (double)g.reach * g.R - P.two_h - 1e-6 * g.R) : 0.0;
   // absolute part of the skin: far above the rounding of FP64 positions; on
   // the mixed path, above twice the rounding of the FP32 absolute positions
@@ -290,14 +301,20 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   c->ss.slot = cv.take<uint32_t>(nmax);
   c->ss.count = cv.take<uint32_t>(c->g.nkey + 1);
   c->ss.scan_tmp = cv.take<uint32_t>((int64_t)scan_tmp_words(std::max<int64_t>(c->g.nkey, n + 1)) + 1);
-  for (int a = 0; a < 3; ++a) {
-    c->dm.x[a] = a < dim ? f64(nd) : nullptr;
-    c->dm.n[a] = a < dim ? f64(nd) : nullptr;
+  const bool body = c->p.body_pieces > 0;
+  for (Dummies *d : {&c->dm, &c->dm2}) {
+    const bool on = d == &c->dm || body;
+    for (int a = 0; a < 3; ++a) {
+      d->x[a] = on && a < dim ? f64(nd) : nullptr;
+      d->n[a] = on && a < dim ? f64(nd) : nullptr;
+      d->x0[a] = body && a < dim ? f64(nd) : nullptr;
+    }
+    d->m = on ? f64(nd) : nullptr;
+    d->phi_in = on ? f64(nd) : nullptr;
+    d->id = on ? cv.take<uint32_t>(nd) : nullptr;
+    d->src = on ? cv.take<int32_t>(nd) : nullptr;
+    d->mov = body ? cv.take<uint8_t>(nd) : nullptr;
   }
-  c->dm.m = f64(nd);
-  c->dm.phi_in = f64(nd);
-  c->dm.id = cv.take<uint32_t>(nd);
-  c->dm.src = cv.take<int32_t>(nd);
   for (int a = 0; a < 3; ++a) {
     c->r.acc[a] = a < dim ? f64(nf) : nullptr;
     c->r.dus[a] = a < dim ? f64(nf) : nullptr;
@@ -326,7 +343,7 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   c->clf.std = cv.take<float>(kNFeat);
   c->sc = cv.take<Scalars>(1);
   // staging: init copies of the inputs, dummy staging, field export, rank scans
-  int64_t per = 8 * (3 * dim + 2) + 1 + 8 * (2 * dim + 2) + 8;
+  int64_t per = 8 * (3 * dim + 2) + 1 + 8 * (2 * dim + 2) + 8 + (body ? 8 * dim + 1 : 0);
   c->stage_bytes = (size_t)n * (size_t)std::max<int64_t>(per + 16, 64 + 8) + ((size_t)16 << 20);
   c->stage = cv.take<unsigned char>((int64_t)c->stage_bytes);
   return cv.off + kAlign;
@@ -401,12 +418,31 @@ sph_status refresh(sph_ctx *c) {
   return hip_check(c, e, "record refresh");
 }
 
+// The moving body at the right-hand side's time: its dummies moved to x0 +
+// D(t_rhs), then all dummies re-sorted by (cell, original index) into the
+// second buffer (the cell-start table of the dummies is rebuilt).
+sph_status move_body(sph_ctx *c) {
+  if (c->nd == 0) return SPH_OK;
+  ProfScope ps(c, 2);
+  hipError_t e = launch_body_move(c->body, c->dm, c->nd, c->dim, c->sc, c->s);
+  if (e == hipSuccess)
+    e = launch_sort_keys(c->g, c->dim, c->dm.x[0], c->dm.x[1], c->dm.x[2], nullptr, c->nd, c->dm.id, c->ss, c->cs_d,
+                         c->perm, c->sc, c->s);
+  if (e == hipSuccess) e = launch_gather_dummies(c->perm, c->nd, c->dm, c->dm2, c->dim, c->s);
+  std::swap(c->dm, c->dm2);
+  return hip_check(c, e, "body motion");
+}
+
 // One right-hand side.  mode: the pair pass's kPairSearch / kPairSearchKeep /
 // kPairKept; win_extra widens the cell searches of the mirror and scan passes
 // (over the cells of the kept lists' build: the bound on any particle's move
 // since).
 sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra = 0.0) {
   hipError_t e = launch_stage_time(c->sc, stage, c->s, mode);
+  if (e == hipSuccess && c->has_body) {
+    sph_status sb = move_body(c);
+    if (sb != SPH_OK) return sb;
+  }
   const bool feat = (c->p.flags & SPH_F_FEATURES) || c->p.fs_mode == SPH_FS_LEARNED;
   Phys Pw = c->P;
   Pw.win = c->P.two_h + win_extra;
@@ -562,7 +598,7 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   if (!inputs_on_device) {
     // host-side validation before any launch
     for (int64_t i = 0; i < n; ++i) {
-      if (kind[i] > 1) return SPH_EINVAL;
+      if (kind[i] > 2) return SPH_EINVAL;
       (kind[i] == 0 ? nf : nd)++;
       for (int a = 0; a < dim; ++a) {
         double v = x[i * dim + a];
@@ -571,7 +607,7 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
       }
       if (!std::isfinite(phi[i])) return SPH_ENONFINITE;
       if (mass && !(mass[i] > 0.0)) return SPH_EINVAL;
-      if (kind[i] == 1) {
+      if (kind[i] != 0) {
         if (!normal) return SPH_EINVAL;
         double s = 0;
         for (int a = 0; a < dim; ++a) s += normal[i * dim + a] * normal[i * dim + a];
@@ -589,6 +625,15 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   c->mixed = p->precision == SPH_MIXED;
   c->status = SPH_OK;
   c->has_clf = false;
+  c->has_body = p->body_pieces > 0;
+  std::memset(&c->body, 0, sizeof(c->body));
+  c->body.pieces = p->body_pieces;
+  for (int k = 0; k <= p->body_pieces; ++k) c->body.T[k] = p->body_t[k];
+  for (int k = 0; k < p->body_pieces; ++k)
+    for (int a = 0; a < 3; ++a) {
+      c->body.a[k][a] = p->body_a[k][a];
+      c->body.b[k][a] = p->body_b[k][a];
+    }
   c->n_kept = c->n_rebuilt = 0.0;
   c->lists_valid = false;
   c->umax_fresh = c->recs_fresh = false;
@@ -664,6 +709,8 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   dst.phi_in = (double *)take(sizeof(double) * nd);
   dst.id = (uint32_t *)take(sizeof(uint32_t) * nd);
   dst.src = nullptr;
+  for (int a = 0; a < 3; ++a) dst.x0[a] = c->has_body && a < dim ? (double *)take(sizeof(double) * nd) : nullptr;
+  dst.mov = c->has_body ? (uint8_t *)take((size_t)nd) : nullptr;
   FluidF64 f0;
   std::memset(&f0, 0, sizeof(f0));
   if (!c->mixed) {
@@ -738,6 +785,10 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   if (rs == SPH_OK) {
     // mirrored wall values at t = 0, so that fields are defined before any step
     hipError_t e3 = launch_stage_time(c->sc, 1, s);
+    if (e3 == hipSuccess && c->has_body) {
+      rs = move_body(c);
+      if (rs != SPH_OK) e3 = hipErrorUnknown;
+    }
     if (e3 == hipSuccess) {
       if (!c->mixed)
         e3 = launch_mirror_f64(c->P, c->g, c->dm, nd, c->rec0, c->rec1, c->rec0 + nf, c->rec1 + nf, c->cs_f,

@@ -139,6 +139,7 @@ struct Scalars {
   // pairs and tests of the last right-hand side that searched (s) and of the
   // last one that ran from kept lists (k), before the current one
   unsigned long long pairs_s, tests_s, pairs_k, tests_k;
+  double body_x[3], body_u[3];  // moving body: displacement and velocity at t_rhs
 };
 
 // Fluid state, FP64 path, sorted by (cell, original index).

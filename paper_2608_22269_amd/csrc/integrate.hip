@@ -398,7 +398,7 @@ __global__ void k_kind_flags(const uint8_t *__restrict__ kind, int64_t n, uint32
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   isf[i] = kind[i] == 0 ? 1u : 0u;
-  isd[i] = kind[i] == 1 ? 1u : 0u;
+  isd[i] = kind[i] != 0 ? 1u : 0u;
 }
 
 hipError_t launch_kind_flags(const uint8_t *kind, int64_t n, uint32_t *isf, uint32_t *isd, hipStream_t s) {
@@ -437,6 +437,10 @@ __global__ void k_split(Phys P, int64_t n, const double *__restrict__ x, const d
     d.phi_in[k] = phi[i];
     d.m[k] = m;
     d.id[k] = (uint32_t)i;
+    if (d.mov) {
+      d.mov[k] = kind[i] == 2 ? 1 : 0;
+      for (int a = 0; a < dim; ++a) d.x0[a][k] = x[i * dim + a];
+    }
   }
 }
 
@@ -461,11 +465,58 @@ __global__ void k_gather_dummies(const uint32_t *__restrict__ perm, int64_t nd, 
   dst.phi_in[k] = src.phi_in[o];
   dst.id[k] = src.id[o];
   dst.src[k] = -1;
+  if (src.mov) {
+    dst.mov[k] = src.mov[o];
+    for (int a = 0; a < dim; ++a) dst.x0[a][k] = src.x0[a][o];
+  }
 }
 
 hipError_t launch_gather_dummies(const uint32_t *perm, int64_t nd, Dummies src, Dummies dst, int dim, hipStream_t s) {
   if (nd <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_dummies, dim3(grid_for(nd)), dim3(kBlock), 0, s, perm, nd, src, dst, dim);
+  return hipGetLastError();
+}
+
+// Displacement D(t) since T_0 and velocity U(t) of the prescribed body
+// motion (the ditching case of Sec. 4 gives U piecewise in time).  On piece
+// k the displacement grows by the integral of a + b s from T_k to
+// min(t, T_{k+1}): a (tau - T_k) + b (tau^2 - T_k^2) / 2.  Every product and
+// sum is rounded as written (no contraction), so that the body's positions do
+// not depend on the compiler's choice of fused operations.
+__device__ void body_motion(const Body &B, double t, double D[3], double U[3]) {
+#pragma clang fp contract(off)
+  for (int a = 0; a < 3; ++a) D[a] = U[a] = 0.0;
+  bool found = false;
+  for (int k = 0; k < B.pieces; ++k) {
+    const double t0 = B.T[k], t1 = B.T[k + 1];
+    if (!found && t >= t0 && t <= t1) {
+      for (int a = 0; a < 3; ++a) U[a] = B.a[k][a] + B.b[k][a] * t;
+      found = true;
+    }
+    if (t > t0) {
+      const double tau = t < t1 ? t : t1;
+      for (int a = 0; a < 3; ++a) D[a] += B.a[k][a] * (tau - t0) + B.b[k][a] * (tau * tau - t0 * t0) / 2.0;
+    }
+  }
+}
+
+__global__ void k_body_move(Body B, Dummies d, int64_t nd, int dim, Scalars *sc) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double D[3], U[3];
+  body_motion(B, sc->t_rhs, D, U);
+  if (k == 0) {
+    for (int a = 0; a < 3; ++a) {
+      sc->body_x[a] = D[a];
+      sc->body_u[a] = U[a];
+    }
+  }
+  if (k >= nd || !d.mov[k]) return;
+  for (int a = 0; a < dim; ++a) d.x[a][k] = d.x0[a][k] + D[a];
+}
+
+hipError_t launch_body_move(const Body &B, const Dummies &d, int64_t nd, int dim, Scalars *sc, hipStream_t s) {
+  if (!d.mov) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_body_move, dim3(grid_for(std::max<int64_t>(nd, 1))), dim3(kBlock), 0, s, B, d, nd, dim, sc);
   return hipGetLastError();
 }
 

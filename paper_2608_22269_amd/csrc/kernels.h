@@ -24,6 +24,18 @@ struct Dummies {
   double *x[3], *n[3], *m, *phi_in;
   uint32_t *id;
   int32_t *src;  // sorted fluid index of the mirror source, -1 if inactive
+  // with a moving body only (else null): positions at the body's reference
+  // time and 1 for the body's dummies (kind 2)
+  double *x0[3];
+  uint8_t *mov;
+};
+
+// Prescribed motion of the body (Sec. 4, aircraft ditching): velocity a_k +
+// b_k t on piece k (T_k <= t <= T_{k+1}), zero outside [T_0, T_K].
+struct Body {
+  int pieces;
+  double T[5];
+  double a[4][3], b[4][3];
 };
 
 // pair.hip
@@ -101,5 +113,8 @@ hipError_t launch_kind_flags(const uint8_t *kind, int64_t n, uint32_t *is_fluid,
                              hipStream_t s);
 hipError_t launch_gather_dummies(const uint32_t *perm, int64_t nd, Dummies src, Dummies dst, int dim,
                                  hipStream_t s);
+// Moves the body's dummies to their positions of time sc->t_rhs (x0 + D(t))
+// and stores D and the body velocity in sc->body_x / sc->body_u.
+hipError_t launch_body_move(const Body &B, const Dummies &d, int64_t nd, int dim, Scalars *sc, hipStream_t s);
 
 }  // namespace wb

@@ -251,7 +251,11 @@ __global__ void __launch_bounds__(256) k_mirror_mixed(Phys P, Grid g, Dummies d,
   for (int a = 0; a < DIM; ++a) gp += G[a] * (xs[a] - xfs[a]);
   const double phid = rec.phi[best] + gp;
   const float nx = (float)d.n[0][k], ny = (float)d.n[1][k], nz = DIM == 3 ? (float)d.n[2][k] : 0.f;
-  const float un = f1.x * nx + f1.y * ny + f1.z * nz;
+  // slip, relative to the body's velocity for the moving body's dummies
+  const bool mv = d.mov != nullptr && d.mov[k];
+  const float wx = mv ? (float)sc->body_u[0] : 0.f, wy = mv ? (float)sc->body_u[1] : 0.f,
+              wz = mv && DIM == 3 ? (float)sc->body_u[2] : 0.f;
+  const float un = (f1.x - wx) * nx + (f1.y - wy) * ny + (f1.z - wz) * nz;
   const float V = (float)(d.m[k] / (P.rho0 * exp(phid * P.inv_c02)));
   rec.r1[o] = make_float4(f1.x - un * nx, f1.y - un * ny, DIM == 3 ? f1.z - un * nz : 0.f, V);
   rec.phi[o] = phid;

@@ -98,9 +98,17 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
   double gp = G[0] * (xd - f0.x) + G[1] * (yd - f0.y);
   if (DIM == 3) gp += G[2] * (zd - f0.z);
   double phid = f0.w + gp;
-  // slip: U_d = U_f - (U_f . n_d) n_d
+  // slip: U_d = U_f - (U_f . n_d) n_d; for the moving body relative to its
+  // velocity Uw, U_d = U_f - ((U_f - Uw) . n_d) n_d (the dummy keeps the
+  // wall's normal velocity)
   double nx = d.n[0][k], ny = d.n[1][k], nz = DIM == 3 ? d.n[2][k] : 0.0;
-  double un = f1.x * nx + f1.y * ny + f1.z * nz;
+  double un;
+  if (d.mov != nullptr && d.mov[k]) {
+    un = (f1.x - sc->body_u[0]) * nx + (f1.y - sc->body_u[1]) * ny;
+    if (DIM == 3) un += (f1.z - sc->body_u[2]) * nz;
+  } else {
+    un = f1.x * nx + f1.y * ny + f1.z * nz;
+  }
   double V = d.m[k] / (P.rho0 * exp(phid * P.inv_c02));
   drec0[k] = make_double4(xd, yd, zd, phid);
   drec1[k] = make_double4(f1.x - un * nx, f1.y - un * ny, DIM == 3 ? f1.z - un * nz : 0.0, V);

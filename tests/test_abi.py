@@ -83,6 +83,39 @@ def test_kept_lists_workspace(L):
     assert extra <= mixed <= extra + 3 * 256
 
 
+def test_body_motion_validation_and_workspace(L):
+    """The prescribed body motion: 1..4 pieces with strictly increasing, finite
+    breakpoints and finite coefficients; a moving body adds a second buffer
+    for the dummies and their reference positions, and no kept lists."""
+    lib = L.lib()
+    c = wl.entry2d()
+    p = L.params_from_dict(c["params"])
+    assert p.body_pieces == 2
+    assert lib.sph_validate(C.byref(p)) == L.SPH_OK
+    for field, val in (("body_pieces", 5), ("body_pieces", -1)):
+        q = L.params_from_dict(c["params"])
+        setattr(q, field, val)
+        assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+    q = L.params_from_dict(c["params"])
+    q.body_t[1] = q.body_t[0]
+    assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+    q = L.params_from_dict(c["params"])
+    q.body_b[1][0] = float("nan")
+    assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+    nf, nd = 1770, 558
+    still = L.params_from_dict({k: v for k, v in c["params"].items() if not k.startswith("body_")})
+    extra = lib.sph_workspace_bytes(C.byref(p), nf, nd) - lib.sph_workspace_bytes(C.byref(still), nf, nd)
+    # per dummy: the second buffer (x, n: 4 doubles; m, phi_in; id, src), the
+    # reference positions and motion flags of both buffers; per particle: the
+    # staging of the reference positions and flags at init; alignment
+    per = 8 * 4 + 8 + 8 + 4 + 4 + 2 * (8 * 2 + 1)
+    assert nd * per <= extra <= nd * per + (8 * 2 + 1) * (nf + nd) + 16 * 256
+    h = c["params"]["h"]
+    kept = L.params_from_dict(wl.with_params(c, keep_lists=True, cell_size=2.1 * h)["params"])
+    plain = L.params_from_dict(wl.with_params(c, cell_size=2.1 * h)["params"])
+    assert lib.sph_workspace_bytes(C.byref(kept), nf, nd) == lib.sph_workspace_bytes(C.byref(plain), nf, nd)
+
+
 def _init(L, case, x=None, u=None, phi=None, kind=None, normal=None, ws=256, ws_bytes=1 << 40):
     lib = L.lib()
     p = L.params_from_dict(case["params"])

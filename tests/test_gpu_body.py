@@ -1,0 +1,136 @@
+"""A body moving along a prescribed velocity history (kind-2 dummies, the
+aircraft-ditching case of Sec. 4) on the GPU against the oracle.
+
+The body's dummies are placed at x + D(t) at every right-hand side and all
+dummies re-sorted; the mirror keeps the wall's normal velocity.  FP64 path:
+one right-hand side at the bars of the fixed-wall cases (fields 1e-12,
+neighbour counts, mirror sources and flags exact), ten-step trajectories
+(fluid to 1e-12 of the domain, the body's positions to rounding), 2D and 3D.
+Mixed path: one right-hand side against the oracle at the state it stores
+(2e-5) and ten steps against the FP64 path.  SPH_F_KEEP_LISTS has no effect
+with a moving body.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from test_gpu_mixed import _own_state_case
+from test_gpu_parity import _flags_all, compare_rates
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2608_22269_amd import Simulation
+    return Simulation
+
+
+def _entry2d(t=0.0):
+    case = wl.entry2d(**_flags_all())
+    case = wl.random_velocity(wl.jitter(case, 0.1, 31), 0.05, 32)
+    case["t"] = t
+    return case
+
+
+def _entry3d(t=0.0):
+    motion = {"body_t": [0.0, 0.1, 0.3], "body_a": [[-0.5, 0.2, -0.5], [-0.75, 0.3, -0.75]],
+              "body_b": [[0.0, 0.0, 0.0], [2.5, -1.0, 2.5]]}
+    case = wl.ditch3d(dx=0.02, tank=(0.6, 0.3, 0.3), depth=0.16, body=((0.3, 0.1, 0.12), (0.42, 0.2, 0.22)),
+                      motion=motion)
+    case = wl.random_velocity(wl.jitter(case, 0.1, 33), 0.05, 34)
+    case["t"] = t
+    return case
+
+
+CASES = [("entry2d t=0", _entry2d()), ("entry2d t=0.12", _entry2d(0.12)), ("ditch3d-mini t=0", _entry3d()),
+         ("ditch3d-mini t=0.05", _entry3d(0.05))]
+
+
+def _body_x(case, t):
+    D, _ = oracle.body_motion(case["params"], t)
+    b = case["kind"] == 2
+    return case["x"][b] + D[: case["params"]["dim"]]
+
+
+@pytest.mark.parametrize("name,case", CASES, ids=[c[0] for c in CASES])
+def test_body_rates_parity(Sim, name, case):
+    sim = Sim(case)
+    sim.eval_rates()
+    ref = oracle.eval_rates(case)
+    print(name, compare_rates(sim, case, ref))
+    b = case["kind"] == 2
+    assert np.array_equal(sim.field("x")[b], _body_x(case, case["t"]))
+    assert (ref["mir_src"][b] >= 0).sum() > 10
+
+
+@pytest.mark.parametrize("name,case", [CASES[0], CASES[2]], ids=[CASES[0][0], CASES[2][0]])
+def test_body_trajectory_parity(Sim, name, case):
+    sim = Sim(case)
+    sim.step(10)
+    ref = oracle.step(case, 10)
+    f = case["kind"] == 0
+    L = max(case["params"]["domain_hi"]) - min(case["params"]["domain_lo"])
+    assert np.abs(sim.field("x")[f] - ref["x"][f]).max() <= 1e-12 * L
+    umax = max(np.abs(ref["u"][f]).max(), 1e-3)
+    assert np.abs(sim.field("u")[f] - ref["u"][f]).max() <= 1e-10 * umax
+    pmax = np.abs(ref["phi"][f]).max()
+    assert np.abs(sim.field("phi")[f] - ref["phi"][f]).max() <= 1e-11 * pmax
+    t = sim.stats()["t"]
+    assert abs(t - ref["t"]) <= 1e-15
+    b = case["kind"] == 2
+    xb = sim.field("x")[b]
+    assert np.abs(xb - _body_x(case, ref["t"])).max() <= 1e-15 * L
+    # the body moved: by more than a few rounding steps of the domain size
+    assert np.abs(xb - case["x"][b]).max() > 1e-6
+
+
+def test_body_keep_lists_have_no_effect(Sim):
+    case = _entry2d()
+    h = case["params"]["h"]
+    case = wl.with_params(case, cell_size=2.1 * h)
+    a = Sim(wl.with_params(case, keep_lists=True, keep_across_steps=True))
+    b = Sim(case)
+    a.step(3)
+    b.step(3)
+    assert a.stats()["n_kept"] == 0
+    for name in ("x", "u", "phi", "dudt", "nnb", "mirror_src"):
+        assert np.array_equal(a.field(name), b.field(name)), name
+
+
+@pytest.mark.parametrize("name,case", [CASES[1], CASES[3]], ids=[CASES[1][0], CASES[3][0]])
+def test_mixed_body_rates(Sim, name, case):
+    sim = Sim(wl.with_params(case, precision="mixed"))
+    sim.eval_rates()
+    ref = oracle.eval_rates(_own_state_case(sim, case))
+    f = case["kind"] == 0
+    acc = sim.field("dudt")
+    s_acc = max(9.81, np.abs(ref["acc"][f]).max())
+    err_acc = np.abs(acc[f] - ref["acc"][f]).max() / s_acc
+    dphi = sim.field("dphidt")
+    s_dphi = max(np.abs(ref["dphi"][f]).max(), case["params"]["c0"] * 9.81 * case["params"]["h"])
+    err_dphi = np.abs(dphi[f] - ref["dphi"][f]).max() / s_dphi
+    bad_nnb = int((sim.field("nnb")[f] != ref["nnb"][f]).sum())
+    print(f"{name}: acc {err_acc:.2e} dphi {err_dphi:.2e} nnb mismatches {bad_nnb}")
+    assert err_acc <= 2e-5
+    assert err_dphi <= 2e-5
+    assert bad_nnb <= max(1, 1e-4 * f.sum())
+
+
+def test_mixed_body_trajectory_tracks_fp64(Sim):
+    case = CASES[0][1]
+    f = case["kind"] == 0
+    sm = Sim(wl.with_params(case, precision="mixed"))
+    sd = Sim(case)
+    sm.step(10)
+    sd.step(10)
+    dx = np.abs(sm.field("x")[f] - sd.field("x")[f]).max()
+    du = np.abs(sm.field("u")[f] - sd.field("u")[f]).max() / np.abs(sd.field("u")[f]).max()
+    dp = np.abs(sm.field("phi")[f] - sd.field("phi")[f]).max() / np.abs(sd.field("phi")[f]).max()
+    print(f"10 steps: |dx| {dx:.2e} m, rel |dU| {du:.2e}, rel |dphi| {dp:.2e}")
+    assert dx <= 1e-7
+    assert du <= 1e-4
+    assert dp <= 1e-4

@@ -43,7 +43,10 @@ def _own_state_case(sim, case):
     c["u"] = sim.field("u")
     c["phi"] = sim.field("phi")
     c["mass"] = sim.field("mass")
-    d = case["kind"] == 1
+    # dummies: their inputs (a moving body's at its reference time; the
+    # oracle places it)
+    d = case["kind"] != 0
+    c["x"][d] = case["x"][d]
     c["u"][d] = case["u"][d]
     c["phi"][d] = case["phi"][d]
     return c

@@ -55,7 +55,7 @@ def _rel(a, b, scale):
 def compare_rates(sim, case, ref, tol=TOL):
     """Element-wise comparison of every output of one right-hand side."""
     f = case["kind"] == 0
-    d = case["kind"] == 1
+    d = case["kind"] != 0
     pd = case["params"]
     gmag = float(np.linalg.norm(pd["gravity"])) or 1.0
     acc = sim.field("dudt")
