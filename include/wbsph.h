@@ -22,8 +22,9 @@
  *     outside the hashed domain, non-finite state, a neighbour list beyond
  *     its capacity) are recorded on the device and reported by the next call
  *     that synchronises (sph_sync, sph_fields into host memory, sph_neighbors);
- *     after such an error only sph_fields, sph_last_error and sph_destroy are
- *     accepted (SPH_ESTATE otherwise).
+ *     after such an error only sph_fields (which still fills its output and
+ *     returns the error), sph_last_error and sph_destroy are accepted
+ *     (SPH_ESTATE otherwise).
  *   - A context is not thread-safe; several contexts may coexist.
  */
 #ifndef WBSPH_H

@@ -45,7 +45,9 @@ def device_buffer(nbytes: int, device="cuda"):
 class Simulation:
     """One context of the library over a workload dictionary (see workloads)."""
 
-    def __init__(self, case: dict, device="cuda", stream=None, **overrides):
+    def __init__(self, case: dict, device="cuda", stream=None, device_inputs=False, **overrides):
+        """device_inputs: hand sph_init device copies of the particle arrays
+        (its inputs_on_device path) instead of host arrays."""
         import torch
         self.torch = torch
         pd = dict(case["params"])
@@ -72,9 +74,19 @@ class Simulation:
         m = case.get("mass")
         m = None if m is None else np.ascontiguousarray(m, dtype=np.float64)
         ctx = C.c_void_p()
-        p_ = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
-        st = lib.sph_init(C.byref(self.p), self.n, p_(x), p_(u), p_(phi), p_(m), p_(kind), p_(nrm), 0,
-                          C.c_void_p(ptr), nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if device_inputs:
+            held = [torch.from_numpy(a).to(self.device) if a is not None else None for a in (x, u, phi, m, kind, nrm)]
+            torch.cuda.synchronize(self.device)
+            p_ = lambda a: C.c_void_p(a.data_ptr()) if a is not None else None
+            x_, u_, phi_, m_, kind_, nrm_ = held
+            st = lib.sph_init(C.byref(self.p), self.n, p_(x_), p_(u_), p_(phi_), p_(m_), p_(kind_), p_(nrm_), 1,
+                              C.c_void_p(ptr), nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+            self.stream.synchronize()
+            del held
+        else:
+            p_ = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+            st = lib.sph_init(C.byref(self.p), self.n, p_(x), p_(u), p_(phi), p_(m), p_(kind), p_(nrm), 0,
+                              C.c_void_p(ptr), nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         _check(st, "sph_init")
         self.ctx = ctx
         t0 = float(case.get("t", 0.0))
