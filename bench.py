@@ -12,7 +12,7 @@ the lists' skin; --keep-cell 0 sorts and searches at both right-hand sides).
 
 Prints one JSON line (metric, value = pair evaluations per second of the
 headline path, ms/step, rooflines of the pair passes, CPU oracle baseline,
-the mixed and learned paths, the lists kept across steps, a body moving
+the mixed, learned and single-precision paths, the lists kept across steps, a body moving
 along the ditching velocity history, MLP inference, spurious velocities).
 """
 from __future__ import annotations
@@ -361,9 +361,10 @@ def main():
     ap.add_argument("--across-cell", type=float, default=1.03,
                     help="cell size in units of h of the runs with the lists kept across steps (more room: longer "
                          "lived lists, slightly more candidates)")
-    ap.add_argument("--paths", default="fp64,mixed,mixed_learned",
+    ap.add_argument("--paths", default="fp64,mixed,mixed_learned,fp32",
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
-                         "mixed_learned: mixed precision with the trained classifier and exact fallback")
+                         "mixed_learned: mixed precision with the trained classifier and exact fallback; "
+                         "fp32: the single-precision form (no kept lists: both stages search, cells of --cell h)")
     ap.add_argument("--dambreak-spin", type=int, default=4000,
                     help="steps of the 3D dam break before the exact / learned detection comparison (0: skip)")
     ap.add_argument("--bump-steps", type=int, default=10000,
@@ -403,6 +404,8 @@ def main():
             results["fp64"] = run_path(run_case, "fp64", args.steps, args.warmup)
         elif path == "mixed":
             results["mixed"] = run_path(wl.with_params(run_case, precision="mixed"), "mixed", args.steps, args.warmup)
+        elif path == "fp32":
+            results["fp32"] = run_path(wl.with_params(case, precision="fp32"), "fp32", args.steps, args.warmup)
         elif path == "mixed_learned":
             results["mixed_learned"] = run_path(wl.with_params(run_case, precision="mixed", fs_mode="learned"),
                                                 "mixed_learned", args.steps, args.warmup, clf=load_classifier())
@@ -465,7 +468,7 @@ def main():
                                                   kept=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.dx)
-    for k in ("mixed", "mixed_learned"):
+    for k in ("mixed", "mixed_learned", "fp32"):
         if k in results:
             out[f"{k}_over_fp64_step_rate"] = results["fp64"]["ms_per_step"] / results[k]["ms_per_step"]
     if args.keep_cell > 0 and not args.no_across_steps:
@@ -487,7 +490,7 @@ def main():
     out["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:
         out["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)
-    out["spurious_u_tank2d_100steps"] = {"fp64": spurious_velocity("fp64"), "mixed": spurious_velocity("mixed")}
+    out["spurious_u_tank2d_100steps"] = {k: spurious_velocity(k) for k in ("fp64", "mixed", "fp32")}
     if args.bump_steps > 0:
         out["spurious_u_bump2d"] = bump_history(args.bump_steps, 500)
     print(json.dumps(out), flush=True)

@@ -52,6 +52,12 @@ typedef int32_t sph_status;
 #define SPH_FP64 0  /* FP64 storage and arithmetic throughout                     */
 #define SPH_MIXED 1 /* int cell + FP32 offset positions, FP32 pair evaluation,
                        FP64 accumulation of L and of the potential-gradient sums */
+#define SPH_FP32 2  /* the paper's single-precision design (Sec. 3): the
+                       mixed path's storage (which keeps what Kahan-compensated
+                       FP32 attributes keep), but every pair term in FP32 from
+                       the absolute FP32 positions and FP32 potentials (sums
+                       per list fill in FP32, totals and epilogue in FP64);
+                       for comparison with the other two forms; no kept lists */
 
 /* free-surface detection */
 #define SPH_FS_NONE 0
@@ -88,7 +94,7 @@ typedef int32_t sph_status;
 
 typedef struct sph_params {
     int32_t dim;        /* 2 or 3; gravity usually along the last axis          */
-    int32_t precision;  /* SPH_FP64 | SPH_MIXED                                 */
+    int32_t precision;  /* SPH_FP64 | SPH_MIXED | SPH_FP32                      */
     int32_t fs_mode;    /* SPH_FS_*                                             */
     uint32_t flags;     /* SPH_F_*                                              */
     double dx;          /* initial particle spacing                             */

@@ -22,7 +22,7 @@ SPH_ESTATE = -6
 SPH_EUNSUPPORTED = -7
 SPH_ECAPACITY = -8
 
-SPH_FP64, SPH_MIXED = 0, 1
+SPH_FP64, SPH_MIXED, SPH_FP32 = 0, 1, 2
 SPH_FS_NONE, SPH_FS_EXACT, SPH_FS_LEARNED = 0, 1, 2
 SPH_F_DELTA, SPH_F_PST, SPH_F_TIC, SPH_F_FS_PROJECT, SPH_F_CONT_UNCORR, SPH_F_FEATURES = 1, 2, 4, 8, 16, 32
 SPH_F_KEEP_LISTS = 64
@@ -123,7 +123,7 @@ def params_from_dict(pd: dict) -> SphParams:
     """sph_params from the plain parameter dictionary of a workload."""
     p = SphParams()
     p.dim = int(pd["dim"])
-    p.precision = SPH_MIXED if pd.get("precision", "fp64") == "mixed" else SPH_FP64
+    p.precision = {"fp64": SPH_FP64, "mixed": SPH_MIXED, "fp32": SPH_FP32}[pd.get("precision", "fp64")]
     p.fs_mode = {"none": SPH_FS_NONE, "exact": SPH_FS_EXACT, "learned": SPH_FS_LEARNED}[pd.get("fs_mode", "none")]
     p.flags = ((SPH_F_DELTA if pd.get("delta_sph") else 0) | (SPH_F_PST if pd.get("pst") else 0)
                | (SPH_F_TIC if pd.get("tic") else 0) | (SPH_F_FS_PROJECT if pd.get("fs_project") else 0)

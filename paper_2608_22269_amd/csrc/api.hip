@@ -127,7 +127,8 @@ bool params_ok(const sph_params *p, std::string *why) {
   };
   if (!p) return bad("params is NULL");
   if (p->dim != 2 && p->dim != 3) return bad("dim must be 2 or 3");
-  if (p->precision != SPH_FP64 && p->precision != SPH_MIXED) return bad("unknown precision");
+  if (p->precision != SPH_FP64 && p->precision != SPH_MIXED && p->precision != SPH_FP32)
+    return bad("unknown precision");
   if (p->fs_mode < SPH_FS_NONE || p->fs_mode > SPH_FS_LEARNED) return bad("unknown fs_mode");
   if (!(p->dx > 0) || !(p->h > 0) || !(p->c0 > 0) || !(p->rho0 > 0)) return bad("dx, h, c0, rho0 must be > 0");
   if (!(p->cfl > 0) || !(p->nu >= 0)) return bad("cfl must be > 0 and nu >= 0");
@@ -209,15 +210,16 @@ void derive(const sph_params *p, Phys &P, Grid &g) {
   // cells of reach R cover a ball of radius reach R around any point; the
   // kept lists need 2h + skin inside it (a small margin keeps the cut away
   // from the rounding of cell indices)
-  // (a moving body re-sorts the dummies at every right-hand side: no lists)
-  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u && p->body_pieces == 0;
+  // (a moving body re-sorts the dummies at every right-hand side, and the
+  // single-precision form has no pass from kept lists: no lists)
+  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u && p->body_pieces == 0 && p->precision != SPH_FP32;
   P.skin_max = keep ? std::max(0.0, (double)g.reach * g.R - P.two_h - 1e-6 * g.R) : 0.0;
   // absolute part of the skin: far above the rounding of FP64 positions; on
   // the mixed path, above twice the rounding of the FP32 absolute positions
   // and of the FP32 distance test
   double xmax = 0.0;
   for (int a = 0; a < p->dim; ++a) xmax = std::max(xmax, std::max(std::fabs(p->domain_lo[a]), std::fabs(p->domain_hi[a])));
-  P.skin_pad = p->precision == SPH_MIXED ? 1e-6 * xmax + 1e-5 * p->h : 1e-9 * p->h;
+  P.skin_pad = p->precision != SPH_FP64 ? 1e-6 * xmax + 1e-5 * p->h : 1e-9 * p->h;
   g.ncell = 1;
   for (int a = 0; a < 3; ++a) {
     g.lo[a] = p->domain_lo[a];
@@ -465,7 +467,7 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
     if (e == hipSuccess) {
       ProfScope ps(c, mode == kPairKept ? 5 : 0);
       e = launch_pair_mixed(c->P, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat,
-                            mode, c->kent, c->kcnt, c->s);
+                            mode, c->kent, c->kcnt, c->s, c->p.precision == SPH_FP32);
     }
   }
   ProfScope ps_fs(c, 3);
@@ -570,7 +572,7 @@ size_t sph_workspace_bytes(const sph_params *p, int64_t n_fluid, int64_t n_dummy
   c.nf = n_fluid;
   c.nd = n_dummy;
   c.n = n_fluid + n_dummy;
-  c.mixed = p->precision == SPH_MIXED;
+  c.mixed = p->precision != SPH_FP64;
   derive(p, c.P, c.g);
   return carve(&c, 0, 0);
 }
@@ -622,7 +624,7 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   c->dim = dim;
   c->n = n;
   c->s = s;
-  c->mixed = p->precision == SPH_MIXED;
+  c->mixed = p->precision != SPH_FP64;
   c->status = SPH_OK;
   c->has_clf = false;
   c->has_body = p->body_pieces > 0;

@@ -403,11 +403,101 @@ __device__ __forceinline__ void mixed_body(const MixedI &I, const float4 &b0, co
   }
 }
 
+// Sums of the single-precision form (SPH_FP32) that the mixed form keeps in
+// FP64: the correction matrix and the potential-gradient sums, here in FP32
+// over one list fill.
+struct Abs32Chunk {
+  float L[6], SR[3], SC[3];
+};
+
+__device__ __forceinline__ void abs32_zero(Abs32Chunk &A) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a) A.L[a] = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) A.SR[a] = A.SC[a] = 0.f;
+}
+
+__device__ __forceinline__ void abs32_flush(const Abs32Chunk &A, PairSums &S) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a) S.L[a] += A.L[a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    S.SR[a] += A.SR[a];
+    S.SC[a] += A.SC[a];
+  }
+}
+
+// Pair body of the single-precision form, as the paper's GPU code computes
+// it (Sec. 3: single precision throughout the particle interactions): r is
+// the difference of the absolute FP32 positions, phi_j - phi_i that of the
+// FP32 potentials, and every sum of Eq. (sph) is an FP32 sum over the list
+// fill.  Only the totals over the fills and the epilogue are FP64.
+template <int DIM, bool FEAT, bool PST4>
+__device__ __forceinline__ void abs32_body(const MixedI &I, const float4 &xi, const float phii, const float4 &xj,
+                                           const float4 &b1, const float phij, const uint32_t j, const uint32_t nf,
+                                           MixedChunk &C, Abs32Chunk &A, PairSums &S) {
+  const float rx = xj.x - xi.x, ry = xj.y - xi.y, rz = DIM == 3 ? xj.z - xi.z : 0.f;
+  const float r2 = rx * rx + ry * ry + rz * rz;
+  S.coincident |= (r2 == 0.f);
+  const float is = rsqrtf(r2);
+  const float s = r2 * is;
+  const float q = fminf(s * I.inv_h, 2.0f);
+  const float t = 1.0f - 0.5f * q;
+  const float t2 = t * t, t3 = t2 * t;
+  const float wv = I.kfac * t3 * b1.w;
+  const float gx = wv * rx, gy = wv * ry, gz = wv * rz;
+  A.L[0] += rx * gx;
+  A.L[1] += ry * gy;
+  A.L[3] += rx * gy;
+  if (DIM == 3) {
+    A.L[2] += rz * gz;
+    A.L[4] += rx * gz;
+    A.L[5] += ry * gz;
+  }
+  const float dph = phij - phii;
+  const float dux = b1.x - I.a1.x, duy = b1.y - I.a1.y, duz = DIM == 3 ? b1.z - I.a1.z : 0.f;
+  const float dun = (dux * rx + duy * ry + duz * rz) * is;
+  const float c2 = dph - I.c0f * dun;
+  const float cs = phij + phii;
+  A.SR[0] += c2 * gx;
+  A.SR[1] += c2 * gy;
+  A.SC[0] += cs * gx;
+  A.SC[1] += cs * gy;
+  if (DIM == 3) {
+    A.SR[2] += c2 * gz;
+    A.SC[2] += cs * gz;
+  }
+  C.gsf[0] += gx;
+  C.gsf[1] += gy;
+  if (DIM == 3) C.gsf[2] += gz;
+  C.Nf[0] += dux * gx;
+  C.Nf[1] += duy * gy;
+  C.Nf[3] += dux * gy + duy * gx;
+  if (DIM == 3) {
+    C.Nf[2] += duz * gz;
+    C.Nf[4] += dux * gz + duz * gx;
+    C.Nf[5] += duy * gz + duz * gy;
+  }
+  C.Df += wv * dph;
+  const float W = I.alpha * t2 * t2 * (2.0f * q + 1.0f);
+  const float wr = W * I.w0inv;
+  const float wrn = PST4 ? (wr * wr) * (wr * wr) : powf(wr, I.pst_n);
+  C.Pf[0] += wrn * gx;
+  C.Pf[1] += wrn * gy;
+  if (DIM == 3) C.Pf[2] += wrn * gz;
+  if (FEAT) {
+    C.S0f += wr * b1.w;
+    S.qmin = fminf(S.qmin, s);
+    S.ndum += j >= nf ? 1u : 0u;
+  }
+}
+
 // The mixed pair pass with its own candidate search (FP32 test on the
-// absolute FP32 positions).  KEEP: as for the FP64 pass -- search radius
+// absolute FP32 positions).  ABS: the single-precision form's body (no kept
+// lists).  KEEP: as for the FP64 pass -- search radius
 // 2h + skin, tagged skin candidates skipped by the body, non-empty list
 // fills kept in kl.
-template <int DIM, bool FEAT, bool PST4, bool KEEP>
+template <int DIM, bool FEAT, bool PST4, bool KEEP, bool ABS = false>
 __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     k_pair_mixed(Phys P, Grid g, MixedRec rec, const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
                  uint32_t nf, Scalars *sc, Rates out, uint32_t *__restrict__ cand, KeptLists kl) {
@@ -459,12 +549,23 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     }
     MixedChunk C;
     chunk_zero(C);
-    for (int k = 0; k < cnt; ++k) {
-      const uint32_t e = list[k][tid];
-      if (KEEP && (e & kSkinTag)) continue;
-      const uint32_t j = e;
-      mixed_body<DIM, FEAT, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], j, nf, C, S);
-      if (KEEP) S.nnb += 1;
+    if constexpr (ABS) {
+      Abs32Chunk A;
+      abs32_zero(A);
+      const float phif = (float)phii;
+      for (int k = 0; k < cnt; ++k) {
+        const uint32_t j = list[k][tid];
+        abs32_body<DIM, FEAT, PST4>(I, axa, phif, rec.xa[j], rec.r1[j], (float)rec.phi[j], j, nf, C, A, S);
+      }
+      abs32_flush(A, S);
+    } else {
+      for (int k = 0; k < cnt; ++k) {
+        const uint32_t e = list[k][tid];
+        if (KEEP && (e & kSkinTag)) continue;
+        const uint32_t j = e;
+        mixed_body<DIM, FEAT, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], j, nf, C, S);
+        if (KEEP) S.nnb += 1;
+      }
     }
     chunk_flush(C, S);
     if (!KEEP) S.nnb += cnt;
@@ -563,10 +664,17 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
 template <int DIM, bool FEAT>
 void launch_pair_mixed_inst(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                             const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
-                            const KeptLists &kl, int mode, hipStream_t s) {
+                            const KeptLists &kl, int mode, bool abs32, hipStream_t s) {
   dim3 gr(grid_for(nf)), bl(kBlock);
   const bool p4 = P.pst_n == 4.0;
-  if (mode == kPairSearch) {
+  if (abs32) {
+    if (p4)
+      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
+                         out, cand, kl);
+    else
+      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
+                         out, cand, kl);
+  } else if (mode == kPairSearch) {
     if (p4)
       hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
                          cand, kl);
@@ -590,20 +698,21 @@ void launch_pair_mixed_inst(const Phys &P, const Grid &g, const MixedRec &rec, c
 
 hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                              const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
-                             bool features, int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s) {
+                             bool features, int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s,
+                             bool abs32) {
   if (nf == 0) return hipSuccess;
-  if (mode != kPairSearch && (!kent || !kcnt)) return hipErrorInvalidValue;
+  if (mode != kPairSearch && (abs32 || !kent || !kcnt)) return hipErrorInvalidValue;
   KeptLists kl{kent, kcnt};
   if (P.dim == 2) {
     if (features)
-      launch_pair_mixed_inst<2, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
+      launch_pair_mixed_inst<2, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
     else
-      launch_pair_mixed_inst<2, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
+      launch_pair_mixed_inst<2, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
   } else {
     if (features)
-      launch_pair_mixed_inst<3, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
+      launch_pair_mixed_inst<3, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
     else
-      launch_pair_mixed_inst<3, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
+      launch_pair_mixed_inst<3, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
   }
   return hipGetLastError();
 }
