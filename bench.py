@@ -461,7 +461,7 @@ def main():
     if "mixed" in results:
         # non-packed FP32 issues at the FP64 rate on this chip: same peak
         out["roofline_mixed"] = roofline(results["mixed"], "pair_mixed",
-                                         "k_pair_mixed<3,false,true,true> (first-stage pass, FP32 body + FP64 sums)")
+                                         "k_pair_mixed<3,false,true,true,false> (first-stage pass, FP32 body + FP64 sums)")
         if "kept_pass" in results["mixed"]:
             out["roofline_kept_mixed"] = roofline(results["mixed"], "pair_kept_mixed",
                                                   "k_pair_kept_mixed<3,false,true> (second stage from the kept lists)",
