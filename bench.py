@@ -375,7 +375,7 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (slab decomposition is designed, "
+        print("bench.py measures one GPU: the library has no multi-GPU path (slab decomposition is designed, "
               "not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
