@@ -19,7 +19,8 @@ hipError_t launch_reorder_f64(const Phys &P, const uint32_t *perm, int64_t n, co
 hipError_t launch_refresh_f64(const Phys &P, const FluidF64 &f, int64_t n, double4 *rec0, double4 *rec1,
                               hipStream_t s);
 
-// Dummy wall particles (static, sorted once by cell).
+// Dummy wall particles, sorted by (cell, original index): once, or at every
+// right-hand side when a body moves.
 struct Dummies {
   double *x[3], *n[3], *m, *phi_in;
   uint32_t *id;
