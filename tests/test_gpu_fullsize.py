@@ -7,7 +7,9 @@ neighbour lists of those particles alone, and every output of the sample is
 compared element by element: FP64 path to 1e-12, mixed path (against the
 oracle at the state the mixed path stores) to its 2e-5 bar.
 The 2D Gaussian-bump layer and the 3D dam break are small enough for the
-oracle to evaluate every particle.
+oracle to evaluate every particle (the dam break also over two steps with
+kept lists); the 3D ditching-style tank with its moving body (3.82M) is
+compared on sampled rows around the body and elsewhere.
 """
 import numpy as np
 import pytest
@@ -146,3 +148,51 @@ def test_kept_lists_full_size(Sim, slosh):
         assert err <= 1e-11, name
     a.close()
     b.close()
+
+
+def test_dam_break_full_size_trajectory_with_kept_lists(Sim):
+    """Two steps of the 3D dam break (1.13M particles) with the second stages
+    from kept lists (cells of 1.01 h) against the oracle's two steps."""
+    case = wl.dambreak3d(dx=0.01)
+    case = wl.random_velocity(case, 0.05, 19)
+    case = wl.with_params(case, cell_size=1.01 * case["params"]["h"], keep_lists=True)
+    sim = Sim(case)
+    sim.step(2)
+    assert sim.stats()["n_kept"] == 2
+    ref = oracle.step(case, 2)
+    f = case["kind"] == 0
+    L = max(case["params"]["domain_hi"]) - min(case["params"]["domain_lo"])
+    ex = np.abs(sim.field("x")[f] - ref["x"][f]).max() / L
+    eu = np.abs(sim.field("u")[f] - ref["u"][f]).max() / np.abs(ref["u"][f]).max()
+    ep = np.abs(sim.field("phi")[f] - ref["phi"][f]).max() / np.abs(ref["phi"][f]).max()
+    print(f"x {ex:.2e} u {eu:.2e} phi {ep:.2e}")
+    assert ex <= 1e-12 and eu <= 1e-10 and ep <= 1e-11
+    assert abs(sim.stats()["t"] - ref["t"]) <= 1e-15
+    sim.close()
+
+
+def test_moving_body_full_size_sampled(Sim):
+    """The bench's 3D ditching-style tank (3.82M fluid, the box body on the
+    printed history, R = h, jittered fluid) at t = 3.7 ms (the body 3.7
+    spacings on): 1,500 sampled fluid rows within 3h of the body and 500
+    elsewhere against the oracle's sampled-row mode."""
+    case = wl.ditch3d(dx=0.005)
+    case = wl.with_params(case, cell_size=case["params"]["h"])
+    case = wl.random_velocity(wl.jitter(case, 0.1, 30), 0.05, 29)
+    case["t"] = 0.0037
+    rng = np.random.default_rng(3)
+    f = np.nonzero(case["kind"] == 0)[0]
+    D, _ = oracle.body_motion(case["params"], case["t"])
+    b = case["kind"] == 2
+    lo = case["x"][b].min(0) + D - 3 * case["params"]["h"]
+    hi = case["x"][b].max(0) + D + 3 * case["params"]["h"]
+    xf = case["x"][f]
+    near = f[np.all((xf > lo) & (xf < hi), axis=1)]
+    rows = np.unique(np.concatenate([rng.choice(near, 1500, replace=False), rng.choice(f, 500, replace=False)]))
+    sim = Sim(case)
+    sim.eval_rates()
+    ref = oracle.eval_rates(case, rows=rows)
+    nnb = _compare_rows(sim, case, ref, rows, TOL, TOL)
+    assert np.array_equal(nnb, ref["nnb"][rows])
+    assert np.array_equal(sim.field("x")[b], case["x"][b] + D)
+    sim.close()
