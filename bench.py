@@ -364,7 +364,7 @@ def main():
     ap.add_argument("--paths", default="fp64,mixed,mixed_learned,fp32",
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
                          "mixed_learned: mixed precision with the trained classifier and exact fallback; "
-                         "fp32: the single-precision form (no kept lists: both stages search, cells of --cell h)")
+                         "fp32: the single-precision form")
     ap.add_argument("--dambreak-spin", type=int, default=4000,
                     help="steps of the 3D dam break before the exact / learned detection comparison (0: skip)")
     ap.add_argument("--bump-steps", type=int, default=10000,
@@ -405,7 +405,7 @@ def main():
         elif path == "mixed":
             results["mixed"] = run_path(wl.with_params(run_case, precision="mixed"), "mixed", args.steps, args.warmup)
         elif path == "fp32":
-            results["fp32"] = run_path(wl.with_params(case, precision="fp32"), "fp32", args.steps, args.warmup)
+            results["fp32"] = run_path(wl.with_params(run_case, precision="fp32"), "fp32", args.steps, args.warmup)
         elif path == "mixed_learned":
             results["mixed_learned"] = run_path(wl.with_params(run_case, precision="mixed", fs_mode="learned"),
                                                 "mixed_learned", args.steps, args.warmup, clf=load_classifier())

@@ -57,7 +57,7 @@ typedef int32_t sph_status;
                        FP32 attributes keep), but every pair term in FP32 from
                        the absolute FP32 positions and FP32 potentials (sums
                        per list fill in FP32, totals and epilogue in FP64);
-                       for comparison with the other two forms; no kept lists */
+                       for comparison with the other two forms              */
 
 /* free-surface detection */
 #define SPH_FS_NONE 0

@@ -210,9 +210,8 @@ void derive(const sph_params *p, Phys &P, Grid &g) {
   // cells of reach R cover a ball of radius reach R around any point; the
   // kept lists need 2h + skin inside it (a small margin keeps the cut away
   // from the rounding of cell indices)
-  // (a moving body re-sorts the dummies at every right-hand side, and the
-  // single-precision form has no pass from kept lists: no lists)
-  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u && p->body_pieces == 0 && p->precision != SPH_FP32;
+  // (a moving body re-sorts the dummies at every right-hand side: no lists)
+  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u && p->body_pieces == 0;
   P.skin_max = keep ? std::max(0.0, (double)g.reach * g.R - P.two_h - 1e-6 * g.R) : 0.0;
   // absolute part of the skin: far above the rounding of FP64 positions; on
   // the mixed path, above twice the rounding of the FP32 absolute positions

@@ -25,7 +25,7 @@ hipError_t launch_mirror_mixed(const Phys &P, const Grid &g, const Dummies &d, i
                                const uint32_t *cs_f, uint32_t nf, const Scalars *sc, hipStream_t s,
                                const uint32_t *fid);
 // modes and kept lists as for launch_pair_f64; abs32: the single-precision
-// form of the pair sums (SPH_FP32; own search only)
+// form of the pair sums (SPH_FP32)
 hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                              const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
                              bool features, int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s,

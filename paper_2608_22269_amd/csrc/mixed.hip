@@ -493,8 +493,7 @@ __device__ __forceinline__ void abs32_body(const MixedI &I, const float4 &xi, co
 }
 
 // The mixed pair pass with its own candidate search (FP32 test on the
-// absolute FP32 positions).  ABS: the single-precision form's body (no kept
-// lists).  KEEP: as for the FP64 pass -- search radius
+// absolute FP32 positions).  ABS: the single-precision form's body.  KEEP: as for the FP64 pass -- search radius
 // 2h + skin, tagged skin candidates skipped by the body, non-empty list
 // fills kept in kl.
 template <int DIM, bool FEAT, bool PST4, bool KEEP, bool ABS = false>
@@ -554,8 +553,11 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
       abs32_zero(A);
       const float phif = (float)phii;
       for (int k = 0; k < cnt; ++k) {
-        const uint32_t j = list[k][tid];
+        const uint32_t e = list[k][tid];
+        if (KEEP && (e & kSkinTag)) continue;
+        const uint32_t j = e;
         abs32_body<DIM, FEAT, PST4>(I, axa, phif, rec.xa[j], rec.r1[j], (float)rec.phi[j], j, nf, C, A, S);
+        if (KEEP) S.nnb += 1;
       }
       abs32_flush(A, S);
     } else {
@@ -606,8 +608,8 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
 
 // A right-hand side from kept candidates: the same FP32 test as the search,
 // on the refreshed records, then the same body, one FP32 chunk sum per kept
-// chunk.
-template <int DIM, bool FEAT, bool PST4>
+// chunk.  ABS: the single-precision form's body.
+template <int DIM, bool FEAT, bool PST4, bool ABS = false>
 __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     k_pair_kept_mixed(Phys P, Grid g, MixedRec rec, uint32_t nf, Scalars *sc, Rates out,
                       uint32_t *__restrict__ cand, KeptLists kl) {
@@ -644,6 +646,8 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     }
     MixedChunk C;
     chunk_zero(C);
+    Abs32Chunk A;
+    if (ABS) abs32_zero(A);
     uint32_t en = cnt > 0 ? list[0][tid] : 0u;
     for (int k = 0; k < cnt; ++k) {
       const uint32_t j = en & ~kSkinTag;
@@ -651,10 +655,14 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
       if (k + 1 < cnt) en = list[k + 1][tid];
       const float dx = b.x - axa.x, dy = b.y - axa.y, dz = DIM == 3 ? b.z - axa.z : 0.f;
       if (dx * dx + dy * dy + dz * dz <= two_h2) {
-        mixed_body<DIM, FEAT, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], j, nf, C, S);
+        if constexpr (ABS)
+          abs32_body<DIM, FEAT, PST4>(I, axa, (float)phii, b, rec.r1[j], (float)rec.phi[j], j, nf, C, A, S);
+        else
+          mixed_body<DIM, FEAT, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], j, nf, C, S);
         S.nnb += 1;
       }
     }
+    if (ABS) abs32_flush(A, S);
     chunk_flush(C, S);
     S.ntest += (uint32_t)cnt;
   }
@@ -668,12 +676,27 @@ void launch_pair_mixed_inst(const Phys &P, const Grid &g, const MixedRec &rec, c
   dim3 gr(grid_for(nf)), bl(kBlock);
   const bool p4 = P.pst_n == 4.0;
   if (abs32) {
-    if (p4)
-      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
-                         out, cand, kl);
-    else
-      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
-                         out, cand, kl);
+    if (mode == kPairSearch) {
+      if (p4)
+        hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
+                           out, cand, kl);
+      else
+        hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf,
+                           sc, out, cand, kl);
+    } else if (mode == kPairSearchKeep) {
+      if (p4)
+        hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
+                           out, cand, kl);
+      else
+        hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
+                           out, cand, kl);
+    } else {
+      if (p4)
+        hipLaunchKernelGGL((k_pair_kept_mixed<DIM, FEAT, true, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
+      else
+        hipLaunchKernelGGL((k_pair_kept_mixed<DIM, FEAT, false, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand,
+                           kl);
+    }
   } else if (mode == kPairSearch) {
     if (p4)
       hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
@@ -701,7 +724,7 @@ hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, 
                              bool features, int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s,
                              bool abs32) {
   if (nf == 0) return hipSuccess;
-  if (mode != kPairSearch && (abs32 || !kent || !kcnt)) return hipErrorInvalidValue;
+  if (mode != kPairSearch && (!kent || !kcnt)) return hipErrorInvalidValue;
   KeptLists kl{kent, kcnt};
   if (P.dim == 2) {
     if (features)

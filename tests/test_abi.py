@@ -116,16 +116,16 @@ def test_body_motion_validation_and_workspace(L):
     assert lib.sph_workspace_bytes(C.byref(kept), nf, nd) == lib.sph_workspace_bytes(C.byref(plain), nf, nd)
 
 
-def test_single_precision_form_validates_without_kept_lists(L):
-    """SPH_FP32 is a valid precision; it has no pass from kept lists, so the
-    flag adds no workspace; an unknown precision is rejected."""
+def test_single_precision_form_validates_with_kept_lists(L):
+    """SPH_FP32 is a valid precision; its kept lists take the workspace of the
+    mixed path's; an unknown precision is rejected."""
     lib = L.lib()
     c = wl.tank2d()
     h = c["params"]["h"]
     q = L.params_from_dict(wl.with_params(c, precision="fp32", cell_size=2.1 * h, keep_lists=True)["params"])
     assert q.precision == L.SPH_FP32
     assert lib.sph_validate(C.byref(q)) == L.SPH_OK
-    r = L.params_from_dict(wl.with_params(c, precision="fp32", cell_size=2.1 * h)["params"])
+    r = L.params_from_dict(wl.with_params(c, precision="mixed", cell_size=2.1 * h, keep_lists=True)["params"])
     assert lib.sph_workspace_bytes(C.byref(q), 5000, 678) == lib.sph_workspace_bytes(C.byref(r), 5000, 678)
     q.precision = 3
     assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL

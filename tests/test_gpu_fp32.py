@@ -112,3 +112,26 @@ def test_fp32_trajectory_tracks_fp64(Sim):
     assert dp <= 1e-4
     # dt follows max |U| (rel. difference below 1e-4 of U_max / C0 per step)
     assert abs(s32.stats()["t"] - sd.stats()["t"]) <= 1e-9
+
+
+def test_fp32_kept_lists_match_rebuilding_path(Sim):
+    """The single-precision form with the second stages from kept lists: the
+    neighbour sets of a rebuild (counts and pair totals exact), fields equal
+    up to the grouping of the FP32 chunk sums."""
+    from test_gpu_keep import CASES_X
+    name, case = CASES_X[1]
+    case = wl.with_params(case, precision="fp32")
+    a = Sim(case)
+    b = Sim(wl.with_params(case, keep_lists=False, keep_across_steps=False))
+    a.step(10)
+    b.step(10)
+    st = a.stats()
+    assert st["n_kept"] + st["n_rebuilt"] == 20 and st["n_kept"] >= 10
+    f = case["kind"] == 0
+    assert np.array_equal(a.field("nnb")[f], b.field("nnb")[f])
+    assert st["pairs"] == b.stats()["pairs"]
+    L = max(case["params"]["domain_hi"]) - min(case["params"]["domain_lo"])
+    assert np.abs(a.field("x")[f] - b.field("x")[f]).max() <= 1e-9 * L
+    for name_ in ("u", "phi", "dudt", "dphidt"):
+        va, vb = a.field(name_)[f], b.field(name_)[f]
+        assert np.abs(va - vb).max() <= 1e-5 * max(np.abs(vb).max(), 1e-30), name_
