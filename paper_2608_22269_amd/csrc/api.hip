@@ -867,9 +867,19 @@ sph_status stage_update(sph_ctx *c, int stage) {
   const bool recs = c->kent && c->lists_valid && (stage == 1 || (c->p.flags & SPH_F_KEEP_ACROSS_STEPS));
   if (c->mixed)
     e = launch_stage_mixed(c->P, c->g, c->mcur, c->r, c->nf, c->sc, stage, c->s, recs ? &c->mrec : nullptr);
-  else
+  else {
+    // stage 1 writes the new state into the stage-0 arrays and the roles
+    // swap: the state of t^n becomes the stage-0 copy without a copy
+    if (stage == 1) {
+      for (int a = 0; a < 3; ++a) {
+        std::swap(c->cur.x[a], c->cur.x0[a]);
+        std::swap(c->cur.u[a], c->cur.u0[a]);
+      }
+      std::swap(c->cur.phi, c->cur.phi0);
+    }
     e = launch_stage_f64(c->P, c->cur, c->r, c->nf, c->sc, stage, c->s, recs ? c->rec0 : nullptr,
                          recs ? c->rec1 : nullptr, stage == 2 ? 1 : 0);
+  }
   c->umax_fresh = true;
   c->recs_fresh = recs;
   if (e == hipSuccess && c->kent) e = launch_disp_add(c->sc, stage, c->s);

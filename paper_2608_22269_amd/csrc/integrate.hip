@@ -151,8 +151,10 @@ hipError_t launch_advance_time(Scalars *sc, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ SSP-RK2, FP64
-// Stage 1: phi1 = phi + dt Dphi, U1 = U + dt a, x1 = x + dt (U + dU).
-// Stage 2: q = 1/2 q0 + 1/2 (q1 + dt rate(q1)) for phi, U and x.
+// Stage 1: phi1 = phi + dt Dphi, U1 = U + dt a, x1 = x + dt (U + dU), with
+// the state of t^n read from the stage-0 arrays (the caller swaps the state
+// and stage-0 arrays first, so t^n needs no copy) and stage 1 written to the
+// state arrays.  Stage 2: q = 1/2 q0 + 1/2 (q1 + dt rate(q1)) for phi, U, x.
 // Written without contraction, as the equations are printed.  The kernel
 // also folds max |U|^2 of the new state into sc->umax2_bits (reset by the
 // caller), checks the new phi and U for finiteness when asked, and writes the
@@ -169,15 +171,11 @@ __global__ void __launch_bounds__(256) k_stage_f64(Phys P, FluidF64 f, Rates r, 
   if (i < n) {
     const double dt = sc->dt;
     double xn[3] = {0.0, 0.0, 0.0}, un[3] = {0.0, 0.0, 0.0}, pn;
-    if (stage == 1) {
-      const double ph = f.phi[i];
-      f.phi0[i] = ph;
-      pn = ph + dt * r.dphi[i];
+    if (stage == 1) {  // the state of t^n is in the stage-0 arrays (the caller swapped them)
+      pn = f.phi0[i] + dt * r.dphi[i];
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        const double x = f.x[a][i], u = f.u[a][i];
-        f.x0[a][i] = x;
-        f.u0[a][i] = u;
+        const double x = f.x0[a][i], u = f.u0[a][i];
         un[a] = u + dt * r.acc[a][i];
         xn[a] = x + dt * (u + r.dus[a][i]);
       }

@@ -78,7 +78,8 @@ hipError_t launch_stage_time(Scalars *sc, int stage, hipStream_t s, int mode = 0
 hipError_t launch_disp_add(Scalars *sc, int stage, hipStream_t s);
 // clears sc->umax2_bits (before a kernel that folds max |U|^2 into it)
 hipError_t launch_reset_umax(Scalars *sc, hipStream_t s);
-// SSP-RK2 stage update (FP64); also max |U|^2 of the new state into
+// SSP-RK2 stage update (FP64; stage 1 reads t^n from the stage-0 arrays,
+// which the caller has swapped with the state arrays); also max |U|^2 of the new state into
 // sc->umax2_bits (reset here), a finiteness check of phi and U (check != 0)
 // and the neighbour records of the new state (rec0 != nullptr)
 hipError_t launch_stage_f64(const Phys &P, const FluidF64 &f, const Rates &r, int64_t nf, Scalars *sc, int stage,
