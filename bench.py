@@ -464,7 +464,7 @@ def main():
                                          "k_pair_mixed<3,false,true,true,false> (first-stage pass, FP32 body + FP64 sums)")
         if "kept_pass" in results["mixed"]:
             out["roofline_kept_mixed"] = roofline(results["mixed"], "pair_kept_mixed",
-                                                  "k_pair_kept_mixed<3,false,true> (second stage from the kept lists)",
+                                                  "k_pair_kept_mixed<3,false,true,false> (second stage from the kept lists)",
                                                   kept=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.dx)
