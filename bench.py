@@ -187,11 +187,25 @@ def cpu_baseline(dx):
     el = time.perf_counter() - t0
     f = sample["kind"] == 0
     pairs = float(r["nnb"][f].sum())
+    # one host core (the paper's CPU reference is a single core), on a
+    # narrower column
+    small = wl.slosh3d(dx=dx, tank=(0.05, 0.1, 0.56), depth=0.28)
+    oracle.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        r1 = oracle.eval_rates(small)
+        el1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(nthreads)
+    pairs1 = float(r1["nnb"][small["kind"] == 0].sum())
     return {
         "value": pairs / el, "unit": "pair-evals/s", "cores": int(nthreads), "kind": "oracle",
         "sample": (f"one right-hand side of a 0.2 x 0.1 x 0.56 m column of the sloshing tank at dx={dx} "
                    f"({sample['meta']['n_fluid']} fluid + {sample['meta']['n_dummy']} dummies, "
                    f"{pairs:.3e} ordered pairs) in {el:.2f} s"),
+        "single_core": {"value": pairs1 / el1, "unit": "pair-evals/s", "cores": 1,
+                        "sample": (f"one right-hand side of a 0.05 x 0.1 x 0.56 m column ({small['meta']['n_fluid']} "
+                                   f"fluid, {pairs1:.3e} ordered pairs) in {el1:.2f} s")},
     }
 
 
@@ -291,13 +305,86 @@ def dambreak_detection(spin, steps):
     return out
 
 
+def dambreak_probes(seconds, every=100):
+    """Pressure at probes on the downstream wall of the 3D dam break (x = 3.22
+    m, y = 0.5 m; z = 0.025, 0.1, 0.2, 0.4 m) from t = 0 to `seconds`, FP64
+    and mixed (all stabilisers, exact detection, cells of 1.01 h, second
+    stages from kept lists; the front reaches the wall near 0.55 s, and after
+    0.7 s particles pass through the wall layers): Shepard
+    interpolation of p = C0^2 (rho - rho0) over the fluid within 2h of each
+    probe, every `every` steps; the mixed series is interpolated to the FP64
+    times.  Reports the maximum and RMS difference per probe against the
+    FP64 series' largest pressure there."""
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    from paper_2608_22269_amd._lib import SphError
+    case = wl.dambreak3d(dx=0.01)
+    h = case["params"]["h"]
+    case = wl.with_params(case, cell_size=1.01 * h, keep_lists=True)
+    f = case["kind"] == 0
+    probes = np.array([[3.22, 0.5, z] for z in (0.025, 0.1, 0.2, 0.4)])
+    alpha = 21.0 / (16.0 * np.pi * h ** 3)
+
+    def probe_p(sim):
+        x = sim.field("x")[f]
+        p = sim.field("p")[f]
+        V = sim.field("mass")[f] / sim.field("rho")[f]
+        out = []
+        for q in probes:
+            d = np.sqrt(((x - q) ** 2).sum(1)) / h
+            sel = d < 2.0
+            w = alpha * (1.0 - 0.5 * d[sel]) ** 4 * (2.0 * d[sel] + 1.0) * V[sel]
+            out.append(float((w * p[sel]).sum() / w.sum()) if w.sum() > 0 else 0.0)
+        return out
+
+    series, stops = {}, {}
+    t0 = time.time()
+    for prec in ("fp64", "mixed"):
+        sim = Simulation(wl.with_params(case, precision=prec))
+        ts, ps = [], []
+        try:
+            while True:
+                sim.step(every)
+                t, p = sim.stats()["t"], probe_p(sim)
+                ts.append(t)
+                ps.append(p)
+                if t >= seconds:
+                    break
+        except SphError as e:  # a device error ends the series (reported)
+            stops[prec] = str(e)
+        series[prec] = (np.array(ts), np.array(ps))
+        sim.close()
+        log(f"dam break probes {prec}: {len(ts)} records to t = {ts[-1]:.3f} s {stops.get(prec, '')}")
+    t64, p64 = series["fp64"]
+    tm, pm = series["mixed"]
+    keep = t64 <= tm[-1]
+    pmi = np.stack([np.interp(t64[keep], tm, pm[:, k]) for k in range(len(probes))], axis=1)
+    diff = pmi - p64[keep]
+    scale = np.maximum(np.abs(p64).max(axis=0), 1e-30)
+    # the same over moving averages of 5 records (500 steps): impact spikes
+    # are not reproducible pointwise between the two paths
+    ker = np.ones(5) / 5.0
+    sm = lambda a: np.stack([np.convolve(a[:, k], ker, mode="valid") for k in range(a.shape[1])], axis=1)
+    dsm = sm(pmi) - sm(p64[keep])
+    return {
+        "workload": (f"3D dam break dx=0.01, {int(f.sum())} fluid, R = 1.01 h, t = 0..{t64[-1]:.3f} s, "
+                     f"every {every} steps"),
+        "probes_xyz": probes.tolist(), "t": t64.tolist(), "p_fp64": p64.tolist(), "p_mixed": pm.tolist(),
+        "t_mixed": tm.tolist(), "max_abs_p_fp64": scale.tolist(),
+        "max_diff_over_max_p": (np.abs(diff).max(axis=0) / scale).tolist(),
+        "rms_diff_over_max_p": (np.sqrt((diff ** 2).mean(axis=0)) / scale).tolist(),
+        "rms_diff_of_5_record_means_over_max_p": (np.sqrt((dsm ** 2).mean(axis=0)) / scale).tolist(),
+        "stopped": stops, "seconds": time.time() - t0,
+    }
+
+
 def bump_history(steps, every):
     """2D water layer 2.0 x 0.5 m over a Gaussian bump (amplitude 0.1 m, sigma
     0.1 m), dx = 0.002 (243.7k fluid), hydrostatic start: fluid max |U| every
     `every` steps on the FP64 and the mixed path, with the printed scheme
     (no stabilisers) and with the tensile-instability switch on.  A run that
-    stops on a device error (the free-surface mode's blow-up) reports the step
-    and the error."""
+    blows up (the free-surface mode) stops at the first record above 1 m/s or
+    on a device error, and reports it."""
     import workloads as wl
     from paper_2608_22269_amd import Simulation
     from paper_2608_22269_amd._lib import SphError
@@ -314,6 +401,9 @@ def bump_history(steps, every):
                     sim.step(every)
                     u = sim.field("u")[f]
                     hist.append([k + every, float(np.sqrt((u * u).sum(1)).max())])
+                    if hist[-1][1] > 1.0:  # the blow-up: later steps only clump particles
+                        err = "stopped: max |U| above 1 m/s"
+                        break
             except SphError as e:
                 err = str(e)
             out[f"{label}/{prec}"] = {"max_u": hist, "error": err, "seconds": time.time() - t0,
@@ -367,6 +457,8 @@ def main():
                          "fp32: the single-precision form")
     ap.add_argument("--dambreak-spin", type=int, default=4000,
                     help="steps of the 3D dam break before the exact / learned detection comparison (0: skip)")
+    ap.add_argument("--probe-seconds", type=float, default=0.7,
+                    help="simulated seconds of the 3D dam-break wall-pressure comparison, FP64 vs mixed (0: skip)")
     ap.add_argument("--bump-steps", type=int, default=10000,
                     help="steps of the 2D Gaussian-bump spurious-velocity history (0: skip)")
     ap.add_argument("--body-dx", type=float, default=0.005,
@@ -490,6 +582,8 @@ def main():
     out["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:
         out["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)
+    if args.probe_seconds > 0:
+        out["dambreak_wall_pressure"] = dambreak_probes(args.probe_seconds)
     out["spurious_u_tank2d_100steps"] = {k: spurious_velocity(k) for k in ("fp64", "mixed", "fp32")}
     if args.bump_steps > 0:
         out["spurious_u_bump2d"] = bump_history(args.bump_steps, 500)
