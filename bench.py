@@ -378,6 +378,42 @@ def dambreak_probes(seconds, every=100):
     }
 
 
+def hydrostatic_l2(steps, every):
+    """The paper's hydrostatic cases (Sec. 4): a 1 x 1 m container with 1 m
+    of water over a rectangular, triangular or Gaussian bottom bump 0.5 m
+    high and 0.4 m wide (Gaussian: sigma = 0.1 m), dx = 0.01, the scheme
+    without stabilisers, FP64: the paper's L2 velocity error sqrt(sum |U|^2
+    V / sum V) over the fluid every `every` steps.  A run stops at the first
+    record with max |U| above 1 m/s (the free-surface mode's blow-up) or on a
+    device error."""
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    from paper_2608_22269_amd._lib import SphError
+    out = {}
+    for shape in ("rect", "tri", "gauss"):
+        case = wl.bump2d(shape, dx=0.01, width=1.0, depth=1.0, amp=0.5, bump_width=0.4, sigma=0.1)
+        f = case["kind"] == 0
+        sim = Simulation(case)
+        hist, err = [], None
+        try:
+            for k in range(0, steps, every):
+                sim.step(every)
+                u = sim.field("u")[f]
+                V = sim.field("mass")[f] / sim.field("rho")[f]
+                u2 = (u * u).sum(1)
+                hist.append([k + every, sim.stats()["t"], float(np.sqrt((u2 * V).sum() / V.sum())),
+                             float(np.sqrt(u2.max()))])
+                if hist[-1][3] > 1.0:
+                    err = "stopped: max |U| above 1 m/s"
+                    break
+        except SphError as e:
+            err = str(e)
+        sim.close()
+        out[shape] = {"n_fluid": int(f.sum()), "step_t_l2_maxu": hist, "error": err}
+        log(f"hydrostatic {shape}: first {hist[0] if hist else None}, last {hist[-1] if hist else None} {err or ''}")
+    return out
+
+
 def bump_history(steps, every):
     """2D water layer 2.0 x 0.5 m over a Gaussian bump (amplitude 0.1 m, sigma
     0.1 m), dx = 0.002 (243.7k fluid), hydrostatic start: fluid max |U| every
@@ -459,6 +495,8 @@ def main():
                     help="steps of the 3D dam break before the exact / learned detection comparison (0: skip)")
     ap.add_argument("--probe-seconds", type=float, default=0.7,
                     help="simulated seconds of the 3D dam-break wall-pressure comparison, FP64 vs mixed (0: skip)")
+    ap.add_argument("--hydro-steps", type=int, default=2000,
+                    help="steps of the paper's three hydrostatic cases (L2 velocity error; 0: skip)")
     ap.add_argument("--bump-steps", type=int, default=10000,
                     help="steps of the 2D Gaussian-bump spurious-velocity history (0: skip)")
     ap.add_argument("--body-dx", type=float, default=0.005,
@@ -587,6 +625,8 @@ def main():
     out["spurious_u_tank2d_100steps"] = {k: spurious_velocity(k) for k in ("fp64", "mixed", "fp32")}
     if args.bump_steps > 0:
         out["spurious_u_bump2d"] = bump_history(args.bump_steps, 500)
+    if args.hydro_steps > 0:
+        out["hydrostatic_l2_paper_cases"] = hydrostatic_l2(args.hydro_steps, 50)
     print(json.dumps(out), flush=True)
 
 
