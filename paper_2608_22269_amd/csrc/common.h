@@ -427,6 +427,53 @@ __device__ __forceinline__ uint32_t walker_key(RowWalker &w, const Grid &g, int 
   return w.tbase + (uint32_t)(x + (y - ty * kTileY) * g.N[0] + (z - tz * kTileZ) * g.N[0] * kTileY);
 }
 
+// Window of row r of the walk (raster order): the sort keys [k0, k1) of the
+// row's cells within the walk's reach, and the row's (y, z) cell; false if
+// the row lies outside the grid or beyond the reach.
+template <int DIM>
+__device__ __forceinline__ bool walker_row(RowWalker &w, const Grid &g, int r, uint32_t &k0, uint32_t &k1, int &iy,
+                                           int &iz) {
+  const int side = 2 * g.reach + 1;
+  const int dy = (DIM == 3 ? r % side : r) - g.reach;
+  const int dz = DIM == 3 ? r / side - g.reach : 0;
+  iy = w.cy + dy;
+  iz = w.cz + dz;
+  if (iy < 0 || iy >= g.N[1]) return false;
+  if (DIM == 3 && (iz < 0 || iz >= g.N[2])) return false;
+  // distance (cells) from the particle to the row's (y, z) slab, shortened
+  float ey = dy > 0 ? (float)dy - w.uy : (dy < 0 ? w.uy - (float)(dy + 1) : 0.0f);
+  float ez = DIM == 3 ? (dz > 0 ? (float)dz - w.uz : (dz < 0 ? w.uz - (float)(dz + 1) : 0.0f)) : 0.0f;
+  ey = fmaxf(0.0f, ey - kWalkSlack);
+  ez = fmaxf(0.0f, ez - kWalkSlack);
+  const float rem = w.rr2 - ey * ey - ez * ez;
+  if (rem < 0.0f) return false;
+  const float reach = __builtin_amdgcn_sqrtf(rem) + kWalkSlack;  // hardware sqrt (~1 ulp), covered by the slack
+  int x0 = w.cx + (int)floorf(w.ux - reach);
+  int x1 = w.cx + (int)floorf(w.ux + reach);
+  x0 = max(x0, max(w.cx - g.reach, 0));
+  x1 = min(x1, min(w.cx + g.reach, g.N[0] - 1));
+  if (x0 > x1) return false;
+  k0 = walker_key(w, g, x0, iy, iz);
+  k1 = k0 + (uint32_t)(x1 - x0) + 1u;  // x-row cells are consecutive keys
+  return true;
+}
+
+// Fluid runs [lo[r], hi[r]) of all NR rows of the walk (NR = (2 reach +
+// 1)^(d-1)), the cell-start loads of every row issued together rather than
+// one row after the other (empty runs for rows out of reach).
+template <int DIM, int NR>
+__device__ __forceinline__ void walker_fluid_runs(RowWalker &w, const Grid &g, const uint32_t *__restrict__ cs_f,
+                                                  uint32_t (&lo)[NR], uint32_t (&hi)[NR]) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    uint32_t k0 = 0u, k1 = 0u;
+    int iy, iz;
+    const bool ok = walker_row<DIM>(w, g, r, k0, k1, iy, iz);
+    lo[r] = ok ? cs_f[k0] : 0u;
+    hi[r] = ok ? cs_f[k1] : 0u;
+  }
+}
+
 // Advances to the next non-empty run; returns false when the walk is over.
 // cs_f / cs_d: start index (per sort key, nkey + 1 entries) of the fluid and
 // dummy records; dummy records live at index nf + k.
@@ -444,28 +491,10 @@ __device__ __forceinline__ bool walker_next(RowWalker &w, const Grid &g, const u
       continue;
     }
     if (w.row >= w.nrows) return false;
-    const int side = 2 * g.reach + 1;
     const int r = w.row++;
-    const int dy = (DIM == 3 ? r % side : r) - g.reach;
-    const int dz = DIM == 3 ? r / side - g.reach : 0;
-    const int iy = w.cy + dy, iz = w.cz + dz;
-    if (iy < 0 || iy >= g.N[1]) continue;
-    if (DIM == 3 && (iz < 0 || iz >= g.N[2])) continue;
-    // distance (cells) from the particle to the row's (y, z) slab, shortened
-    float ey = dy > 0 ? (float)dy - w.uy : (dy < 0 ? w.uy - (float)(dy + 1) : 0.0f);
-    float ez = DIM == 3 ? (dz > 0 ? (float)dz - w.uz : (dz < 0 ? w.uz - (float)(dz + 1) : 0.0f)) : 0.0f;
-    ey = fmaxf(0.0f, ey - kWalkSlack);
-    ez = fmaxf(0.0f, ez - kWalkSlack);
-    const float rem = w.rr2 - ey * ey - ez * ez;
-    if (rem < 0.0f) continue;
-    const float reach = __builtin_amdgcn_sqrtf(rem) + kWalkSlack;  // hardware sqrt (~1 ulp), covered by the slack
-    int x0 = w.cx + (int)floorf(w.ux - reach);
-    int x1 = w.cx + (int)floorf(w.ux + reach);
-    x0 = max(x0, max(w.cx - g.reach, 0));
-    x1 = min(x1, min(w.cx + g.reach, g.N[0] - 1));
-    if (x0 > x1) continue;
-    const uint32_t k0 = walker_key(w, g, x0, iy, iz);
-    const uint32_t k1 = k0 + (uint32_t)(x1 - x0) + 1u;  // x-row cells are consecutive keys
+    uint32_t k0, k1;
+    int iy, iz;
+    if (!walker_row<DIM>(w, g, r, k0, k1, iy, iz)) continue;
     const uint32_t flo = cs_f[k0], fhi = cs_f[k1];
     w.dlo = nf + cs_d[k0];
     w.dhi = nf + cs_d[k1];

@@ -207,9 +207,8 @@ __global__ void __launch_bounds__(256) k_mirror_mixed(Phys P, Grid g, Dummies d,
   int64_t best = -1;
   uint32_t best_id = 0;
   float best_r2 = 0.f;
-  while (walker_next<DIM>(w, g, cs_f, cs_f, nf)) {
-    if (w.cur >= nf) continue;
-    for (uint32_t j = w.cur; j < w.end; ++j) {
+  auto test_run = [&](uint32_t a, uint32_t e) {
+    for (uint32_t j = a; j < e; ++j) {
       float4 b = rec.xa[j];
       float dxv = b.x - xf, dyv = b.y - yf, dzv = DIM == 3 ? b.z - zf : 0.f;
       float r2 = dxv * dxv + dyv * dyv + dzv * dzv;
@@ -222,6 +221,17 @@ __global__ void __launch_bounds__(256) k_mirror_mixed(Phys P, Grid g, Dummies d,
         }
       }
     }
+  };
+  // fluid runs, as in the FP64 mirror
+  if (g.reach == 2) {
+    constexpr int NR = DIM == 3 ? 25 : 5;
+    uint32_t lo[NR], hi[NR];
+    walker_fluid_runs<DIM, NR>(w, g, cs_f, lo, hi);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) test_run(lo[r], hi[r]);
+  } else {
+    while (walker_next<DIM>(w, g, cs_f, cs_f, nf))
+      if (w.cur < nf) test_run(w.cur, w.end);
   }
   d.src[k] = (int32_t)best;
   // static part of the record: cell and offset of the dummy

@@ -68,11 +68,8 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
   int64_t best = -1;
   uint32_t best_id = 0;
   double best_r2 = 0.0;
-  // fluid runs only (the dummy cell-start array is not needed: pass cs_f twice
-  // and stop at the first dummy run)
-  while (walker_next<DIM>(w, g, cs_f, cs_f, nf)) {
-    if (w.cur >= nf) continue;
-    for (uint32_t j = w.cur; j < w.end; ++j) {
+  auto test_run = [&](uint32_t a, uint32_t e) {
+    for (uint32_t j = a; j < e; ++j) {
       double4 b = rec0[j];
       double r2 = dist2_exact<DIM>(b.x - xd, b.y - yd, b.z - zd);
       if (r2 <= P.two_h2) {
@@ -84,6 +81,19 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
         }
       }
     }
+  };
+  // fluid runs only; at reach 2 the cell starts of all rows are loaded
+  // together (the walk is bound by the latency of its row-by-row loads),
+  // otherwise row by row (pass cs_f twice and skip the dummy runs)
+  if (g.reach == 2) {
+    constexpr int NR = DIM == 3 ? 25 : 5;
+    uint32_t lo[NR], hi[NR];
+    walker_fluid_runs<DIM, NR>(w, g, cs_f, lo, hi);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) test_run(lo[r], hi[r]);
+  } else {
+    while (walker_next<DIM>(w, g, cs_f, cs_f, nf))
+      if (w.cur < nf) test_run(w.cur, w.end);
   }
   d.src[k] = (int32_t)best;
   if (best < 0) {
