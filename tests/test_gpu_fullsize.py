@@ -9,7 +9,9 @@ oracle at the state the mixed path stores) to its 2e-5 bar.
 The 2D Gaussian-bump layer and the 3D dam break are small enough for the
 oracle to evaluate every particle (the dam break also over two steps with
 kept lists); the 3D ditching-style tank with its moving body (3.82M) is
-compared on sampled rows around the body and elsewhere.
+compared on sampled rows around the body and elsewhere; a 140,000-particle
+sloshing tank runs 50 steps with lists kept across steps against the
+oracle's 50 steps.
 """
 import numpy as np
 import pytest
@@ -195,4 +197,29 @@ def test_moving_body_full_size_sampled(Sim):
     nnb = _compare_rows(sim, case, ref, rows, TOL, TOL)
     assert np.array_equal(nnb, ref["nnb"][rows])
     assert np.array_equal(sim.field("x")[b], case["x"][b] + D)
+    sim.close()
+
+
+def test_sloshing_tank_50_steps_lists_across_steps(Sim):
+    """50 steps of a forced sloshing tank (dx = 0.01, 140,000 fluid, seeded
+    velocities, forcing phase t = 0.37 s) with candidate lists kept across
+    steps (cells of 1.03 h) against the oracle's 50 steps, which search
+    afresh at every right-hand side."""
+    case = wl.slosh3d(dx=0.01)
+    case = wl.with_params(case, cell_size=1.03 * case["params"]["h"], keep_lists=True, keep_across_steps=True)
+    case = wl.random_velocity(wl.jitter(case, 0.1, 61), 0.05, 62)
+    case["t"] = 0.37
+    sim = Sim(case)
+    sim.step(50)
+    st = sim.stats()
+    assert st["n_kept"] >= 50
+    ref = oracle.step(case, 50)
+    f = case["kind"] == 0
+    L = max(case["params"]["domain_hi"]) - min(case["params"]["domain_lo"])
+    ex = np.abs(sim.field("x")[f] - ref["x"][f]).max() / L
+    eu = np.abs(sim.field("u")[f] - ref["u"][f]).max() / np.abs(ref["u"][f]).max()
+    ep = np.abs(sim.field("phi")[f] - ref["phi"][f]).max() / np.abs(ref["phi"][f]).max()
+    print(f"kept {st['n_kept']} rebuilt {st['n_rebuilt']}: x {ex:.2e} u {eu:.2e} phi {ep:.2e}")
+    assert ex <= 1e-12 and eu <= 1e-10 and ep <= 1e-11
+    assert abs(st["t"] - ref["t"]) <= 1e-14
     sim.close()
