@@ -10,16 +10,19 @@ sorts the particles into cells (hash, counting sort, reorder) and keeps its
 candidate lists, the second runs from them (cells of 1.01 h leave room for
 the lists' skin; --keep-cell 0 sorts and searches at both right-hand sides).
 
-Prints one JSON line (metric, value = pair evaluations per second of the
-headline path, ms/step, rooflines of the pair passes, CPU oracle baseline,
-the mixed, learned and single-precision paths, the lists kept across steps, a body moving
-along the ditching velocity history, MLP inference, spurious velocities).
+Prints one compact JSON line on stdout (a few KB: metric, value = pair
+evaluations per second of the FP64 path, ms/step, the dominant kernel's
+roofline, the CPU oracle baseline, one summary per path -- mixed, learned,
+single precision -- and per side measurement); the full record (histories,
+probe traces, per-kernel times) goes to the file given by --detail.  Progress
+goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -203,22 +206,29 @@ def cpu_baseline(dx):
         "sample": (f"one right-hand side of a 0.2 x 0.1 x 0.56 m column of the sloshing tank at dx={dx} "
                    f"({sample['meta']['n_fluid']} fluid + {sample['meta']['n_dummy']} dummies, "
                    f"{pairs:.3e} ordered pairs) in {el:.2f} s"),
+        "sample_short": (f"1 RHS of a 0.2x0.1x0.56 m column of the tank, {sample['meta']['n_fluid']} fluid, "
+                         f"{el:.1f} s"),
         "single_core": {"value": pairs1 / el1, "unit": "pair-evals/s", "cores": 1,
                         "sample": (f"one right-hand side of a 0.05 x 0.1 x 0.56 m column ({small['meta']['n_fluid']} "
                                    f"fluid, {pairs1:.3e} ordered pairs) in {el1:.2f} s")},
     }
 
 
-def spurious_velocity(precision):
-    """Hydrostatic 2D tank (5,000 fluid): max |U| after 100 steps."""
+def spurious_velocity(precision, steps):
+    """Hydrostatic 2D tank (5,000 fluid, the scheme without stabilisers):
+    fluid max |U| every 50 steps up to `steps`."""
     import workloads as wl
     from paper_2608_22269_amd import Simulation
     case = wl.tank2d(precision=precision)
+    f = case["kind"] == 0
     sim = Simulation(case)
-    sim.step(100)
-    u = sim.field("u")[case["kind"] == 0]
+    out = {}
+    for k in range(50, steps + 1, 50):
+        sim.step(50)
+        out[str(k)] = float(np.abs(sim.field("u")[f]).max())
     sim.close()
-    return float(np.abs(u).max())
+    log(f"tank2d {precision}: max |U| {out}")
+    return out
 
 
 def mlp_inference(n, reps=5):
@@ -378,20 +388,21 @@ def dambreak_probes(seconds, every=100):
     }
 
 
-def hydrostatic_l2(steps, every):
-    """The paper's hydrostatic cases (Sec. 4): a 1 x 1 m container with 1 m
-    of water over a rectangular, triangular or Gaussian bottom bump 0.5 m
-    high and 0.4 m wide (Gaussian: sigma = 0.1 m), dx = 0.01, the scheme
-    without stabilisers, FP64: the paper's L2 velocity error sqrt(sum |U|^2
-    V / sum V) over the fluid every `every` steps.  A run stops at the first
-    record with max |U| above 1 m/s (the free-surface mode's blow-up) or on a
-    device error."""
+def hydrostatic_l2(steps, every, c0=30.0, h_factor=1.5):
+    """The paper's hydrostatic cases (Sec. 4) with the paper's constants (C0 =
+    30 m/s, h = 1.5 dx): a 1 x 1 m container with 1 m of water over a
+    rectangular, triangular or Gaussian bottom bump 0.5 m high and 0.4 m wide
+    (Gaussian: sigma = 0.1 m), dx = 0.01, the scheme without stabilisers,
+    FP64: the paper's L2 velocity error sqrt(sum |U|^2 V / sum V) over the
+    fluid every `every` steps.  A run stops at the first record with max |U|
+    above 1 m/s (the free-surface mode's blow-up) or on a device error."""
     import workloads as wl
     from paper_2608_22269_amd import Simulation
     from paper_2608_22269_amd._lib import SphError
-    out = {}
+    out = {"_constants": {"c0": c0, "h_over_dx": h_factor, "dx": 0.01}}
     for shape in ("rect", "tri", "gauss"):
-        case = wl.bump2d(shape, dx=0.01, width=1.0, depth=1.0, amp=0.5, bump_width=0.4, sigma=0.1)
+        case = wl.bump2d(shape, dx=0.01, width=1.0, depth=1.0, amp=0.5, bump_width=0.4, sigma=0.1, c0=c0,
+                         h_factor=h_factor)
         f = case["kind"] == 0
         sim = Simulation(case)
         hist, err = [], None
@@ -469,6 +480,143 @@ def moving_body(dx, steps, warmup):
     return res
 
 
+def _sig(v, n=4):
+    """v rounded to n significant digits (non-floats pass through; non-finite
+    floats become strings so that the line stays strict JSON)."""
+    if isinstance(v, float):
+        if not math.isfinite(v):
+            return str(v)
+        return float(f"{v:.{n}g}")
+    return v
+
+
+def _short(s, n=90):
+    return s if not isinstance(s, str) or len(s) <= n else s[:n - 3] + "..."
+
+
+def _roof_summary(r, full=True):
+    if r is None:
+        return None
+    out = {k: _sig(r.get(k)) for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+    out["kernel"] = r["kernel"] if full else r["kernel"].split(" ")[0]
+    out["launch_ms"] = _sig(r["pair_pass_ms"])
+    out["pairs_per_launch"] = _sig(r["pairs_per_launch"])
+    out["candidate_tests_per_launch"] = _sig(r["tests_per_launch"])
+    if full:
+        out["flop_per_pair"] = FLOP_PER_PAIR_3D
+        out["tflops_with_tests"] = _sig(r["tflops_with_tests"])
+    if "valu_issue" in r:
+        out["valu_issue_frac"] = _sig(r["valu_issue"]["frac"], 3)
+    if "ta_busy" in r:
+        out["ta_busy_frac"] = _sig(r["ta_busy"]["frac"], 3)
+    return out
+
+
+def _path_summary(r):
+    out = {"ms_per_step": _sig(r["ms_per_step"]), "pair_evals_per_s": _sig(r["pair_evals_per_s"]),
+           "pair_pass_ms": _sig(r["pair_pass_ms"])}
+    if "kept_pass" in r:
+        out["kept_pass_ms"] = _sig(r["kept_pass"]["ms"])
+    kms = r.get("kernel_ms_per_step", {})
+    if "fs_detect" in kms:
+        out["fs_detect_ms"] = _sig(kms["fs_detect"], 3)
+    if "misclassification" in r:
+        m = r["misclassification"]
+        out["fs_candidates"] = m["candidates"]
+        out["decided_by_mlp"] = m["decided_by_mlp"]
+        out["misclassified"] = m["misclassified"]
+        out["misclassified_frac"] = _sig(m["rate_of_candidates"], 3)
+    return out
+
+
+def compact_line(d):
+    """The one JSON line bench.py prints: the headline with its roofline and
+    CPU baseline, then one short summary per path and per side measurement.
+    The full record (histories, probe traces, per-kernel times) goes to the
+    detail file named in the line."""
+    head = d["paths"]["fp64"]
+    line = {
+        "metric": METRIC, "value": _sig(head["pair_evals_per_s"]), "unit": "pair-evals/s", "n_gpus": 1,
+        "steps": d["steps"], "warmup": d["warmup"], "ms_per_step": _sig(head["ms_per_step"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": d["data"], "config": d["config"], "roofline": _roof_summary(d["roofline"]),
+    }
+    if d.get("cpu_baseline"):
+        c = d["cpu_baseline"]
+        line["cpu_baseline"] = {"value": _sig(c["value"]), "unit": c["unit"], "cores": c["cores"], "kind": c["kind"],
+                                "sample": c["sample_short"], "cpu_model": c["cpu_model"],
+                                "single_core_value": _sig(c["single_core"]["value"])}
+    line["paths"] = {k: _path_summary(v) for k, v in d["paths"].items()}
+    p = d["paths"]
+    ratios = {}
+    for k in ("mixed", "mixed_learned", "fp32"):
+        if k in p:
+            ratios[f"{k}_over_fp64"] = _sig(p["fp64"]["ms_per_step"] / p[k]["ms_per_step"], 3)
+    if "mixed" in p and "mixed_learned" in p:
+        ratios["mixed_learned_over_mixed"] = _sig(p["mixed"]["ms_per_step"] / p["mixed_learned"]["ms_per_step"], 3)
+    line["step_rate_ratios"] = ratios
+    if d.get("at_rest"):
+        line["at_rest_ms_per_step"] = {k: _sig(v["ms_per_step"]) for k, v in d["at_rest"].items()}
+    if d.get("roofline_kept"):
+        line["roofline_kept_pass"] = _roof_summary(d["roofline_kept"], full=False)
+    if d.get("spurious_u_tank2d"):
+        line["spurious_u_tank2d_max"] = {k: {s: _sig(u, 2) for s, u in v.items() if s in ("100", "200")}
+                                         for k, v in d["spurious_u_tank2d"].items()}
+    if d.get("hydrostatic_l2_paper_cases"):
+        hs = {}
+        for shape, r in d["hydrostatic_l2_paper_cases"].items():
+            if shape.startswith("_"):
+                continue
+            hist = r["step_t_l2_maxu"]
+            below = [s for s, _, l2, _ in hist if l2 <= 1e-12]
+            at = {int(s): _sig(l2, 2) for s, _, l2, _ in hist if int(s) in (100, 200)}
+            hs[shape] = {"l2_at": at, "last_step_below_1e-12": max(below) if below else 0,
+                         "stop": _short(r["error"], 40)}
+        hs["constants"] = d["hydrostatic_l2_paper_cases"].get("_constants")
+        line["hydrostatic_paper_cases"] = hs
+    if d.get("spurious_u_bump2d"):
+        line["bump2d_last_step_max_u"] = {k: [v["max_u"][-1][0], _sig(v["max_u"][-1][1], 2)] if v["max_u"] else None
+                                          for k, v in d["spurious_u_bump2d"].items()}
+    if d.get("keep_across_steps"):
+        k = d["keep_across_steps"]
+        line["keep_across_steps_ms_per_step"] = {n: _sig(k[n]["ms_per_step"]) for n in
+                                                 ("from_rest", "moving", "moving_within_step") if n in k}
+    if d.get("moving_body"):
+        b = d["moving_body"]
+        line["moving_body"] = {"n_fluid": b["n_fluid"], "fp64_ms_per_step": _sig(b["fp64"]["ms_per_step"]),
+                               "mixed_ms_per_step": _sig(b["mixed"]["ms_per_step"]),
+                               "motion_cost_ms_per_step": _sig(b["motion_cost_ms_per_step"], 3)}
+    if d.get("mlp_inference_17_5M"):
+        m = d["mlp_inference_17_5M"]
+        line["mlp_inference"] = {"rows": m["rows"], "ms_per_call": _sig(m["ms_per_call"]),
+                                 "hbm_frac": _sig(m["hbm_frac"], 3)}
+    if d.get("dambreak_detection"):
+        r = d["dambreak_detection"]
+        ln = r["learned"]
+        line["dambreak_detection"] = {
+            "exact_ms_per_step": _sig(r["exact"]["ms_per_step"]), "learned_ms_per_step": _sig(ln["ms_per_step"]),
+            "candidates": ln["misclassification"]["candidates"],
+            "misclassified": ln["misclassification"]["misclassified"]}
+    if d.get("dambreak_wall_pressure"):
+        r = d["dambreak_wall_pressure"]
+        line["dambreak_wall_pressure"] = {"t_end": _sig(r["t"][-1], 3) if r["t"] else None,
+                                          "rms_diff_over_max_p": [_sig(v, 2) for v in r["rms_diff_over_max_p"]],
+                                          "stopped": {k: _short(v, 60) for k, v in r["stopped"].items()}}
+    line["detail"] = d.get("detail_path")
+    return line
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -481,7 +629,12 @@ def main():
     ap.add_argument("--keep-cell", type=float, default=1.01,
                     help="cell size in units of h when the first stage's candidate lists serve the second (room "
                          "for a skin of (2 x keep-cell - 2) h); 0: no kept lists, cells of --cell h")
+    ap.add_argument("--state", choices=("moving", "rest"), default="moving",
+                    help="state the paths are timed on: 'moving' = the lattice jittered by N(0, (0.05 dx)^2) "
+                         "with seeded velocities N(0, 0.05^2) m/s per component (irregular neighbour lists, "
+                         "particles moving through the lists' skin); 'rest' = the hydrostatic lattice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-at-rest", action="store_true", help="skip the FP64 and learned runs at rest")
     ap.add_argument("--no-across-steps", action="store_true",
                     help="skip the runs with the candidate lists kept across steps")
     ap.add_argument("--across-cell", type=float, default=1.03,
@@ -495,14 +648,20 @@ def main():
                     help="steps of the 3D dam break before the exact / learned detection comparison (0: skip)")
     ap.add_argument("--probe-seconds", type=float, default=0.7,
                     help="simulated seconds of the 3D dam-break wall-pressure comparison, FP64 vs mixed (0: skip)")
-    ap.add_argument("--hydro-steps", type=int, default=2000,
+    ap.add_argument("--hydro-steps", type=int, default=1000,
                     help="steps of the paper's three hydrostatic cases (L2 velocity error; 0: skip)")
+    ap.add_argument("--tank-steps", type=int, default=200,
+                    help="steps of the 2D hydrostatic tank's spurious-velocity check (0: skip)")
     ap.add_argument("--bump-steps", type=int, default=10000,
                     help="steps of the 2D Gaussian-bump spurious-velocity history (0: skip)")
     ap.add_argument("--body-dx", type=float, default=0.005,
                     help="particle spacing of the 3D moving-body run (3.82M fluid at 0.005; 0: skip)")
+    ap.add_argument("--mlp", action=argparse.BooleanOptionalAction, default=True,
+                    help="standalone BF16 MLP inference over as many rows as the tank has fluid particles")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file that receives the full record (histories, traces, per-kernel times)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (slab decomposition is designed, "
@@ -525,39 +684,52 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read + 1 GiB written")
         del src_t, dst_t
-    results = {}
     # every path keeps the first stage's candidate lists for the second (cells
     # of keep_cell h, room for the skin) unless --keep-cell 0
-    run_case = case if args.keep_cell <= 0 else wl.with_params(case, cell_size=args.keep_cell * h, keep_lists=True)
+    rest_case = case if args.keep_cell <= 0 else wl.with_params(case, cell_size=args.keep_cell * h, keep_lists=True)
+    run_case = rest_case
+    if args.state == "moving":
+        run_case = wl.random_velocity(wl.jitter(rest_case, 0.05, seed=11), 0.05, seed=12)
+    state_desc = ("lattice jittered by 0.05 dx, velocities 0.05 m/s rms per component (seeded)"
+                  if args.state == "moving" else "hydrostatic lattice at rest")
+    d = {"steps": args.steps, "warmup": args.warmup, "paths": {}}
+    clf = load_classifier()
     for path in args.paths.split(","):
         if path == "fp64":
-            results["fp64"] = run_path(run_case, "fp64", args.steps, args.warmup)
+            d["paths"]["fp64"] = run_path(run_case, "fp64", args.steps, args.warmup)
         elif path == "mixed":
-            results["mixed"] = run_path(wl.with_params(run_case, precision="mixed"), "mixed", args.steps, args.warmup)
+            d["paths"]["mixed"] = run_path(wl.with_params(run_case, precision="mixed"), "mixed", args.steps,
+                                           args.warmup)
         elif path == "fp32":
-            results["fp32"] = run_path(wl.with_params(run_case, precision="fp32"), "fp32", args.steps, args.warmup)
+            d["paths"]["fp32"] = run_path(wl.with_params(run_case, precision="fp32"), "fp32", args.steps, args.warmup)
         elif path == "mixed_learned":
-            results["mixed_learned"] = run_path(wl.with_params(run_case, precision="mixed", fs_mode="learned"),
-                                                "mixed_learned", args.steps, args.warmup, clf=load_classifier())
+            d["paths"]["mixed_learned"] = run_path(wl.with_params(run_case, precision="mixed", fs_mode="learned"),
+                                                   "mixed_learned", args.steps, args.warmup, clf=clf)
         else:
             raise SystemExit(f"unknown path {path}")
-    head = results["fp64"]
+    head = d["paths"]["fp64"]
+    if args.state == "moving" and not args.no_at_rest:
+        d["at_rest"] = {"fp64": run_path(rest_case, "fp64 at rest", args.steps, args.warmup),
+                        "mixed_learned": run_path(wl.with_params(rest_case, precision="mixed", fs_mode="learned"),
+                                                  "mixed_learned at rest", args.steps, args.warmup, clf=clf)}
 
     def roofline(res, key, kernel, kept=False):
         src = PAIR_SOURCES[key]
         prof = profile_summary(f"{key}_slosh3d")
         if kept:  # the second stage's pass from the kept lists
             k = res["kept_pass"]
-            tflops, ms = k["tflops"], k["ms"]
-            flops = k["pairs"] * FLOP_PER_PAIR_3D + k["kept_candidates_tested"] * FLOP_PER_TEST_3D
+            ms, pairs, tests = k["ms"], k["pairs"], k["kept_candidates_tested"]
         else:
-            tflops, ms = res["pair_pass_tflops"], res["pair_pass_ms"]
-            flops = res["pairs_per_rhs"] * FLOP_PER_PAIR_3D + res["candidate_tests_per_rhs"] * FLOP_PER_TEST_3D
+            ms, pairs, tests = res["pair_pass_ms"], res["pairs_per_rhs"], res["candidate_tests_per_rhs"]
+        # the method's work only: FLOP of the in-range pairs; the candidate
+        # distance tests of the search are reported beside it
+        achieved = pairs * FLOP_PER_PAIR_3D / (ms * 1e-3) / 1e12
         out = {
-            "bound": "alu", "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": tflops / PEAK_FP64_TFLOPS,
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": prof["hbm_bytes_per_launch"] if prof else None,
-            "kernel": kernel, "pair_pass_ms": ms, "flop_per_launch": flops,
+            "kernel": kernel, "pair_pass_ms": ms, "pairs_per_launch": pairs, "tests_per_launch": tests,
+            "tflops_with_tests": (pairs * FLOP_PER_PAIR_3D + tests * FLOP_PER_TEST_3D) / (ms * 1e-3) / 1e12,
             "source_sha": source_sha(src),
         }
         if prof and "valu_issue_frac" in prof:
@@ -569,46 +741,37 @@ def main():
             out["ta_busy"] = {"frac": prof["ta_busy_frac"], "from": f"profiles/{key}_slosh3d_pmc.json"}
         return out
 
-    roof = roofline(head, "pair_f64", "k_pair_f64<3,false,true,true> (search and pair pass of the first stage, "
-                    "keeping its candidates, FP64)")
-    out = {
-        "metric": METRIC, "value": head["pair_evals_per_s"], "unit": "pair-evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic (seeded lattice tank, hydrostatic start, tank-frame forcing)",
-        "config": {"workload": (f"3D sloshing tank 1.0x0.5x0.56 m, depth 0.28 m, dx={args.dx}: "
+    d["roofline"] = roofline(head, "pair_f64", "k_pair_f64<3,false,true,true> (first-stage search + pair pass)")
+    d["data"] = f"synthetic: seeded lattice tank, tank-frame forcing; timed state: {state_desc}"
+    d["config"] = {"workload": (f"3D sloshing tank 1.0x0.5x0.56 m, depth 0.28 m, dx={args.dx}: "
                                 f"{case['meta']['n_fluid']} fluid + {case['meta']['n_dummy']} dummies"),
-                   "path": "fp64", "fs_mode": "exact",
+                   "path": "fp64", "fs_mode": "exact", "state": args.state,
                    "cell_size_over_h": args.keep_cell if args.keep_cell > 0 else args.cell,
                    "second_stage": "kept candidate lists" if args.keep_cell > 0 else "rebuild and search",
-                   "parallelism": "single GPU"},
-        "roofline": roof,
-        "paths": results,
-    }
+                   "parallelism": "single GPU"}
     if "kept_pass" in head:
-        out["roofline_kept"] = roofline(head, "pair_kept_f64", "k_pair_kept_f64<3,false,true> (second stage from the "
-                                        "kept lists, FP64)", kept=True)
-    if "mixed" in results:
+        d["roofline_kept"] = roofline(head, "pair_kept_f64", "k_pair_kept_f64<3,false,true> (second stage, kept "
+                                      "lists)", kept=True)
+    if "mixed" in d["paths"]:
         # non-packed FP32 issues at the FP64 rate on this chip: same peak
-        out["roofline_mixed"] = roofline(results["mixed"], "pair_mixed",
-                                         "k_pair_mixed<3,false,true,true,false> (first-stage pass, FP32 body + FP64 sums)")
-        if "kept_pass" in results["mixed"]:
-            out["roofline_kept_mixed"] = roofline(results["mixed"], "pair_kept_mixed",
-                                                  "k_pair_kept_mixed<3,false,true,false> (second stage from the kept lists)",
-                                                  kept=True)
+        d["roofline_mixed"] = roofline(d["paths"]["mixed"], "pair_mixed",
+                                       "k_pair_mixed<3,false,true,true,false> (first-stage pass, FP32 body + FP64 sums)")
+        if "kept_pass" in d["paths"]["mixed"]:
+            d["roofline_kept_mixed"] = roofline(d["paths"]["mixed"], "pair_kept_mixed",
+                                                "k_pair_kept_mixed<3,false,true,false> (second stage from the kept "
+                                                "lists)", kept=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.dx)
-    for k in ("mixed", "mixed_learned", "fp32"):
-        if k in results:
-            out[f"{k}_over_fp64_step_rate"] = results["fp64"]["ms_per_step"] / results[k]["ms_per_step"]
+        cb = cpu_baseline(args.dx)
+        cb["cpu_model"] = cpu_model()
+        d["cpu_baseline"] = cb
     if args.keep_cell > 0 and not args.no_across_steps:
         # the lists kept across steps as well (SPH_F_KEEP_ACROSS_STEPS): from
-        # the bench's start (a state near rest: one build serves many steps)
-        # and from a moving state (seeded random velocities, |U| up to about
-        # 0.3 m/s), where the bound on the particles' moves runs out sooner
+        # the lattice near rest (one build serves many steps) and from a
+        # moving state (seeded random velocities, |U| up to about 0.3 m/s),
+        # where the bound on the particles' moves runs out sooner
         xs = wl.with_params(case, cell_size=args.across_cell * h, keep_lists=True, keep_across_steps=True)
         moving = wl.random_velocity(xs, 0.05, 21)
-        out["keep_across_steps"] = {
+        d["keep_across_steps"] = {
             "cell_size_over_h": args.across_cell,
             "from_rest": run_path(xs, "fp64 across steps (near rest)", args.steps, args.warmup),
             "moving": run_path(moving, "fp64 across steps (moving, |U| <= ~0.3 m/s)", args.steps, args.warmup),
@@ -616,18 +779,28 @@ def main():
                                            "fp64 within steps (moving)", args.steps, args.warmup),
         }
     if args.body_dx > 0:
-        out["moving_body"] = moving_body(args.body_dx, args.steps, args.warmup)
-    out["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
+        d["moving_body"] = moving_body(args.body_dx, args.steps, args.warmup)
+    if args.mlp:
+        d["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:
-        out["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)
+        d["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)
     if args.probe_seconds > 0:
-        out["dambreak_wall_pressure"] = dambreak_probes(args.probe_seconds)
-    out["spurious_u_tank2d_100steps"] = {k: spurious_velocity(k) for k in ("fp64", "mixed", "fp32")}
+        d["dambreak_wall_pressure"] = dambreak_probes(args.probe_seconds)
+    if args.tank_steps > 0:
+        d["spurious_u_tank2d"] = {k: spurious_velocity(k, args.tank_steps) for k in ("fp64", "mixed", "fp32")}
     if args.bump_steps > 0:
-        out["spurious_u_bump2d"] = bump_history(args.bump_steps, 500)
+        d["spurious_u_bump2d"] = bump_history(args.bump_steps, 500)
     if args.hydro_steps > 0:
-        out["hydrostatic_l2_paper_cases"] = hydrostatic_l2(args.hydro_steps, 50)
-    print(json.dumps(out), flush=True)
+        d["hydrostatic_l2_paper_cases"] = hydrostatic_l2(args.hydro_steps, 50)
+    d["detail_path"] = args.detail
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump(d, f)
+    except OSError as e:
+        log(f"detail file not written: {e}")
+        d["detail_path"] = None
+    print(json.dumps(compact_line(d), separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

@@ -831,6 +831,7 @@ __global__ void __launch_bounds__(256) k_stage_mixed(Phys P, Grid g, FluidMixed 
   if (i < n) {
     const double dt = sc->dt;
     uint32_t c = f.cell[i];
+    uint32_t bad = 0u;
     int cc[3] = {cell_x(c), cell_y(c), cell_z(c)};
     float of[3] = {0.f, 0.f, 0.f}, uf[3] = {0.f, 0.f, 0.f};
     for (int a = 0; a < DIM; ++a) {
@@ -849,7 +850,9 @@ __global__ void __launch_bounds__(256) k_stage_mixed(Phys P, Grid g, FluidMixed 
       }
       // keep the offset inside its cell: move whole cells, subtract k R exactly
       const double ov = (double)o - (double)oc;
-      const int kc = (int)floor(ov / g.R);
+      if (!isfinite(ov) || !isfinite((double)u)) bad |= kErrNonFinite;
+      const double kf = isfinite(ov) ? floor(ov / g.R) : 0.0;
+      const int kc = (int)fmin(fmax(kf, -4096.0), 4096.0);
       if (kc != 0) {
         cc[a] += kc;
         kahan_add(o, oc, -(double)kc * g.R);
@@ -862,8 +865,12 @@ __global__ void __launch_bounds__(256) k_stage_mixed(Phys P, Grid g, FluidMixed 
       uf[a] = u;
       u2 += (double)u * (double)u;
     }
-    // cells outside the grid are caught by the next hash (domain error); keep
-    // the packed fields from wrapping meanwhile
+    // a particle whose cell left the grid is an error (reported at the next
+    // synchronisation); the packed fields are kept from wrapping meanwhile
+    for (int a = 0; a < DIM; ++a) {
+      const double xa = g.lo[a] + (double)cc[a] * g.R + ((double)of[a] - (double)f.oc[a][i]);
+      if (cc[a] < 0 || cc[a] >= g.N[a] || !(xa >= g.lo[a] && xa <= g.hi[a])) bad |= kErrDomain;
+    }
     for (int a = 0; a < 3; ++a) cc[a] = min(max(cc[a], 0), a == 2 ? 1023 : 2047);
     c = pack_cell(cc[0], cc[1], cc[2]);
     f.cell[i] = c;
@@ -876,6 +883,8 @@ __global__ void __launch_bounds__(256) k_stage_mixed(Phys P, Grid g, FluidMixed 
       ph += 0.5 * (dp - f.dphi1[i]);
     }
     f.phi[i] = ph;
+    if (!isfinite(ph)) bad |= kErrNonFinite;
+    if (bad) atomicOr(&sc->err, bad);
     if (write_rec) {  // the records of the new state, as the reorder writes them
       const float V = (float)((double)f.m[i] / (P.rho0 * exp(ph * P.inv_c02)));
       float xa[3] = {0.f, 0.f, 0.f};

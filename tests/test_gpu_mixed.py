@@ -148,3 +148,26 @@ def test_mixed_trajectory_tracks_fp64(Sim):
     assert du <= 1e-4
     assert dp <= 1e-4
     assert abs(sm.stats()["t"] - sd.stats()["t"]) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+@pytest.mark.parametrize("side", ["low", "high"])
+def test_out_of_domain_is_reported_mixed(Sim, precision, side):
+    """The mixed storage keeps a cell index per particle: a particle whose
+    stage update carries it out of the hashed box through either side is
+    reported as SPH_EDOMAIN at the next synchronising call (and is not moved
+    back into the first or last cell)."""
+    from paper_2608_22269_amd import _lib as L
+    pd = wl.base_params(2, 0.01, domain_lo=[0, 0, 0], domain_hi=[1, 1, 0], gravity=[0, 0, 0], precision=precision)
+    x0, u0 = (0.0005, -50.0) if side == "low" else (0.9995, 50.0)
+    case = {"params": pd, "x": np.array([[0.5, 0.5], [x0, 0.5]]), "u": np.array([[0.0, 0.0], [u0, 0.0]]),
+            "phi": np.zeros(2), "kind": np.zeros(2, np.uint8), "normal": np.zeros((2, 2)), "mass": None, "t": 0.0}
+    sim = Sim(case)
+    sim.step(1, dt=1e-4)
+    with pytest.raises(L.SphError) as e:
+        sim.sync()
+    assert e.value.code == L.SPH_EDOMAIN
+    with pytest.raises(L.SphError) as e:
+        sim.step(1)
+    assert e.value.code == L.SPH_ESTATE
+    sim.close()
