@@ -9,6 +9,7 @@ This module only marshals arguments (ctypes) and builds the C file with gcc.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -31,14 +32,47 @@ FS_EXACT = 1
 NFEAT = 16
 
 
+def _compile(src: str, out: str) -> str:
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-shared", "-fPIC", src, "-o", out + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the C oracle (gcc, FP64, no contraction, OpenMP)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
+        _compile(_SRC, _LIB)
     return _LIB
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+def build_variant(text: str, workdir: str) -> str:
+    """Compiles a variant of the oracle's C source (a test's planted mistake)
+    into workdir/liborc_variant.so, with the oracle's own flags."""
+    os.makedirs(workdir, exist_ok=True)
+    src = os.path.join(workdir, "wbsph_oracle_variant.c")
+    with open(src, "w") as f:
+        f.write(text)
+    return _compile(src, os.path.join(workdir, "liborc_variant.so"))
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Routes every call of this module to the library at `path` (a variant
+    built by build_variant) inside the with-block."""
+    global _lib
+    saved = _lib
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 class Params(C.Structure):
@@ -65,35 +99,39 @@ class _Rates(C.Structure):
 _lib = None
 
 
+def _load(path):
+    L = C.CDLL(path)
+    P = C.POINTER(Params)
+    vp = C.c_void_p
+    L.orc_W.restype = C.c_double
+    L.orc_W.argtypes = [C.c_int, C.c_double, C.c_double]
+    L.orc_K.restype = C.c_double
+    L.orc_K.argtypes = [C.c_int, C.c_double, C.c_double]
+    L.orc_cells.argtypes = [P, C.c_int64, vp, vp, vp]
+    L.orc_neighbors_brute.argtypes = [P, C.c_int64, vp, vp, vp, C.c_int64, vp]
+    L.orc_neighbors_cells.argtypes = [P, C.c_int64, vp, vp, vp, C.c_int64, vp]
+    L.orc_eigvals.argtypes = [C.c_int, vp, vp]
+    L.orc_eigvals.restype = None
+    L.orc_eval_rates.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int, vp,
+                                 C.POINTER(_Rates)]
+    L.orc_dt.restype = C.c_double
+    L.orc_dt.argtypes = [P, C.c_int64, vp, vp]
+    L.orc_step.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_double),
+                           C.c_int32, C.c_double, C.c_int, C.POINTER(C.c_double)]
+    L.orc_body_motion.argtypes = [P, C.c_double, vp, vp]
+    L.orc_body_motion.restype = None
+    L.orc_num_threads.restype = C.c_int
+    L.orc_set_num_threads.argtypes = [C.c_int]
+    L.orc_set_num_threads.restype = None
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
-        P = C.POINTER(Params)
-        vp = C.c_void_p
-        L.orc_W.restype = C.c_double
-        L.orc_W.argtypes = [C.c_int, C.c_double, C.c_double]
-        L.orc_K.restype = C.c_double
-        L.orc_K.argtypes = [C.c_int, C.c_double, C.c_double]
-        L.orc_cells.argtypes = [P, C.c_int64, vp, vp, vp]
-        L.orc_neighbors_brute.argtypes = [P, C.c_int64, vp, vp, vp, C.c_int64, vp]
-        L.orc_neighbors_cells.argtypes = [P, C.c_int64, vp, vp, vp, C.c_int64, vp]
-        L.orc_eigvals.argtypes = [C.c_int, vp, vp]
-        L.orc_eigvals.restype = None
-        L.orc_eval_rates.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int, vp,
-                                     C.POINTER(_Rates)]
-        L.orc_dt.restype = C.c_double
-        L.orc_dt.argtypes = [P, C.c_int64, vp, vp]
-        L.orc_step.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_double),
-                               C.c_int32, C.c_double, C.c_int, C.POINTER(C.c_double)]
-        L.orc_body_motion.argtypes = [P, C.c_double, vp, vp]
-        L.orc_body_motion.restype = None
-        L.orc_num_threads.restype = C.c_int
-        L.orc_set_num_threads.argtypes = [C.c_int]
-        L.orc_set_num_threads.restype = None
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
 
 
