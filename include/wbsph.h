@@ -14,7 +14,9 @@
  *     doubles (x0 y0 [z0] x1 y1 ...).
  *   - The caller owns every buffer it passes.  The workspace handed to
  *     sph_init (and sph_mlp_create) must stay allocated and untouched until
- *     the matching destroy call; the library never allocates device memory.
+ *     the matching destroy call; the library allocates no device memory (the
+ *     one fixed array it holds, for sph_mlp_forward_noalloc, is part of the
+ *     loaded code object).
  *   - All device work is enqueued on the caller's hipStream_t (passed as
  *     void*; NULL = the null stream).  Calls return before the GPU finishes
  *     unless they write host memory, which synchronises the stream.
@@ -315,6 +317,30 @@ sph_status sph_mlp_get_params(sph_mlp *m, float *out, int32_t out_on_device);
  * stream order. */
 sph_status sph_mlp_infer_bf16(const float *params, const float *mean, const float *std,
                               const float *X, int64_t n, float *logits, void *hip_stream);
+
+/* ------------------------------------------------ allocation-free variant */
+
+/* Largest batch of sph_mlp_forward_noalloc. */
+#define SPH_MLP_NOALLOC_MAX_ROWS 8192
+
+/* For callers that cannot allocate device memory or hand over a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the FP32 forward pass of sph_mlp_forward without a trainer.
+ * Same kernel and same logits bit for bit; the weights come from `params`
+ * (device, 5,313 floats, the layout of sph_set_classifier), the
+ * standardisation from mean/std (device, 16 floats each), rows from X
+ * (device, B*16 floats), logits[b] to `logits` (device, B floats).  The
+ * activations the kernel stores go to a fixed scratch array inside the
+ * library (B <= SPH_MLP_NOALLOC_MAX_ROWS, about 6.8 MB per device, held
+ * until the process ends); no device memory is allocated, neither here nor
+ * on the first call of a device (which only looks the array up).
+ * B > SPH_MLP_NOALLOC_MAX_ROWS or B < 0 -> SPH_EINVAL before any launch; B
+ * = 0 -> SPH_OK.  Asynchronous on hip_stream.  Every call on one device
+ * shares that device's scratch array: calls that overlap in time on one
+ * device (other streams, other threads) race on it and must be ordered by
+ * the caller. */
+sph_status sph_mlp_forward_noalloc(const float *params, const float *mean, const float *std,
+                                   const float *X, int64_t B, float *logits, void *hip_stream);
 
 #ifdef __cplusplus
 }

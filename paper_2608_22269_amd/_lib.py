@@ -21,6 +21,7 @@ SPH_ENONFINITE = -5
 SPH_ESTATE = -6
 SPH_EUNSUPPORTED = -7
 SPH_ECAPACITY = -8
+MLP_NOALLOC_MAX_ROWS = 8192  # SPH_MLP_NOALLOC_MAX_ROWS
 
 SPH_FP64, SPH_MIXED, SPH_FP32 = 0, 1, 2
 SPH_FS_NONE, SPH_FS_EXACT, SPH_FS_LEARNED = 0, 1, 2
@@ -99,6 +100,7 @@ def lib():
         "sph_mlp_train_epoch": (i32, [vp, vp, vp, vp, vp, i64, i64, C.c_float, C.POINTER(C.c_float)]),
         "sph_mlp_get_params": (i32, [vp, vp, i32]),
         "sph_mlp_infer_bf16": (i32, [vp, vp, vp, vp, i64, vp, vp]),
+        "sph_mlp_forward_noalloc": (i32, [vp, vp, vp, vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -115,7 +117,7 @@ def exported_symbols():
         "sph_last_error", "sph_build_cells", "sph_step", "sph_eval_rates", "sph_sync", "sph_set_time", "sph_fields",
         "sph_stats", "sph_neighbors", "sph_profile", "sph_profile_read", "sph_set_classifier", "sph_mlp_workspace_bytes", "sph_mlp_create",
         "sph_mlp_destroy", "sph_mlp_forward", "sph_mlp_loss_grad", "sph_mlp_adam", "sph_mlp_train_epoch",
-        "sph_mlp_get_params", "sph_mlp_infer_bf16",
+        "sph_mlp_get_params", "sph_mlp_infer_bf16", "sph_mlp_forward_noalloc",
     ]
 
 

@@ -16,6 +16,7 @@
 // (persistent, grid-stride) kernel.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "mlp.h"
@@ -443,6 +444,36 @@ hipError_t mlp_adam(sph_mlp *m, float lr, float b1, float b2, float eps) {
 
 }  // namespace
 
+// Scratch of sph_mlp_forward_noalloc: the activations k_mlp_fwd stores
+// (standardised input, both pre-activations, the second activation) for up
+// to SPH_MLP_NOALLOC_MAX_ROWS rows, in a fixed device array (each device
+// that runs the library holds its own copy).  Host code never passes the
+// array's name to a kernel: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and kept.
+static __device__ __align__(256) float scratch[(size_t)SPH_MLP_NOALLOC_MAX_ROWS * (kMlpIn + 3 * kMlpHid)];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the current device's scratch array.
+sph_status noalloc_scratch(float **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return SPH_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return SPH_EHIP;
+    g_scratch_ptr[dev] = static_cast<float *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return SPH_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t sph_mlp_workspace_bytes(int64_t max_batch) {
@@ -536,6 +567,22 @@ sph_status sph_mlp_get_params(sph_mlp *m, float *out, int32_t out_on_device) {
                                 out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, m->s);
   if (e == hipSuccess && !out_on_device) e = hipStreamSynchronize(m->s);
   return e == hipSuccess ? SPH_OK : SPH_EHIP;
+}
+
+sph_status sph_mlp_forward_noalloc(const float *params, const float *mean, const float *std, const float *X,
+                                   int64_t B, float *logits, void *hip_stream) {
+  if (!params || !mean || !std || !X || !logits || B < 0 || B > SPH_MLP_NOALLOC_MAX_ROWS) return SPH_EINVAL;
+  if (B == 0) return SPH_OK;
+  float *sp = nullptr;
+  if (noalloc_scratch(&sp) != SPH_OK) return SPH_EHIP;
+  float *xs = sp;
+  float *z1 = xs + (size_t)SPH_MLP_NOALLOC_MAX_ROWS * kMlpIn;
+  float *z2 = z1 + (size_t)SPH_MLP_NOALLOC_MAX_ROWS * kMlpHid;
+  float *a2 = z2 + (size_t)SPH_MLP_NOALLOC_MAX_ROWS * kMlpHid;
+  const unsigned rb = (unsigned)((B + 3) / 4);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(rb), dim3(256), 0, (hipStream_t)hip_stream, params, mean, std, X,
+                     (const int32_t *)nullptr, (int64_t)0, B, xs, z1, z2, a2, logits);
+  return hipGetLastError() == hipSuccess ? SPH_OK : SPH_EHIP;
 }
 
 sph_status sph_mlp_infer_bf16(const float *params, const float *mean, const float *std, const float *X, int64_t n,

@@ -107,6 +107,24 @@ def infer_bf16(params, mean, std, X, stream=None):
     return out
 
 
+def forward_noalloc(params, mean, std, X, stream=None):
+    """FP32 logits of the rows of X through sph_mlp_forward_noalloc (the
+    trainer's forward pass without a trainer or workspace; at most
+    SPH_MLP_NOALLOC_MAX_ROWS rows).  Returns a device tensor."""
+    import torch
+    w = _dev(params, torch.float32)
+    mu = _dev(mean, torch.float32)
+    sd = _dev(std, torch.float32)
+    Xd = X if isinstance(X, torch.Tensor) else _dev(X, torch.float32)
+    out = torch.empty(Xd.shape[0], dtype=torch.float32, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(L.lib().sph_mlp_forward_noalloc(C.c_void_p(w.data_ptr()), C.c_void_p(mu.data_ptr()),
+                                           C.c_void_p(sd.data_ptr()), C.c_void_p(Xd.data_ptr()), Xd.shape[0],
+                                           C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)),
+           "sph_mlp_forward_noalloc")
+    return out
+
+
 def candidate_samples(sim: Simulation):
     """Features and exact labels of the particles the scan-region pass decided
     in the last right-hand side (lambda between the two thresholds)."""
