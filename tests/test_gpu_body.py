@@ -78,9 +78,9 @@ def test_body_trajectory_parity(Sim, name, case):
     L = max(case["params"]["domain_hi"]) - min(case["params"]["domain_lo"])
     assert np.abs(sim.field("x")[f] - ref["x"][f]).max() <= 1e-12 * L
     umax = max(np.abs(ref["u"][f]).max(), 1e-3)
-    assert np.abs(sim.field("u")[f] - ref["u"][f]).max() <= 1e-10 * umax
+    assert np.abs(sim.field("u")[f] - ref["u"][f]).max() <= 1e-12 * umax
     pmax = np.abs(ref["phi"][f]).max()
-    assert np.abs(sim.field("phi")[f] - ref["phi"][f]).max() <= 1e-11 * pmax
+    assert np.abs(sim.field("phi")[f] - ref["phi"][f]).max() <= 1e-12 * pmax
     t = sim.stats()["t"]
     assert abs(t - ref["t"]) <= 1e-15
     b = case["kind"] == 2

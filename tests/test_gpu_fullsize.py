@@ -52,7 +52,7 @@ def _sample(case, seed=0):
     return np.unique(rows)
 
 
-def _compare_rows(sim, case, ref, rows, tol, tol_lam, fs_tie=1e-9):
+def _compare_rows(sim, case, ref, rows, tol, tol_lam, fs_tie=1e-9, max_ties=2):
     pd = case["params"]
     gmag = float(np.linalg.norm(pd["gravity"])) or 1.0
     acc = sim.field("dudt")[rows]
@@ -75,6 +75,7 @@ def _compare_rows(sim, case, ref, rows, tol, tol_lam, fs_tie=1e-9):
         near |= np.abs(lmin - thr) < max(1e-10, 10 * tol_lam)
     assert np.array_equal(tic[~near], ref["tic"][rows][~near])
     tie = near | (ref["fs_margin"][rows] < fs_tie * pd["h"] ** 2)
+    assert tie.sum() <= max_ties, (int(near.sum()), int(tie.sum()))
     assert np.array_equal(fs[~tie], ref["fs"][rows][~tie])
     return nnb
 
@@ -96,7 +97,7 @@ def test_mixed_sloshing_tank_full_size_sampled(Sim, slosh):
     sim = Sim(wl.with_params(slosh, precision="mixed"))
     sim.eval_rates()
     ref = oracle.eval_rates(_own_state_case(sim, slosh), rows=rows)
-    nnb = _compare_rows(sim, slosh, ref, rows, 2e-5, 1e-5, fs_tie=1e-4)
+    nnb = _compare_rows(sim, slosh, ref, rows, 2e-5, 1e-5, fs_tie=1e-4, max_ties=len(rows) // 100)
     # FP32 candidate tests may move pairs within ~1e-7 m of 2h in or out
     assert np.abs(nnb.astype(np.int64) - ref["nnb"][rows]).max() <= 1
     sim.close()
@@ -147,7 +148,7 @@ def test_kept_lists_full_size(Sim, slosh):
         va, vb = a.field(name)[f], b.field(name)[f]
         err = np.abs(va - vb).max() / max(np.abs(vb).max(), 1e-30)
         print(name, err)
-        assert err <= 1e-11, name
+        assert err <= 1e-12, name
     a.close()
     b.close()
 
@@ -168,7 +169,7 @@ def test_dam_break_full_size_trajectory_with_kept_lists(Sim):
     eu = np.abs(sim.field("u")[f] - ref["u"][f]).max() / np.abs(ref["u"][f]).max()
     ep = np.abs(sim.field("phi")[f] - ref["phi"][f]).max() / np.abs(ref["phi"][f]).max()
     print(f"x {ex:.2e} u {eu:.2e} phi {ep:.2e}")
-    assert ex <= 1e-12 and eu <= 1e-10 and ep <= 1e-11
+    assert ex <= 1e-12 and eu <= 1e-12 and ep <= 1e-12
     assert abs(sim.stats()["t"] - ref["t"]) <= 1e-15
     sim.close()
 
@@ -220,6 +221,6 @@ def test_sloshing_tank_50_steps_lists_across_steps(Sim):
     eu = np.abs(sim.field("u")[f] - ref["u"][f]).max() / np.abs(ref["u"][f]).max()
     ep = np.abs(sim.field("phi")[f] - ref["phi"][f]).max() / np.abs(ref["phi"][f]).max()
     print(f"kept {st['n_kept']} rebuilt {st['n_rebuilt']}: x {ex:.2e} u {eu:.2e} phi {ep:.2e}")
-    assert ex <= 1e-12 and eu <= 1e-10 and ep <= 1e-11
+    assert ex <= 1e-12 and eu <= 1e-12 and ep <= 1e-12
     assert abs(st["t"] - ref["t"]) <= 1e-14
     sim.close()

@@ -2,7 +2,8 @@
 
 Bars: cell indices and neighbour sets bit-exact; FP64 fields within 1e-12 of
 the field's scale (see _scale); flags exact except particles whose decision
-sits within a tie margin in the oracle (listed, expected to be none).
+sits within a tie margin in the oracle (at most MAX_TIES rows per case; none
+occur in the cases here); trajectories within 1e-12 of their scale.
 """
 import math
 
@@ -15,6 +16,7 @@ import workloads as wl
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
 TOL = 1e-12
+MAX_TIES = 2
 
 
 @pytest.fixture(scope="module")
@@ -80,6 +82,8 @@ def compare_rates(sim, case, ref, tol=TOL):
     assert np.array_equal(tic[f][~near], ref["tic"][f][~near])
     fs = sim.field("fs")
     tie = near | (ref["fs_margin"][f] < 1e-9 * pd["h"] ** 2)
+    # the rows left out of the flag comparison: at most MAX_TIES per case
+    assert tie.sum() <= MAX_TIES, (int(near.sum()), int(tie.sum()))
     assert np.array_equal(fs[f][~tie], ref["fs"][f][~tie])
     agree = (fs[f] == ref["fs"][f])
     assert _rel(dus[f][agree], ref["dushift"][f][agree], s_dus) <= tol
@@ -179,6 +183,39 @@ def test_hydrostatic_tank_gpu(Sim):
     assert abs(st["t"] - ref["t"]) <= 1e-15 and st["steps"] == 100
 
 
+def test_hydrostatic_tank_200_steps_surface_mode(Sim):
+    """The 2D tank's 200 steps (5,000 fluid, FP64, no stabilisers), stated as
+    they come out.  The tank is an exact discrete equilibrium and stays below
+    1e-12 m/s through step 100; then the literal scheme's free-surface mode
+    grows from round-off: the linearised right-hand side has a real
+    eigenvalue of 0.605 C0/dx in the top particle layer (pinned on the CPU in
+    test_oracle_surface_mode.py), so max |U| passes 1e-12 between steps 100
+    and 150 and the 1e-12 target does not hold at 200 steps under this
+    reading.  Asserted: the window, the growth rate between steps 150 and 200
+    within 10% of what SSP-RK2 gives that eigenvalue, and max |U| at step 200
+    within a factor 10 of the oracle's (each grows from its own round-off)."""
+    import math
+    from tests.test_oracle_surface_mode import rk2_rate
+    case = wl.tank2d()
+    f = case["kind"] == 0
+    sim = Sim(case)
+    sim.step(100)
+    assert np.abs(sim.field("u")[f]).max() <= 1e-12
+    sim.step(50)
+    u150, t150 = np.abs(sim.field("u")[f]).max(), sim.stats()["t"]
+    sim.step(50)
+    u200, t200 = np.abs(sim.field("u")[f]).max(), sim.stats()["t"]
+    dt = sim.stats()["dt"]
+    print(f"max |U|: step 150 {u150:.3e}, step 200 {u200:.3e}")
+    assert u200 > 1e-12  # the mode, not a pass of the target
+    c0dx = case["params"]["c0"] / case["params"]["dx"]
+    rate, want = math.log(u200 / u150) / (t200 - t150), rk2_rate(0.605 * c0dx, dt)
+    assert abs(rate - want) <= 0.10 * want, (rate, want)
+    ref = oracle.step(case, 200)
+    u_ref = np.abs(ref["u"][f]).max()
+    assert 0.1 * u_ref <= u200 <= 10.0 * u_ref, (u200, u_ref)
+
+
 @pytest.mark.parametrize("name,case,nsteps", [
     ("tank2d-dyn", CASES[1][1], 10),
     ("dambreak3d-mini", wl.dambreak3d(dx=0.04, tank=(0.8, 0.4, 0.4), column=(0.3, 0.4, 0.22)), 10),
@@ -191,9 +228,9 @@ def test_trajectory_parity(Sim, name, case, nsteps):
     L = max(case["params"]["domain_hi"]) - min(case["params"]["domain_lo"])
     assert np.abs(sim.field("x")[f] - ref["x"][f]).max() <= 1e-12 * L
     umax = max(np.abs(ref["u"][f]).max(), 1e-3)
-    assert np.abs(sim.field("u")[f] - ref["u"][f]).max() <= 1e-10 * umax
+    assert np.abs(sim.field("u")[f] - ref["u"][f]).max() <= 1e-12 * umax
     pmax = np.abs(ref["phi"][f]).max()
-    assert np.abs(sim.field("phi")[f] - ref["phi"][f]).max() <= 1e-11 * pmax
+    assert np.abs(sim.field("phi")[f] - ref["phi"][f]).max() <= 1e-12 * pmax
     assert abs(sim.stats()["t"] - ref["t"]) <= 1e-15
 
 
