@@ -273,21 +273,25 @@ def state_of(sim, case):
 
 
 def dambreak_detection(spin, steps):
-    """Exact vs learned free-surface detection on the 3D dam break of the
-    workloads (660,000 fluid, dx = 0.01, mixed precision) after `spin` steps of
-    the collapse: step time, detection time per step and misclassification on
+    """Exact vs learned free-surface detection on a dam break the classifier
+    never saw (its training used the 3.22 x 1 x 1 m tank with a 1.2 x 1 x
+    0.55 m column and a 2.0 x 0.6 x 1.0 m tank with a 0.5 x 0.6 x 0.6 m
+    column, both at dx = 0.01): a 2.4 x 0.7 x 0.9 m tank, a 0.7 x 0.7 x
+    0.45 m column, dx = 0.008 (mixed precision), after `spin` steps of the
+    collapse: step time, detection time per step and misclassification on
     the same state."""
     import torch
     import workloads as wl
     from paper_2608_22269_amd import Simulation
     clf = load_classifier()
-    case = wl.dambreak3d(dx=0.01, precision="mixed")
+    case = wl.dambreak3d(dx=0.008, tank=(2.4, 0.7, 0.9), column=(0.7, 0.7, 0.45), precision="mixed")
     case = wl.with_params(case, cell_size=case["params"]["h"])
     sim = Simulation(case)
     sim.step(spin)
     state = state_of(sim, case)
     sim.close()
-    out = {"workload": f"3D dam break dx=0.01, {case['meta']['n_fluid']} fluid, after {spin} steps (t = {state['t']:.3f} s)"}
+    out = {"workload": (f"3D dam break (held out) tank 2.4x0.7x0.9, column 0.7x0.7x0.45, dx=0.008, "
+                        f"{case['meta']['n_fluid']} fluid, after {spin} steps (t = {state['t']:.3f} s)")}
     for mode in ("exact", "learned"):
         s2 = Simulation(wl.with_params(state, fs_mode=mode))
         if mode == "learned":
@@ -313,6 +317,31 @@ def dambreak_detection(spin, steps):
         out[mode] = r
         log(f"dam break {mode}: {r}")
     return out
+
+
+def slosh_surface_detection(dx, steps):
+    """The learned detector on the full-size sloshing tank with a moved
+    surface, a state no training snapshot holds: the first mode's shape
+    (2 cm, cos(pi x/L)) released from rest, after `steps` steps of the mixed
+    path with the classifier; misclassification against the exact criterion
+    on that state."""
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    clf = load_classifier()
+    case = wl.slosh3d(dx=dx, surface_amp=0.02, precision="mixed", fs_mode="learned")
+    h = case["params"]["h"]
+    case = wl.with_params(case, cell_size=1.01 * h, keep_lists=True)
+    sim = Simulation(case)
+    sim.set_classifier(clf["params"], clf["mean"], clf["std"], float(clf["margin"]))
+    sim.step(steps)
+    m = misclassification(sim, case, clf)
+    st = sim.stats()
+    sim.close()
+    m["workload"] = (f"3D sloshing tank dx={dx}, surface 0.28 + 0.02 cos(pi x/L) released from rest, "
+                     f"{case['meta']['n_fluid']} fluid, after {steps} steps (t = {st['t']:.4f} s, "
+                     f"max |U| {st['umax']:.3f} m/s)")
+    log(f"slosh surface detection: {m}")
+    return m
 
 
 def dambreak_probes(seconds, every=100):
@@ -593,10 +622,14 @@ def compact_line(d):
     if d.get("dambreak_detection"):
         r = d["dambreak_detection"]
         ln = r["learned"]
-        line["dambreak_detection"] = {
+        line["dambreak_heldout_detection"] = {
             "exact_ms_per_step": _sig(r["exact"]["ms_per_step"]), "learned_ms_per_step": _sig(ln["ms_per_step"]),
             "candidates": ln["misclassification"]["candidates"],
             "misclassified": ln["misclassification"]["misclassified"]}
+    if d.get("slosh_surface_detection"):
+        m = d["slosh_surface_detection"]
+        line["slosh_moved_surface_detection"] = {"candidates": m["candidates"], "misclassified": m["misclassified"],
+                                                 "fallback_exact": m["fallback_exact"]}
     if d.get("dambreak_wall_pressure"):
         r = d["dambreak_wall_pressure"]
         line["dambreak_wall_pressure"] = {"t_end": _sig(r["t"][-1], 3) if r["t"] else None,
@@ -644,8 +677,12 @@ def main():
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
                          "mixed_learned: mixed precision with the trained classifier and exact fallback; "
                          "fp32: the single-precision form")
-    ap.add_argument("--dambreak-spin", type=int, default=4000,
-                    help="steps of the 3D dam break before the exact / learned detection comparison (0: skip)")
+    ap.add_argument("--dambreak-spin", type=int, default=5000,
+                    help="steps of the held-out 3D dam break before the exact / learned detection comparison "
+                         "(0: skip)")
+    ap.add_argument("--surface-steps", type=int, default=200,
+                    help="steps of the full-size tank with a moved (cosine) surface before the learned "
+                         "detector's misclassification is taken (0: skip)")
     ap.add_argument("--probe-seconds", type=float, default=0.7,
                     help="simulated seconds of the 3D dam-break wall-pressure comparison, FP64 vs mixed (0: skip)")
     ap.add_argument("--hydro-steps", type=int, default=1000,
@@ -784,6 +821,8 @@ def main():
         d["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:
         d["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)
+    if args.surface_steps > 0:
+        d["slosh_surface_detection"] = slosh_surface_detection(args.dx, args.surface_steps)
     if args.probe_seconds > 0:
         d["dambreak_wall_pressure"] = dambreak_probes(args.probe_seconds)
     if args.tank_steps > 0:

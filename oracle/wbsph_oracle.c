@@ -740,8 +740,7 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const dou
 
         /* pair sums over N(i), Algorithm 1 / Eq. (sph) */
         double L[9] = {0}, g[3] = {0}, SR[3] = {0}, SC[3] = {0}, Nm[9] = {0}, P[3] = {0};
-        double Dsum = 0.0, S0 = 0.0, qmin = 2.0;
-        int nd_count = 0;
+        double Dsum = 0.0;
         const double *xi = x + i * dim, *ui = uv + i * dim;
         const double phii = phiv[i];
         for (int64_t k = off[i]; k < off[i + 1]; ++k) {
@@ -782,10 +781,6 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const dou
             double wr = Wq / W0;
             double pw = 1.0 + p->pst_R * pow(wr, p->pst_n);
             for (int a = 0; a < dim; ++a) P[a] += pw * gw[a] * Vj;
-            /* classifier inputs: kernel sum, closest neighbour, dummies */
-            S0 += Wq * Vj;
-            if (q < qmin) qmin = q;
-            if (kind[j] != 0) nd_count++;
         }
 
         /* eigenvalues of the (symmetric) correction matrix */
@@ -850,41 +845,47 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const dou
             }
         }
 
-        /* features (16): eigenvalues of L, det L, kernel sum (with the self
-         * term), neighbour count, |g| h, the moments of the kernel-gradient
-         * sum g and of L along the normal n and across it, |L^-T g| h, n
-         * against gravity, dummy fraction, closest-neighbour q, |P| h */
+        /* features (16), all from the sums above: eigenvalues of L, det L,
+         * the shifting sum P along the normal n, neighbour count, |g| h, the
+         * moments of the kernel-gradient sum g and of L along n and across
+         * it, |L^-T g| h, n against gravity, P across n, the cosine between
+         * P and n, |P| h */
         {
-            double Wself = orc_W(dim, h, 0.0) * V[i];
-            double S0s = S0 + Wself;
-            double ng = 0.0, gn2 = 0.0, nLn = 0.0, trL = 0.0, Pn2 = 0.0, ngrav = 0.0, gg2 = 0.0;
+            double ng = 0.0, gn2 = 0.0, nLn = 0.0, trL = 0.0, Pn2 = 0.0, ngrav = 0.0, gg2 = 0.0, nP = 0.0;
             for (int a = 0; a < dim; ++a) {
                 ng += nrm[a] * g[a];
                 gn2 += g[a] * g[a];
                 trL += L[a * dim + a];
                 Pn2 += P[a] * P[a];
+                nP += nrm[a] * P[a];
                 ngrav += nrm[a] * G[a];
                 gg2 += G[a] * G[a];
                 for (int b = 0; b < dim; ++b) nLn += nrm[a] * L[a * dim + b] * nrm[b];
             }
-            double gt2 = gn2 - ng * ng;
+            double gt2 = 0.0, Pt2 = 0.0; /* tangential parts by components */
+            for (int a = 0; a < dim; ++a) {
+                double tg = g[a] - ng * nrm[a], tp = P[a] - nP * nrm[a];
+                gt2 += tg * tg;
+                Pt2 += tp * tp;
+            }
             int cnt = (int)(off[i + 1] - off[i]);
+            double Pm = sqrt(Pn2);
             ft[0] = lam[0];
             ft[1] = lam[1];
             ft[2] = dim == 3 ? lam[2] : lam[1];
             ft[3] = det_d(dim, L);
-            ft[4] = S0s;
+            ft[4] = nP * h;
             ft[5] = (double)cnt;
             ft[6] = sqrt(gn2) * h;
             ft[7] = ng * h;
-            ft[8] = sqrt(gt2 > 0.0 ? gt2 : 0.0) * h;
+            ft[8] = sqrt(gt2) * h;
             ft[9] = nLn;
             ft[10] = trL - nLn;
             ft[11] = nn * h;
             ft[12] = gg2 > 0.0 ? ngrav / sqrt(gg2) : 0.0;
-            ft[13] = cnt > 0 ? (double)nd_count / (double)cnt : 0.0;
-            ft[14] = qmin;
-            ft[15] = sqrt(Pn2) * h;
+            ft[13] = sqrt(Pt2) * h;
+            ft[14] = Pm > 0.0 ? nP / Pm : 0.0;
+            ft[15] = Pm * h;
         }
     }
 

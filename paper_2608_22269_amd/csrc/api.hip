@@ -444,7 +444,10 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
     sph_status sb = move_body(c);
     if (sb != SPH_OK) return sb;
   }
-  const bool feat = (c->p.flags & SPH_F_FEATURES) || c->p.fs_mode == SPH_FS_LEARNED;
+  // classifier features: every row when exported, else the candidates' in
+  // the learned mode (all sixteen from the pair pass's own sums)
+  const bool feat = (c->p.flags & SPH_F_FEATURES) != 0;
+  const bool learned = c->p.fs_mode == SPH_FS_LEARNED && c->has_clf;
   Phys Pw = c->P;
   Pw.win = c->P.two_h + win_extra;
   if (!c->mixed) {
@@ -455,8 +458,8 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
     }
     if (e == hipSuccess) {
       ProfScope ps(c, mode == kPairKept ? 5 : 0);
-      e = launch_pair_f64(c->P, c->g, c->rec0, c->rec1, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat,
-                          mode, c->kent, c->kcnt, c->s);
+      e = launch_pair_f64(c->P, c->g, c->rec0, c->rec1, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, mode,
+                          c->kent, c->kcnt, c->s);
     }
   } else {
     if (e == hipSuccess) {
@@ -465,17 +468,16 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
     }
     if (e == hipSuccess) {
       ProfScope ps(c, mode == kPairKept ? 5 : 0);
-      e = launch_pair_mixed(c->P, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, feat,
-                            mode, c->kent, c->kcnt, c->s, c->p.precision == SPH_FP32);
+      e = launch_pair_mixed(c->P, c->g, c->mrec, c->cs_f, c->cs_d, (uint32_t)c->nf, c->sc, c->r, c->cand, mode,
+                            c->kent, c->kcnt, c->s, c->p.precision == SPH_FP32);
     }
   }
   ProfScope ps_fs(c, 3);
   // classifier features: every fluid row when exported, else the candidates'
   if (e == hipSuccess && feat) {
-    if (c->p.flags & SPH_F_FEATURES)
-      e = launch_features(c->P, c->r, nullptr, nullptr, (uint32_t)c->nf, c->sc, c->s);
-    else if (c->p.fs_mode == SPH_FS_LEARNED && c->has_clf)
-      e = launch_features(c->P, c->r, c->cand, &c->sc->n_cand, (uint32_t)c->nf, c->sc, c->s);
+    e = launch_features(c->P, c->r, nullptr, nullptr, (uint32_t)c->nf, c->sc, c->s);
+  } else if (e == hipSuccess && learned) {
+    e = launch_features(c->P, c->r, c->cand, &c->sc->n_cand, (uint32_t)c->nf, c->sc, c->s);
   }
   if (e == hipSuccess && c->p.fs_mode != SPH_FS_NONE) {
     const uint32_t *list = c->cand;

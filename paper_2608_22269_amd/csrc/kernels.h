@@ -50,7 +50,7 @@ hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int
 constexpr int kPairSearch = 0, kPairSearchKeep = 1, kPairKept = 2;
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
-                           uint32_t *cand, bool features, int mode, uint32_t *kent, unsigned long long *kcnt,
+                           uint32_t *cand, int mode, uint32_t *kent, unsigned long long *kcnt,
                            hipStream_t s);
 // classifier features from the raw sums of the pair-pass epilogue, for the
 // rows of a device-counted list (count != nullptr) or rows 0 .. n - 1

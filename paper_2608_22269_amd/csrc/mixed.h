@@ -28,7 +28,7 @@ hipError_t launch_mirror_mixed(const Phys &P, const Grid &g, const Dummies &d, i
 // form of the pair sums (SPH_FP32)
 hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                              const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
-                             bool features, int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s,
+                             int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s,
                              bool abs32 = false);
 // records of the mixed state in its current order (no sort)
 hipError_t launch_refresh_mixed(const Phys &P, const Grid &g, const FluidMixed &f, int64_t nf, const MixedRec &rec,

@@ -28,15 +28,11 @@
 
 namespace wb {
 
-// waves per SIMD the register allocation targets (plain / with the
-// classifier sums; 4 measured faster for both)
+// waves per SIMD the register allocation targets (4 measured fastest)
 #ifndef WB_MIXED_WAVES
 #define WB_MIXED_WAVES 4
 #endif
-#ifndef WB_MIXED_WAVES_FEAT
-#define WB_MIXED_WAVES_FEAT 4
-#endif
-#define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_MIXED_WAVES_FEAT : WB_MIXED_WAVES)))
+#define WB_MIXED_ATTR __attribute__((amdgpu_waves_per_eu(WB_MIXED_WAVES)))
 constexpr int kMList = kPairList;  // kept lists share the FP64 pass's layout
 constexpr int kMBatch = 4;
 static_assert(kMBatch <= kRecPad, "batched candidate loads run at most kRecPad records past a run");
@@ -316,7 +312,7 @@ __device__ __forceinline__ MixedI mixed_i(const Phys &P, const Grid &g, const fl
 
 // FP32 partial sums of one list chunk, flushed into the FP64 totals.
 struct MixedChunk {
-  float gsf[3], Nf[6], Pf[3], Df, S0f;
+  float gsf[3], Nf[6], Pf[3], Df;
 };
 
 __device__ __forceinline__ void chunk_zero(MixedChunk &C) {
@@ -324,7 +320,7 @@ __device__ __forceinline__ void chunk_zero(MixedChunk &C) {
   for (int a = 0; a < 3; ++a) C.gsf[a] = C.Pf[a] = 0.f;
 #pragma unroll
   for (int a = 0; a < 6; ++a) C.Nf[a] = 0.f;
-  C.Df = C.S0f = 0.f;
+  C.Df = 0.f;
 }
 
 __device__ __forceinline__ void chunk_flush(const MixedChunk &C, PairSums &S) {
@@ -336,14 +332,13 @@ __device__ __forceinline__ void chunk_flush(const MixedChunk &C, PairSums &S) {
 #pragma unroll
   for (int a = 0; a < 6; ++a) S.N[a] += C.Nf[a];
   S.Ds += C.Df;
-  S.S0 += C.S0f;
 }
 
 // Pair body of the mixed path for neighbour j (records b0, b1, phij).  PST4:
 // the shifting exponent is 4 (two squarings); otherwise powf().
-template <int DIM, bool FEAT, bool PST4>
+template <int DIM, bool PST4>
 __device__ __forceinline__ void mixed_body(const MixedI &I, const float4 &b0, const float4 &b1, const double phij,
-                                           const uint32_t j, const uint32_t nf, MixedChunk &C, PairSums &S) {
+                                           MixedChunk &C, PairSums &S) {
   const uint32_t cj = __float_as_uint(b0.w);
   // r = (c_j - c_i) R + (o_j - o_i), formed in FP64 from the integer cell
   // difference and the promoted offsets (one rounding): the same r enters
@@ -406,11 +401,6 @@ __device__ __forceinline__ void mixed_body(const MixedI &I, const float4 &b0, co
   C.Pf[0] += wrn * gx;
   C.Pf[1] += wrn * gy;
   if (DIM == 3) C.Pf[2] += wrn * gz;
-  if (FEAT) {
-    C.S0f += wr * b1.w;  // W / W(dx) V
-    S.qmin = fminf(S.qmin, s);
-    S.ndum += j >= nf ? 1u : 0u;
-  }
 }
 
 // Sums of the single-precision form (SPH_FP32) that the mixed form keeps in
@@ -442,10 +432,10 @@ __device__ __forceinline__ void abs32_flush(const Abs32Chunk &A, PairSums &S) {
 // the difference of the absolute FP32 positions, phi_j - phi_i that of the
 // FP32 potentials, and every sum of Eq. (sph) is an FP32 sum over the list
 // fill.  Only the totals over the fills and the epilogue are FP64.
-template <int DIM, bool FEAT, bool PST4>
+template <int DIM, bool PST4>
 __device__ __forceinline__ void abs32_body(const MixedI &I, const float4 &xi, const float phii, const float4 &xj,
-                                           const float4 &b1, const float phij, const uint32_t j, const uint32_t nf,
-                                           MixedChunk &C, Abs32Chunk &A, PairSums &S) {
+                                           const float4 &b1, const float phij, MixedChunk &C, Abs32Chunk &A,
+                                           PairSums &S) {
   const float rx = xj.x - xi.x, ry = xj.y - xi.y, rz = DIM == 3 ? xj.z - xi.z : 0.f;
   const float r2 = rx * rx + ry * ry + rz * rz;
   S.coincident |= (r2 == 0.f);
@@ -495,18 +485,13 @@ __device__ __forceinline__ void abs32_body(const MixedI &I, const float4 &xi, co
   C.Pf[0] += wrn * gx;
   C.Pf[1] += wrn * gy;
   if (DIM == 3) C.Pf[2] += wrn * gz;
-  if (FEAT) {
-    C.S0f += wr * b1.w;
-    S.qmin = fminf(S.qmin, s);
-    S.ndum += j >= nf ? 1u : 0u;
-  }
 }
 
 // The mixed pair pass with its own candidate search (FP32 test on the
 // absolute FP32 positions).  ABS: the single-precision form's body.  KEEP: as for the FP64 pass -- search radius
 // 2h + skin, tagged skin candidates skipped by the body, non-empty list
 // fills kept in kl.
-template <int DIM, bool FEAT, bool PST4, bool KEEP, bool ABS = false>
+template <int DIM, bool PST4, bool KEEP, bool ABS = false>
 __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     k_pair_mixed(Phys P, Grid g, MixedRec rec, const uint32_t *__restrict__ cs_f, const uint32_t *__restrict__ cs_d,
                  uint32_t nf, Scalars *sc, Rates out, uint32_t *__restrict__ cand, KeptLists kl) {
@@ -547,8 +532,16 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
       const int chunk = (int)(book >> kKeptNchShift);
       const bool room = chunk < kKeepChunks;
       uint32_t *dst = kl.ent + kept_entry(i, min(chunk, kKeepChunks - 1), 0);
-      for (int k = 0; k < kmax; ++k)
-        if (room && k < cnt) dst[(size_t)k * 64u] = list[k][tid];
+      // eight LDS reads in flight before their stores (read per entry, the
+      // copy waited out the LDS latency once per entry)
+      for (int k0 = 0; k0 < kmax; k0 += 8) {
+        uint32_t e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = list[min(k0 + u, kMList - 1)][tid];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (room && k0 + u < cnt) dst[(size_t)(k0 + u) * 64u] = e[u];
+      }
       if (cnt > 0) {
         if (room) book |= (unsigned long long)cnt << (6 * chunk);
         else sc->vovf = 1u;
@@ -566,7 +559,7 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
         const uint32_t e = list[k][tid];
         if (KEEP && (e & kSkinTag)) continue;
         const uint32_t j = e;
-        abs32_body<DIM, FEAT, PST4>(I, axa, phif, rec.xa[j], rec.r1[j], (float)rec.phi[j], j, nf, C, A, S);
+        abs32_body<DIM, PST4>(I, axa, phif, rec.xa[j], rec.r1[j], (float)rec.phi[j], C, A, S);
         if (KEEP) S.nnb += 1;
       }
       abs32_flush(A, S);
@@ -575,7 +568,7 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
         const uint32_t e = list[k][tid];
         if (KEEP && (e & kSkinTag)) continue;
         const uint32_t j = e;
-        mixed_body<DIM, FEAT, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], j, nf, C, S);
+        mixed_body<DIM, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], C, S);
         if (KEEP) S.nnb += 1;
       }
     }
@@ -613,13 +606,13 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     const int nch = min((int)(book >> kKeptNchShift), kKeepChunks);
     kl.cnt[i] = (book & ((1ull << kKeptNchShift) - 1ull)) | ((unsigned long long)nch << kKeptNchShift);
   }
-  pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
+  pair_epilogue<DIM>(P, sc, out, cand, i, active, S);
 }
 
 // A right-hand side from kept candidates: the same FP32 test as the search,
 // on the refreshed records, then the same body, one FP32 chunk sum per kept
 // chunk.  ABS: the single-precision form's body.
-template <int DIM, bool FEAT, bool PST4, bool ABS = false>
+template <int DIM, bool PST4, bool ABS = false>
 __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     k_pair_kept_mixed(Phys P, Grid g, MixedRec rec, uint32_t nf, Scalars *sc, Rates out,
                       uint32_t *__restrict__ cand, KeptLists kl) {
@@ -666,9 +659,9 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
       const float dx = b.x - axa.x, dy = b.y - axa.y, dz = DIM == 3 ? b.z - axa.z : 0.f;
       if (dx * dx + dy * dy + dz * dz <= two_h2) {
         if constexpr (ABS)
-          abs32_body<DIM, FEAT, PST4>(I, axa, (float)phii, b, rec.r1[j], (float)rec.phi[j], j, nf, C, A, S);
+          abs32_body<DIM, PST4>(I, axa, (float)phii, b, rec.r1[j], (float)rec.phi[j], C, A, S);
         else
-          mixed_body<DIM, FEAT, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], j, nf, C, S);
+          mixed_body<DIM, PST4>(I, rec.r0[j], rec.r1[j], rec.phi[j], C, S);
         S.nnb += 1;
       }
     }
@@ -676,10 +669,10 @@ __global__ void __launch_bounds__(256) WB_MIXED_ATTR
     chunk_flush(C, S);
     S.ntest += (uint32_t)cnt;
   }
-  pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, (double)a1.w, S);
+  pair_epilogue<DIM>(P, sc, out, cand, i, active, S);
 }
 
-template <int DIM, bool FEAT>
+template <int DIM>
 void launch_pair_mixed_inst(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                             const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
                             const KeptLists &kl, int mode, bool abs32, hipStream_t s) {
@@ -688,65 +681,57 @@ void launch_pair_mixed_inst(const Phys &P, const Grid &g, const MixedRec &rec, c
   if (abs32) {
     if (mode == kPairSearch) {
       if (p4)
-        hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
+        hipLaunchKernelGGL((k_pair_mixed<DIM, true, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
                            out, cand, kl);
       else
-        hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf,
+        hipLaunchKernelGGL((k_pair_mixed<DIM, false, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf,
                            sc, out, cand, kl);
     } else if (mode == kPairSearchKeep) {
       if (p4)
-        hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
+        hipLaunchKernelGGL((k_pair_mixed<DIM, true, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
                            out, cand, kl);
       else
-        hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
+        hipLaunchKernelGGL((k_pair_mixed<DIM, false, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc,
                            out, cand, kl);
     } else {
       if (p4)
-        hipLaunchKernelGGL((k_pair_kept_mixed<DIM, FEAT, true, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
+        hipLaunchKernelGGL((k_pair_kept_mixed<DIM, true, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
       else
-        hipLaunchKernelGGL((k_pair_kept_mixed<DIM, FEAT, false, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand,
+        hipLaunchKernelGGL((k_pair_kept_mixed<DIM, false, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand,
                            kl);
     }
   } else if (mode == kPairSearch) {
     if (p4)
-      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
+      hipLaunchKernelGGL((k_pair_mixed<DIM, true, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
                          cand, kl);
     else
-      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
+      hipLaunchKernelGGL((k_pair_mixed<DIM, false, false>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
                          cand, kl);
   } else if (mode == kPairSearchKeep) {
     if (p4)
-      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
+      hipLaunchKernelGGL((k_pair_mixed<DIM, true, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
                          cand, kl);
     else
-      hipLaunchKernelGGL((k_pair_mixed<DIM, FEAT, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
+      hipLaunchKernelGGL((k_pair_mixed<DIM, false, true>), gr, bl, 0, s, P, g, rec, cs_f, cs_d, nf, sc, out,
                          cand, kl);
   } else {
     if (p4)
-      hipLaunchKernelGGL((k_pair_kept_mixed<DIM, FEAT, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
+      hipLaunchKernelGGL((k_pair_kept_mixed<DIM, true>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
     else
-      hipLaunchKernelGGL((k_pair_kept_mixed<DIM, FEAT, false>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
+      hipLaunchKernelGGL((k_pair_kept_mixed<DIM, false>), gr, bl, 0, s, P, g, rec, nf, sc, out, cand, kl);
   }
 }
 
 hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,
                              const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out, uint32_t *cand,
-                             bool features, int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s,
-                             bool abs32) {
+                             int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s, bool abs32) {
   if (nf == 0) return hipSuccess;
   if (mode != kPairSearch && (!kent || !kcnt)) return hipErrorInvalidValue;
   KeptLists kl{kent, kcnt};
-  if (P.dim == 2) {
-    if (features)
-      launch_pair_mixed_inst<2, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
-    else
-      launch_pair_mixed_inst<2, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
-  } else {
-    if (features)
-      launch_pair_mixed_inst<3, true>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
-    else
-      launch_pair_mixed_inst<3, false>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
-  }
+  if (P.dim == 2)
+    launch_pair_mixed_inst<2>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
+  else
+    launch_pair_mixed_inst<3>(P, g, rec, cs_f, cs_d, nf, sc, out, cand, kl, mode, abs32, s);
   return hipGetLastError();
 }
 
@@ -809,8 +794,7 @@ hipError_t launch_scan_mixed(const Phys &P, const Grid &g, const MixedRec &rec, 
                              const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
                              const Rates &out, Scalars *sc, hipStream_t s) {
   if (nf == 0) return hipSuccess;
-  unsigned blocks = grid_for(nf);
-  if (blocks > 2048) blocks = 2048;
+  unsigned blocks = candidate_grid(nf);
   if (P.dim == 2)
     hipLaunchKernelGGL(k_scan_mixed<2>, dim3(blocks), dim3(kBlock), 0, s, P, g, rec, cs_f, cs_d, nf, list, count, out,
                        sc);

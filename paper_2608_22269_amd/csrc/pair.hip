@@ -32,14 +32,9 @@ namespace wb {
 #ifndef WB_PAIR_UNROLL
 #define WB_PAIR_UNROLL 1
 #endif
-// waves per SIMD the register allocation targets (plain instance / the one
-// with the classifier sums; 4 measured faster for both, despite a few spills
-// in the latter)
+// waves per SIMD the register allocation targets (4 measured fastest)
 #ifndef WB_PAIR_WAVES
 #define WB_PAIR_WAVES 4
-#endif
-#ifndef WB_PAIR_WAVES_FEAT
-#define WB_PAIR_WAVES_FEAT 4
 #endif
 // waves per SIMD of the pass from kept lists (2, 3 and 4 measured equal: its
 // record gathers bound it, not latency)
@@ -49,7 +44,7 @@ namespace wb {
 constexpr int kList = kPairList;       // LDS list entries per lane
 constexpr int kBatch = WB_PAIR_BATCH;  // candidates fetched per search iteration
 static_assert(kBatch <= kRecPad, "batched candidate loads run at most kRecPad records past a run");
-#define WB_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(FEAT ? WB_PAIR_WAVES_FEAT : WB_PAIR_WAVES)))
+#define WB_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(WB_PAIR_WAVES)))
 
 // ------------------------------------------------------------------ mirror
 
@@ -129,9 +124,9 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
 // Dense pair body: every sum of Eq. (sph) for neighbour j (records b0, b1) of
 // particle i (records a0, a1).  PST4: the shifting exponent is 4 (the paper's
 // value), evaluated as two squarings; otherwise pow().
-template <int DIM, bool FEAT, bool PST4>
+template <int DIM, bool PST4>
 __device__ __forceinline__ void pair_body_f64(const Phys &P, const double4 &a0, const double4 &a1, const double4 &b0,
-                                              const double4 &b1, const uint32_t j, const uint32_t nf, PairSums &S) {
+                                              const double4 &b1, PairSums &S) {
   const double rx = b0.x - a0.x, ry = b0.y - a0.y, rz = DIM == 3 ? b0.z - a0.z : 0.0;
   // membership was decided by the exact test; here |r| only feeds W and K
   const double r2 = DIM == 3 ? fma(rx, rx, fma(ry, ry, rz * rz)) : fma(rx, rx, ry * ry);
@@ -188,11 +183,6 @@ __device__ __forceinline__ void pair_body_f64(const Phys &P, const double4 &a0, 
   S.Ps[0] += wrn * gx;
   S.Ps[1] += wrn * gy;
   if (DIM == 3) S.Ps[2] += wrn * gz;
-  if (FEAT) {
-    S.S0 += (float)(wr * b1.w);  // W / W(dx) V
-    S.qmin = fminf(S.qmin, (float)s);
-    S.ndum += j >= nf ? 1u : 0u;
-  }
 }
 
 // The pair pass with its own candidate search (Algorithm 1).  KEEP (the
@@ -201,7 +191,7 @@ __device__ __forceinline__ void pair_body_f64(const Phys &P, const double4 &a0, 
 // are skipped by the body, and every non-empty list fill is also copied to kl
 // for the later right-hand sides; a lane with more than kKeepChunks fills
 // raises sc->vovf.
-template <int DIM, bool FEAT, bool PST4, bool KEEP>
+template <int DIM, bool PST4, bool KEEP>
 __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, const double4 *__restrict__ rec0,
                                                   const double4 *__restrict__ rec1, const uint32_t *__restrict__ cs_f,
                                                   const uint32_t *__restrict__ cs_d, uint32_t nf, Scalars *sc,
@@ -237,8 +227,16 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
       const int chunk = (int)(book >> kKeptNchShift);
       const bool room = chunk < kKeepChunks;
       uint32_t *dst = kl.ent + kept_entry(i, min(chunk, kKeepChunks - 1), 0);
-      for (int k = 0; k < kmax; ++k)
-        if (room && k < cnt) dst[(size_t)k * 64u] = list[k][tid];
+      // eight LDS reads in flight before their stores (read per entry, the
+      // copy waited out the LDS latency once per entry)
+      for (int k0 = 0; k0 < kmax; k0 += 8) {
+        uint32_t e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = list[min(k0 + u, kList - 1)][tid];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (room && k0 + u < cnt) dst[(size_t)(k0 + u) * 64u] = e[u];
+      }
       if (cnt > 0) {
         if (room) book |= (unsigned long long)cnt << (6 * chunk);
         else sc->vovf = 1u;
@@ -254,7 +252,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
       const double4 b0 = rec0[j], b1 = rec1[j];
       if (k + 1 < cnt) en = list[k + 1][tid];
       if (!KEEP || !(e & kSkinTag)) {
-        pair_body_f64<DIM, FEAT, PST4>(P, a0, a1, b0, b1, j, nf, S);
+        pair_body_f64<DIM, PST4>(P, a0, a1, b0, b1, S);
         if (KEEP) S.nnb += 1;
       }
     }
@@ -285,7 +283,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
     kl.cnt[i] = (book & ((1ull << kKeptNchShift) - 1ull)) | ((unsigned long long)nch << kKeptNchShift);
   }
 
-  pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
+  pair_epilogue<DIM>(P, sc, out, cand, i, active, S);
 }
 
 // A right-hand side from kept candidates (no search): the records hold the
@@ -294,7 +292,7 @@ __global__ void __launch_bounds__(256) WB_PAIR_ATTR k_pair_f64(Phys P, Grid g, c
 // the lists only while twice the bound on any particle's move since the build
 // fits the skin: a pair within 2h now was within 2h + skin then, so the
 // neighbour sets are those of a fresh search.
-template <int DIM, bool FEAT, bool PST4>
+template <int DIM, bool PST4>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WB_KEPT_WAVES))) k_pair_kept_f64(Phys P, const double4 *__restrict__ rec0,
                                                                     const double4 *__restrict__ rec1, uint32_t nf,
                                                                     Scalars *sc, Rates out,
@@ -332,16 +330,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WB_KEP
       const double4 b0 = rec0[j], b1 = rec1[j];
       if (k + 1 < cnt) en = list[k + 1][tid];
       if (dist2_exact<DIM>(b0.x - a0.x, b0.y - a0.y, DIM == 3 ? b0.z - a0.z : 0.0) <= P.two_h2) {
-        pair_body_f64<DIM, FEAT, PST4>(P, a0, a1, b0, b1, j, nf, S);
+        pair_body_f64<DIM, PST4>(P, a0, a1, b0, b1, S);
         S.nnb += 1;
       }
     }
     S.ntest += (uint32_t)cnt;
   }
-  pair_epilogue<DIM, FEAT>(P, sc, out, cand, i, active, a1.w, S);
+  pair_epilogue<DIM>(P, sc, out, cand, i, active, S);
 }
 
-template <int DIM, bool FEAT>
+template <int DIM>
 void launch_pair_f64_inst(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                           const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
                           uint32_t *cand, const KeptLists &kl, int mode, hipStream_t s) {
@@ -349,55 +347,46 @@ void launch_pair_f64_inst(const Phys &P, const Grid &g, const double4 *rec0, con
   const bool p4 = P.pst_n == 4.0;
   if (mode == kPairSearch) {
     if (p4)
-      hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, true, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc,
-                         out, cand, kl);
+      hipLaunchKernelGGL((k_pair_f64<DIM, true, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand,
+                         kl);
     else
-      hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, false, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc,
-                         out, cand, kl);
+      hipLaunchKernelGGL((k_pair_f64<DIM, false, false>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out,
+                         cand, kl);
   } else if (mode == kPairSearchKeep) {
     if (p4)
-      hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, true, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc,
-                         out, cand, kl);
+      hipLaunchKernelGGL((k_pair_f64<DIM, true, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand,
+                         kl);
     else
-      hipLaunchKernelGGL((k_pair_f64<DIM, FEAT, false, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc,
-                         out, cand, kl);
+      hipLaunchKernelGGL((k_pair_f64<DIM, false, true>), gr, bl, 0, s, P, g, rec0, rec1, cs_f, cs_d, nf, sc, out,
+                         cand, kl);
   } else {
     if (p4)
-      hipLaunchKernelGGL((k_pair_kept_f64<DIM, FEAT, true>), gr, bl, 0, s, P, rec0, rec1, nf, sc, out, cand, kl);
+      hipLaunchKernelGGL((k_pair_kept_f64<DIM, true>), gr, bl, 0, s, P, rec0, rec1, nf, sc, out, cand, kl);
     else
-      hipLaunchKernelGGL((k_pair_kept_f64<DIM, FEAT, false>), gr, bl, 0, s, P, rec0, rec1, nf, sc, out, cand, kl);
+      hipLaunchKernelGGL((k_pair_kept_f64<DIM, false>), gr, bl, 0, s, P, rec0, rec1, nf, sc, out, cand, kl);
   }
 }
 
 hipError_t launch_pair_f64(const Phys &P, const Grid &g, const double4 *rec0, const double4 *rec1,
                            const uint32_t *cs_f, const uint32_t *cs_d, uint32_t nf, Scalars *sc, const Rates &out,
-                           uint32_t *cand, bool features, int mode, uint32_t *kent, unsigned long long *kcnt,
-                           hipStream_t s) {
+                           uint32_t *cand, int mode, uint32_t *kent, unsigned long long *kcnt, hipStream_t s) {
   if (nf == 0) return hipSuccess;
   if (mode != kPairSearch && (!kent || !kcnt)) return hipErrorInvalidValue;
   KeptLists kl{kent, kcnt};
-  if (P.dim == 2) {
-    if (features)
-      launch_pair_f64_inst<2, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
-    else
-      launch_pair_f64_inst<2, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
-  } else {
-    if (features)
-      launch_pair_f64_inst<3, true>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
-    else
-      launch_pair_f64_inst<3, false>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
-  }
+  if (P.dim == 2)
+    launch_pair_f64_inst<2>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
+  else
+    launch_pair_f64_inst<3>(P, g, rec0, rec1, cs_f, cs_d, nf, sc, out, cand, kl, mode, s);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------- classifier features
 
 // The 16 classifier features of a particle from the raw sums the pair-pass
-// epilogue left in its row (L, g = sum grad W V, the shifting sum P, the
-// kernel sum, the closest-neighbour q, the dummy fraction) and its
-// eigenvalues, normal and neighbour count: eigenvalues of L (3), det L,
-// kernel sum, neighbour count, |g| h, n.g h, tangential |g| h, n.L.n,
-// tr L - n.L.n, |L^-T g| h, n.G / |G|, dummy fraction, closest q, |P| h.
+// epilogue left in its row (L, g = sum grad W V, the shifting sum P) and its
+// eigenvalues, normal n and neighbour count: eigenvalues of L (3), det L,
+// n.P h, neighbour count, |g| h, n.g h, tangential |g| h, n.L.n,
+// tr L - n.L.n, |L^-T g| h, n.G / |G|, tangential |P| h, n.P / |P|, |P| h.
 // Rows of the device-counted list (count != nullptr) or rows 0 .. n - 1.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_features(Phys P, Rates out, const uint32_t *__restrict__ list,
@@ -410,30 +399,33 @@ __global__ void __launch_bounds__(256) k_features(Phys P, Rates out, const uint3
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
     const uint32_t i = list ? list[k] : k;
     float *f = out.feat + (size_t)i * kNFeat;
-    float raw[kNFeat - 1];
+    float raw[12];
 #pragma unroll
-    for (int c = 0; c < kNFeat - 1; ++c) raw[c] = f[c];
+    for (int c = 0; c < 12; ++c) raw[c] = f[c];
     const double L[6] = {raw[0], raw[1], raw[2], raw[3], raw[4], raw[5]};
     const double g[3] = {raw[6], raw[7], raw[8]}, Pv[3] = {raw[9], raw[10], raw[11]};
     const double n[3] = {out.nrm[0][i], out.nrm[1][i], DIM == 3 ? out.nrm[2][i] : 0.0};
     const double Lm[3][3] = {{L[0], L[3], L[4]}, {L[3], L[1], L[5]}, {L[4], L[5], L[2]}};
-    double ng = 0, gn2 = 0, nLn = 0, trL = 0, pn2 = 0, ngr = 0;
+    double ng = 0, gn2 = 0, nLn = 0, trL = 0, pn2 = 0, ngr = 0, nP = 0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       ng += n[a] * g[a];
       gn2 += g[a] * g[a];
       trL += Lm[a][a];
       pn2 += Pv[a] * Pv[a];
+      nP += n[a] * Pv[a];
       ngr += n[a] * G[a];
 #pragma unroll
       for (int b = 0; b < DIM; ++b) nLn += n[a] * Lm[a][b] * n[b];
     }
-    double gt2 = 0;  // tangential part by components (no cancellation)
+    double gt2 = 0, pt2 = 0;  // tangential parts by components (no cancellation)
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      const double t = g[a] - ng * n[a];
+      const double t = g[a] - ng * n[a], tp = Pv[a] - nP * n[a];
       gt2 += t * t;
+      pt2 += tp * tp;
     }
+    const double pm = sqrt(pn2);
     // |L^-T g| (L symmetric), or |g| where L is singular (the epilogue's rule)
     double ngv[3] = {g[0], g[1], g[2]};
     if (out.lam[0][i] > P.lambda_sing) {
@@ -449,7 +441,7 @@ __global__ void __launch_bounds__(256) k_features(Phys P, Rates out, const uint3
     f[1] = (float)out.lam[1][i];
     f[2] = (float)(DIM == 3 ? out.lam[2][i] : out.lam[1][i]);
     f[3] = (float)detL;
-    f[4] = raw[12];
+    f[4] = (float)(nP * P.h);
     f[5] = (float)out.nnb[i];
     f[6] = (float)(sqrt(gn2) * P.h);
     f[7] = (float)(ng * P.h);
@@ -458,9 +450,9 @@ __global__ void __launch_bounds__(256) k_features(Phys P, Rates out, const uint3
     f[10] = (float)(trL - nLn);
     f[11] = (float)(nn * P.h);
     f[12] = (float)(gg > 0.0 ? ngr / gg : 0.0);
-    f[13] = raw[14];
-    f[14] = raw[13];
-    f[15] = (float)(sqrt(pn2) * P.h);
+    f[13] = (float)(sqrt(pt2) * P.h);
+    f[14] = (float)(pm > 0.0 ? nP / pm : 0.0);
+    f[15] = (float)(pm * P.h);
   }
 }
 
@@ -529,8 +521,7 @@ hipError_t launch_scan_f64(const Phys &P, const Grid &g, const double4 *rec0, co
                            const uint32_t *cs_d, uint32_t nf, const uint32_t *list, const uint32_t *count,
                            const Rates &out, Scalars *sc, hipStream_t s) {
   if (nf == 0) return hipSuccess;
-  unsigned blocks = grid_for(nf);
-  if (blocks > 2048) blocks = 2048;
+  unsigned blocks = candidate_grid(nf);
   if (P.dim == 2)
     hipLaunchKernelGGL(k_scan_f64<2>, dim3(blocks), dim3(kBlock), 0, s, P, g, rec0, cs_f, cs_d, nf, list, count, out,
                        sc);

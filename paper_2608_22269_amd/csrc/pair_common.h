@@ -53,12 +53,10 @@ __device__ __forceinline__ size_t kept_entry(uint32_t i, int c, int k) {
 
 // Neighbour sums of one particle (FP64).  L and N are symmetric and packed
 // as (xx, yy, zz, xy, xz, yz); N holds N_ab + N_ba off the diagonal.  Ps is
-// sum (W / W(dx))^n grad W V (the shifting sum is gs + R Ps).  S0 (sum of
-// W / W(dx) V), qmin (closest distance) and ndum only feed the classifier.
+// sum (W / W(dx))^n grad W V (the shifting sum is gs + R Ps).
 struct PairSums {
   double L[6], gs[3], SR[3], SC[3], Ps[3], N[6], Ds;
-  float S0, qmin;  // classifier inputs only: FP32 is ample
-  uint32_t nnb, ndum, ntest;
+  uint32_t nnb, ntest;
   bool coincident;
 };
 
@@ -68,25 +66,24 @@ __device__ __forceinline__ void sums_zero(PairSums &S) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) S.gs[k] = S.SR[k] = S.SC[k] = S.Ps[k] = 0.0;
   S.Ds = 0.0;
-  S.S0 = 0.0f;
-  S.qmin = INFINITY;
-  S.nnb = S.ndum = S.ntest = 0;
+  S.nnb = S.ntest = 0;
   S.coincident = false;
 }
 
 // Must be reached by every lane of the wave (wave-level atomics at the end).
-template <int DIM, bool FEAT>
+template <int DIM>
 __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const Rates &out, uint32_t *cand,
-                                              uint32_t i, bool active, double Vi, const PairSums &S) {
+                                              uint32_t i, bool active, const PairSums &S) {
   const uint32_t flags = P.flags;
   double lam[3];
   eig_sym<DIM>(S.L, lam);
   const double lmin = lam[0];
-  // classifier inputs: the raw sums of the particles in the candidate window
-  // of lambda_min (every row when the features are exported), written here
-  // so that they need no registers later; k_features completes them
-  if (FEAT && active &&
-      ((flags & SPH_F_FEATURES) || (P.fs_mode != SPH_FS_NONE && lmin > P.lambda_lo && lmin <= P.lambda_hi))) {
+  // classifier inputs: the raw sums L, g and the shifting sum of the
+  // particles in the candidate window of lambda_min (every row when the
+  // features are exported), written here so that they need no registers
+  // later; k_features turns them into the sixteen features
+  if (((flags & SPH_F_FEATURES) || P.fs_mode == SPH_FS_LEARNED) && active &&
+      ((flags & SPH_F_FEATURES) || (lmin > P.lambda_lo && lmin <= P.lambda_hi))) {
     float *f = out.feat + (size_t)i * kNFeat;
 #pragma unroll
     for (int k = 0; k < 6; ++k) f[k] = (float)S.L[k];
@@ -95,9 +92,6 @@ __device__ __forceinline__ void pair_epilogue(const Phys &P, Scalars *sc, const 
       f[6 + a] = (float)S.gs[a];
       f[9 + a] = (float)(S.gs[a] + P.pst_R * S.Ps[a]);
     }
-    f[12] = (float)((double)S.S0 / P.w0inv + P.wself * Vi);  // sum W V, self term included
-    f[13] = (float)fmin((double)S.qmin * P.inv_h, 2.0);
-    f[14] = (float)(S.nnb > 0 ? (double)S.ndum / (double)S.nnb : 0.0);
   }
   const bool singular = lmin <= P.lambda_sing;
   const bool tic = (flags & SPH_F_TIC) && lmin < P.lambda_tic;

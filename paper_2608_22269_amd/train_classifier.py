@@ -8,7 +8,11 @@ tank), a 3D sloshing tank, and strongly disordered fluid blocks (lattice
 jitter 0.2-0.4 dx: candidates inside the fluid, mostly covered, supply the
 interior class), evaluated on the GPU; at every snapshot the particles lambda_min alone cannot
 decide (0.2 < lambda <= 0.75) are collected with their 16 features and the
-scan-region label.  Split: seeded 80/20.  Training: the library's FP32 HIP kernels (forward, backward, Adam),
+scan-region label.  Split: seeded 80/20 over blocks of consecutive snapshots
+(ten snapshots of one trajectory, or one disordered block, per group; 20% of
+each source's groups), so that no validation candidate has a neighbour in
+time in the training set.
+Training: the library's FP32 HIP kernels (forward, backward, Adam),
 weighted binary cross-entropy with class weights balancing the two labels.
 The fallback margin tau is the smallest |logit| threshold whose confident
 predictions misclassify at most `target` of the validation candidates; the
@@ -44,17 +48,18 @@ def collect(case, nsteps, every, label):
     import workloads as wl
 
     sim = Simulation(wl.with_params(case, features=True, fs_mode="exact"))
-    X, Y = [], []
+    X, Y, S = [], [], []
     for k in range(nsteps // every):
         sim.step(every)
         sim.eval_rates()
         f, y = candidate_samples(sim)
         X.append(f)
         Y.append(y)
+        S.append(np.full(len(y), k, np.int64))
         st = sim.stats()
         log(f"{label}: t={st['t']:.3f} s, max|U|={st['umax']:.3f}, candidates {len(y)} ({y.mean():.3f} surface)")
     sim.close()
-    return np.concatenate(X), np.concatenate(Y)
+    return np.concatenate(X), np.concatenate(Y), np.concatenate(S)
 
 
 def collect_disordered(seeds=(11, 12, 13, 14, 15, 16), sigmas=(0.2, 0.3, 0.4)):
@@ -64,7 +69,7 @@ def collect_disordered(seeds=(11, 12, 13, 14, 15, 16), sigmas=(0.2, 0.3, 0.4)):
     from paper_2608_22269_amd.learn import candidate_samples
     import workloads as wl
 
-    X, Y = [], []
+    X, Y, S = [], [], []
     for sd in seeds:
         for sg in sigmas:
             c = wl.box3d(0.01, (0.6, 0.4, 0.5), (0.6, 0.4, 0.3), delta_sph=True, pst=True, tic=True,
@@ -77,8 +82,9 @@ def collect_disordered(seeds=(11, 12, 13, 14, 15, 16), sigmas=(0.2, 0.3, 0.4)):
             sim.close()
             X.append(f)
             Y.append(y)
+            S.append(np.full(len(y), len(S), np.int64))
             log(f"disordered block sigma={sg} seed={sd}: candidates {len(y)} ({y.mean():.3f} surface)")
-    return np.concatenate(X), np.concatenate(Y)
+    return np.concatenate(X), np.concatenate(Y), np.concatenate(S)
 
 
 def initial_params(seed):
@@ -143,24 +149,35 @@ def main():
     t0 = time.time()
     db = wl.dambreak3d(dx=0.01)
     db = wl.with_params(db, cell_size=db["params"]["h"])
-    Xa, ya = collect(db, args.dambreak_steps, args.every, "dambreak3d")
+    Xa, ya, sa = collect(db, args.dambreak_steps, args.every, "dambreak3d")
     tall = wl.dambreak3d(dx=0.01, tank=(2.0, 0.6, 1.0), column=(0.5, 0.6, 0.6))
     tall = wl.with_params(tall, cell_size=tall["params"]["h"])
     tall_steps = min(args.dambreak_steps, 6000)  # t ~ 0.34 s: the front reaches the far wall
-    Xt, yt = collect(tall, tall_steps, args.every, "dambreak3d tall column")
+    Xt, yt, st = collect(tall, tall_steps, args.every, "dambreak3d tall column")
     sl = wl.slosh3d(dx=0.004, amp=0.02)
     sl = wl.with_params(sl, cell_size=sl["params"]["h"])
-    Xb, yb = collect(sl, 4000, 250, "slosh3d")
-    Xc, yc = collect_disordered()
+    Xb, yb, sb = collect(sl, 4000, 250, "slosh3d")
+    Xc, yc, sc = collect_disordered()
     X = np.concatenate([Xa, Xt, Xb, Xc]).astype(np.float32)
     y = np.concatenate([ya, yt, yb, yc]).astype(np.float32)
     names = ["dambreak3d", "dambreak3d_tall", "slosh3d", "disordered_blocks"]
     src = np.concatenate([np.full(len(v), k) for k, v in enumerate((ya, yt, yb, yc))])
+    # groups: blocks of ten consecutive snapshots of a trajectory; each
+    # disordered block on its own
+    grp = np.concatenate([sa // 10, st // 10, sb // 10, sc]) + 1000 * src
+    ugrp = np.unique(grp)
     rng = np.random.default_rng(0)
-    idx = rng.permutation(len(y))
-    ntr = int(0.8 * len(y))
-    tr_i, va_i = idx[:ntr], idx[ntr:]
-    log(f"{len(y)} labelled candidates ({y.mean():.3f} surface); train {ntr}, validation {len(va_i)}")
+    # 20% of each source's groups (at least one), so every source is validated
+    val_groups = []
+    for k in range(len(names)):
+        gk = ugrp[ugrp // 1000 == k]
+        val_groups.extend(rng.permutation(gk)[: max(1, int(round(0.2 * len(gk))))].tolist())
+    val_groups = np.array(val_groups)
+    is_val = np.isin(grp, val_groups)
+    tr_i, va_i = np.nonzero(~is_val)[0], np.nonzero(is_val)[0]
+    ntr = len(tr_i)
+    log(f"{len(y)} labelled candidates ({y.mean():.3f} surface) in {len(ugrp)} snapshot groups; "
+        f"train {ntr}, validation {len(va_i)} ({len(val_groups)} groups)")
     params, mean, std, hist = train(X[tr_i], y[tr_i], epochs=args.epochs)
     lg = infer_bf16(params, mean, std, X[va_i]).cpu().numpy()
     yv = y[va_i]
@@ -182,7 +199,9 @@ def main():
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.savez(args.out, params=params, mean=mean, std=std, margin=np.float32(tau))
     report = {"n_samples": int(len(y)), "surface_fraction": float(y.mean()), "n_train": int(ntr),
-              "n_val": int(len(va_i)), "loss_history": hist, "val_misclassification_raw": err_raw,
+              "n_val": int(len(va_i)), "split": "by blocks of ten consecutive snapshots (seeded 80/20 per source over "
+                                                 f"{len(ugrp)} groups, {len(val_groups)} for validation)",
+              "loss_history": hist, "val_misclassification_raw": err_raw,
               "margin": tau, "val_confident_fraction": float(conf.mean()),
               "val_misclassification_with_fallback": err_conf, "val_per_source": per_source,
               "seconds": time.time() - t0, "epochs": args.epochs,

@@ -53,6 +53,7 @@ def stub_detail():
         "dambreak_detection": {"exact": {"ms_per_step": 2.13}, "learned": {"ms_per_step": 2.08,
                                                                           "misclassification": {"candidates": 21683,
                                                                                                 "misclassified": 15}}},
+        "slosh_surface_detection": {"candidates": 412000, "misclassified": 17, "fallback_exact": 9000},
         "dambreak_wall_pressure": {"t": [k * 0.01 for k in range(70)], "p_fp64": [[1.0] * 4] * 70,
                                    "rms_diff_over_max_p": [0.1, 0.2, 0.26, 0.15], "stopped": {}},
         "spurious_u_tank2d": {p: {str(k): 1e-14 * 1.5 ** (k / 50) for k in range(50, 201, 50)}
@@ -88,6 +89,7 @@ def test_line_is_compact_and_complete():
 def test_line_without_side_measurements():
     d = stub_detail()
     for k in ("at_rest", "keep_across_steps", "moving_body", "mlp_inference_17_5M", "dambreak_detection",
+              "slosh_surface_detection",
               "dambreak_wall_pressure", "spurious_u_tank2d", "spurious_u_bump2d", "hydrostatic_l2_paper_cases",
               "cpu_baseline", "roofline_kept"):
         d.pop(k)

@@ -156,3 +156,30 @@ def test_trained_classifier_against_exact(learn):
     assert ex.stats()["n_scan"] == ncand
     assert st["n_scan"] <= 0.1 * ncand
     assert st["n_mlp"] + st["n_scan"] == ncand
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_mode_candidate_features_equal_exported(learn, precision):
+    """The learned mode computes the classifier inputs of its candidates only,
+    from the sums of its pair pass; they equal, bit for bit, the features
+    exported for every row (SPH_F_FEATURES) on a disordered box with walls
+    and a free surface."""
+    from paper_2608_22269_amd import Simulation
+    base = wl.random_velocity(wl.jitter(wl.box3d(0.02, (0.4, 0.3, 0.4), (0.4, 0.3, 0.2), delta_sph=True, pst=True,
+                                                 tic=True, fs_project=True, cont_uncorr=True, precision=precision),
+                                        0.1, 6), 0.05, 7)
+    full = Simulation(wl.with_params(base, fs_mode="exact", features=True))
+    full.eval_rates()
+    le = Simulation(wl.with_params(base, fs_mode="learned"))
+    th = omlp.init_params(3).astype(np.float32)
+    le.set_classifier(th, np.zeros(16), np.ones(16), np.inf)
+    le.eval_rates()
+    f = base["kind"] == 0
+    lam = le.field("lambda")[f, 0]
+    cand = (lam > 0.2) & (lam <= 0.75)
+    assert cand.sum() > 50
+    a = full.field("features")[f][cand].astype(np.float64)
+    b = le.field("features")[f][cand].astype(np.float64)
+    assert np.array_equal(a, b)
+    full.close()
+    le.close()

@@ -212,9 +212,12 @@ def slosh_omega(length=1.0, depth=0.28, factor=1.2):
     return w1 / factor
 
 
-def slosh3d(dx=0.002, tank=(1.0, 0.5, 0.56), depth=0.28, amp=0.005, **kw):
+def slosh3d(dx=0.002, tank=(1.0, 0.5, 0.56), depth=0.28, amp=0.005, surface_amp=0.0, **kw):
     """3D sloshing tank forced horizontally in its own frame: G(t) = (A w^2
-    sin wt, 0, -g).  At dx = 0.002: 17,500,000 fluid + 2,047,296 dummies."""
+    sin wt, 0, -g).  At dx = 0.002: 17,500,000 fluid + 2,047,296 dummies.
+    surface_amp > 0: the first sloshing mode's shape released from rest, the
+    free surface at depth + surface_amp cos(pi x / L) and the potential
+    hydrostatic below it, phi = g (eta(x) - z)."""
     kw.setdefault("delta_sph", True)
     kw.setdefault("pst", True)
     kw.setdefault("tic", True)
@@ -224,8 +227,22 @@ def slosh3d(dx=0.002, tank=(1.0, 0.5, 0.56), depth=0.28, amp=0.005, **kw):
     w = slosh_omega(tank[0], depth)
     kw.setdefault("forcing_amp", (amp, 0.0, 0.0))
     kw.setdefault("forcing_omega", w)
-    return box3d(dx, tank, (tank[0], tank[1], depth), name="slosh3d",
-                 desc=f"3D sloshing tank {tank}, depth {depth}, forcing A={amp} m, dx={dx}", **kw)
+    kw.setdefault("depth", depth)
+    case = box3d(dx, tank, (tank[0], tank[1], depth + surface_amp), name="slosh3d",
+                 desc=f"3D sloshing tank {tank}, depth {depth}, forcing A={amp} m, dx={dx}"
+                      + (f", surface {surface_amp} cos(pi x/L)" if surface_amp > 0 else ""), **kw)
+    if surface_amp <= 0.0:
+        return case
+    f = case["kind"] == 0
+    eta = depth + surface_amp * np.cos(math.pi * case["x"][:, 0] / tank[0])
+    keep = ~f | (case["x"][:, 2] < eta)
+    out = {k: (v[keep] if isinstance(v, np.ndarray) else v) for k, v in case.items()}
+    g = float(np.linalg.norm(case["params"]["gravity"]))
+    fk = out["kind"] == 0
+    out["phi"] = out["phi"].copy()
+    out["phi"][fk] = g * (eta[keep][fk] - out["x"][fk, 2])
+    out["meta"] = dict(case["meta"], n_fluid=int(fk.sum()), H=depth)
+    return out
 
 
 def jitter(case, sigma=0.1, seed=0):
