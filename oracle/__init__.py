@@ -87,7 +87,15 @@ class Params(C.Structure):
         ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3), ("cell_size", C.c_double),
         ("body_pieces", C.c_int32), ("pad2_", C.c_int32),
         ("body_t", C.c_double * 5), ("body_a", C.c_double * 12), ("body_b", C.c_double * 12),
+        ("body_free", C.c_int32), ("pad3_", C.c_int32),
+        ("body_mass", C.c_double), ("body_inertia", C.c_double * 6), ("body_c0", C.c_double * 3),
     ]
+
+
+class Body(C.Structure):
+    """State of a free rigid body: centre, unit quaternion (w, x, y, z),
+    velocity, angular velocity (world frame)."""
+    _fields_ = [("c", C.c_double * 3), ("q", C.c_double * 4), ("v", C.c_double * 3), ("w", C.c_double * 3)]
 
 
 class _Rates(C.Structure):
@@ -113,11 +121,11 @@ def _load(path):
     L.orc_eigvals.argtypes = [C.c_int, vp, vp]
     L.orc_eigvals.restype = None
     L.orc_eval_rates.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int, vp,
-                                 C.POINTER(_Rates)]
+                                 C.POINTER(_Rates), C.POINTER(Body)]
     L.orc_dt.restype = C.c_double
     L.orc_dt.argtypes = [P, C.c_int64, vp, vp]
     L.orc_step.argtypes = [P, C.c_int64, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_double),
-                           C.c_int32, C.c_double, C.c_int, C.POINTER(C.c_double)]
+                           C.c_int32, C.c_double, C.c_int, C.POINTER(C.c_double), C.POINTER(Body)]
     L.orc_body_motion.argtypes = [P, C.c_double, vp, vp]
     L.orc_body_motion.restype = None
     L.orc_num_threads.restype = C.c_int
@@ -174,7 +182,26 @@ def make_params(pd: dict) -> Params:
             rows = [list(r) + [0.0] * 3 for r in pd[name]]
             flat = [float(r[c]) for r in rows[:k] for c in range(3)]
             setattr(p, name, (C.c_double * 12)(*(flat + [0.0] * (12 - len(flat)))))
+    if pd.get("body_free"):
+        p.body_free = 1
+        p.body_mass = float(pd["body_mass"])
+        p.body_inertia = (C.c_double * 6)(*[float(v) for v in pd["body_inertia"]])
+        c0 = list(pd["body_c0"]) + [0.0] * 3
+        p.body_c0 = (C.c_double * 3)(*[float(v) for v in c0[:3]])
     return p
+
+
+def make_body(state):
+    """Body struct from a dict with c, q, v, w (missing components zero)."""
+    b = Body()
+    for k, nk in (("c", 3), ("q", 4), ("v", 3), ("w", 3)):
+        v = list(state.get(k, [1.0, 0.0, 0.0, 0.0] if k == "q" else [0.0] * nk)) + [0.0] * nk
+        setattr(b, k, (C.c_double * nk)(*[float(a) for a in v[:nk]]))
+    return b
+
+
+def body_dict(b):
+    return {k: np.array(getattr(b, k)[:]) for k in ("c", "q", "v", "w")}
 
 
 def _ptr(a):
@@ -258,7 +285,7 @@ def eval_rates(case, t=None, mode="cells", rows=None):
         "fs": np.zeros(n, dtype=np.int32), "tic": np.zeros(n, dtype=np.int32),
         "nnb": np.zeros(n, dtype=np.int32), "feat": np.zeros((n, NFEAT)),
         "fs_margin": np.zeros(n), "mir_phi": np.zeros(n), "mir_u": np.zeros((n, dim)),
-        "mir_src": np.zeros(n, dtype=np.int32), "scal": np.zeros(4),
+        "mir_src": np.zeros(n, dtype=np.int32), "scal": np.zeros(10),
     }
     r = _Rates(*[_ptr(out[k]) for k in ("acc", "dphi", "dushift", "lam", "normal", "fs", "tic", "nnb",
                                         "feat", "fs_margin", "mir_phi", "mir_u", "mir_src", "scal")])
@@ -266,11 +293,13 @@ def eval_rates(case, t=None, mode="cells", rows=None):
     if rows is not None:
         only = np.zeros(n, dtype=np.uint8)
         only[np.asarray(rows, dtype=np.int64)] = 1
+    body = make_body(case["body"]) if case.get("body") is not None else None
     st = lib().orc_eval_rates(C.byref(p), n, _ptr(x), _ptr(u), _ptr(phi), _ptr(m), _ptr(kind), _ptr(nd),
                               t, 0 if mode == "brute" else 1, _ptr(only) if only is not None else None,
-                              C.byref(r))
+                              C.byref(r), C.byref(body) if body is not None else None)
     _check(st, "eval_rates")
-    out["umax"], out["gmag"], out["t"], out["n_singular"] = out["scal"].tolist()
+    out["umax"], out["gmag"], out["t"], out["n_singular"] = out["scal"][:4].tolist()
+    out["body_force"], out["body_torque"] = out["scal"][4:7].copy(), out["scal"][7:10].copy()
     return out
 
 
@@ -299,12 +328,15 @@ def step(case, nsteps=1, dt_override=0.0, mode="cells"):
     p = make_params(case["params"])
     t = C.c_double(float(case.get("t", 0.0)))
     dtl = C.c_double(0.0)
+    body = make_body(case["body"]) if case.get("body") is not None else None
     st = lib().orc_step(C.byref(p), n, _ptr(x), _ptr(u), _ptr(phi), _ptr(m), _ptr(kind), _ptr(nd),
                         C.byref(t), int(nsteps), float(dt_override), 0 if mode == "brute" else 1,
-                        C.byref(dtl))
+                        C.byref(dtl), C.byref(body) if body is not None else None)
     _check(st, "step")
     out = dict(case)
     out.update({"x": x, "u": u, "phi": phi, "t": t.value, "mass": m, "dt": dtl.value})
+    if body is not None:
+        out["body"] = body_dict(body)
     return out
 
 

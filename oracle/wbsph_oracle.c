@@ -19,6 +19,8 @@
  *   walls           Sec. 2.4, Eq. (phiBn) and the slip mirror
  *   moving walls    Sec. 4 (aircraft ditching): a body moving along a
  *                   prescribed velocity history U(T) given piecewise
+ *   free body       Sec. 4 (cylinder water entry): a rigid body falling
+ *                   under gravity and the water's force and torque
  *   neighbours      Sec. 3, Eqs. (hashid), (ixyz), Algorithm 1
  *   eigenvalues     Sec. 3 (minimum eigenvalue of L), by Jacobi rotations
  * Readings of passages that are silent or garbled are noted where they are
@@ -63,7 +65,20 @@ typedef struct {
      * zero outside [T_0, T_K]; body_a / body_b hold 3 components per piece */
     int32_t body_pieces, pad2_;
     double body_t[5], body_a[12], body_b[12];
+    /* a rigid body of kind-2 dummies moving under G(t) and the water's force
+     * and torque (body_free != 0; the prescribed motion is then unused):
+     * mass, inertia tensor about the centre in the body frame (xx yy zz xy
+     * xz yz), and the centre of the pose the dummies are given in */
+    int32_t body_free, pad3_;
+    double body_mass, body_inertia[6], body_c0[3];
 } orc_params;
+
+/* State of the free body: centre, unit quaternion (w, x, y, z) of the
+ * rotation from the reference pose, velocity, angular velocity (world
+ * frame). */
+typedef struct {
+    double c[3], q[4], v[3], w[3];
+} orc_body;
 
 /* Outputs of one right-hand-side evaluation, one row per particle in the
  * caller's order.  Rows of dummy particles hold the mirrored phi / U and the
@@ -82,7 +97,9 @@ typedef struct {
     double *mir_phi;   /* n      dummies: mirrored phi                   */
     double *mir_u;     /* n*dim  dummies: mirrored U                     */
     int32_t *mir_src;  /* n      dummies: source fluid index or -1       */
-    double *scal;      /* 4      U_max, |G(t)|, t, singular count        */
+    double *scal;      /* 10     U_max, |G(t)|, t, singular count, force
+                                   (3) and torque (3) of the water on the
+                                   free body                             */
 } orc_rates;
 
 static const double ORC_PI = 3.14159265358979323846;
@@ -155,6 +172,49 @@ static double body_force_max(const orc_params *p) {
         if (sqrt(s2) > best) best = sqrt(s2);
     }
     return best;
+}
+
+/* Rotation matrix (row-major) of the unit quaternion q = (w, x, y, z). */
+static void quat_matrix(const double q[4], double R[9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+static void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Pose of a free-body dummy: x = c + R (x_ref - c0), n = R n_ref, and the
+ * wall velocity there, U_w = v + w x (x - c).  dim-component rows. */
+static void free_body_place(const orc_params *p, const orc_body *b, const double *xr, const double *nr, double *x,
+                            double *n, double *uw) {
+    int dim = p->dim;
+    double R[9], d0[3] = {0, 0, 0}, n0[3] = {0, 0, 0}, d[3], r[3], wr[3];
+    quat_matrix(b->q, R);
+    for (int a = 0; a < dim; ++a) {
+        d0[a] = xr[a] - p->body_c0[a];
+        n0[a] = nr[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+        d[a] = R[3 * a] * d0[0] + R[3 * a + 1] * d0[1] + R[3 * a + 2] * d0[2];
+        r[a] = R[3 * a] * n0[0] + R[3 * a + 1] * n0[1] + R[3 * a + 2] * n0[2];
+    }
+    cross3(b->w, d, wr);
+    for (int a = 0; a < dim; ++a) {
+        x[a] = b->c[a] + d[a];
+        n[a] = r[a];
+        uw[a] = b->v[a] + wr[a];
+    }
 }
 
 /* ---------------------------------------------------------- neighbours */
@@ -550,6 +610,8 @@ static void mirror_dummies(const orc_params *p, int64_t n, const double *x, cons
                            const double *phi, const uint8_t *kind, const double *nd, const double *G,
                            const double *Uw, const int64_t *off, const int32_t *ids, double *mphi,
                            double *mu, int32_t *msrc) {
+    /* nd: unit normals of every row; Uw: wall velocity of every row (used
+     * for kind 2) */
     int dim = p->dim;
 #pragma omp parallel for schedule(static)
     for (int64_t d = 0; d < n; ++d) {
@@ -576,7 +638,7 @@ static void mirror_dummies(const orc_params *p, int64_t n, const double *x, cons
         mphi[d] = phi[best] + gp;
         double un = 0.0;
         for (int a = 0; a < dim; ++a) {
-            double rel = u[best * dim + a] - (kind[d] == 2 ? Uw[a] : 0.0);
+            double rel = u[best * dim + a] - (kind[d] == 2 ? Uw[d * dim + a] : 0.0);
             un += rel * nd[d * dim + a];
         }
         for (int a = 0; a < dim; ++a) mu[d * dim + a] = u[best * dim + a] - un * nd[d * dim + a];
@@ -638,18 +700,37 @@ static int scan_region(const orc_params *p, int64_t i, const double *x, const do
  * kind 2 (the moving body) hold the body at T_0; they take part at their
  * position of time t, x + D(t). */
 int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const double *u,
-                   const double *phi, const double *mass, const uint8_t *kind, const double *nd,
-                   double t, int nbr_mode, const uint8_t *only, orc_rates *out) {
+                   const double *phi, const double *mass, const uint8_t *kind, const double *nd_in,
+                   double t, int nbr_mode, const uint8_t *only, orc_rates *out, const orc_body *body) {
     int dim = p->dim;
     if (dim != 2 && dim != 3) return ORC_EINVAL;
     if (only && nbr_mode == 0) return ORC_EINVAL;
-    double Db[3], Uw[3];
-    orc_body_motion(p, t, Db, Uw);
-    double *xw = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * dim);
-    if (!xw) return ORC_ENOMEM;
-    for (int64_t i = 0; i < n; ++i)
-        for (int a = 0; a < dim; ++a) xw[i * dim + a] = x_in[i * dim + a] + (kind[i] == 2 ? Db[a] : 0.0);
+    if (p->body_free && (!body || !(p->body_mass > 0.0))) return ORC_EINVAL;
+    /* kind-2 rows at the time t: the prescribed motion's translation, or
+     * the free body's pose (positions, rotated normals, wall velocities) */
+    double Db[3], Ub[3];
+    orc_body_motion(p, t, Db, Ub);
+    size_t nn_ = (size_t)(n > 0 ? n : 1);
+    double *xw = (double *)malloc(sizeof(double) * nn_ * dim);
+    double *ndw = (double *)malloc(sizeof(double) * nn_ * dim);
+    double *uww = (double *)malloc(sizeof(double) * nn_ * dim);
+    if (!xw || !ndw || !uww) {
+        free(xw); free(ndw); free(uww);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (kind[i] == 2 && p->body_free) {
+            free_body_place(p, body, x_in + i * dim, nd_in + i * dim, xw + i * dim, ndw + i * dim, uww + i * dim);
+            continue;
+        }
+        for (int a = 0; a < dim; ++a) {
+            xw[i * dim + a] = x_in[i * dim + a] + (kind[i] == 2 ? Db[a] : 0.0);
+            ndw[i * dim + a] = nd_in[i * dim + a];
+            uww[i * dim + a] = kind[i] == 2 ? Ub[a] : 0.0;
+        }
+    }
     const double *x = xw;
+    const double *nd = ndw;
     int64_t *off = NULL;
     int32_t *ids = NULL;
     int st;
@@ -660,7 +741,7 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const dou
          * neighbour lists (the wall mirror needs their lists) */
         uint8_t *rows = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
         if (!rows) {
-            free(xw);
+            free(xw); free(ndw); free(uww);
             return ORC_ENOMEM;
         }
         for (int64_t i = 0; i < n; ++i) rows[i] = (uint8_t)(only[i] && kind[i] == 0);
@@ -680,7 +761,7 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const dou
         free(rows);
     }
     if (st != ORC_OK) {
-        free(xw);
+        free(xw); free(ndw); free(uww);
         return st;
     }
 
@@ -694,13 +775,13 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const dou
     double *V = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     int32_t *src = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     if (!phiv || !uv || !V || !src) {
-        free(off); free(ids); free(phiv); free(uv); free(V); free(src); free(xw);
+        free(off); free(ids); free(phiv); free(uv); free(V); free(src); free(xw); free(ndw); free(uww);
         return ORC_ENOMEM;
     }
     for (int64_t i = 0; i < n; ++i) src[i] = -1;
     memcpy(phiv, phi, sizeof(double) * (size_t)n);
     memcpy(uv, u, sizeof(double) * (size_t)n * dim);
-    mirror_dummies(p, n, x, u, phi, kind, nd, G, Uw, off, ids, phiv, uv, src);
+    mirror_dummies(p, n, x, u, phi, kind, nd, G, uww, off, ids, phiv, uv, src);
     for (int64_t i = 0; i < n; ++i) {
         if (kind[i] != 0 && src[i] < 0) V[i] = 0.0;
         else V[i] = volume_of(p, mass[i], phiv[i]);
@@ -920,8 +1001,48 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const dou
         out->scal[1] = sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
         out->scal[2] = t;
         out->scal[3] = nsing;
+        for (int a = 4; a < 10; ++a) out->scal[a] = 0.0;
     }
-    free(off); free(ids); free(phiv); free(uv); free(V); free(src); free(xw);
+
+    /* Force and torque of the water on the free body.  Reading (the paper
+     * says the cylinder falls under gravity and the interaction force with
+     * the water, not how that force is formed): each dummy of the body gets
+     * the acceleration Eq. (sph) gives a particle with a truncated support,
+     * the conservative form (Sec. 2.3, the branch for lambda_min < 0.75),
+     * from its fluid neighbours, a_d = -sum_i (phi_i + phi_d) grad_d W_di V_i,
+     * with its mirrored potential; the body's force is sum_d m_d a_d and its
+     * torque about the centre sum_d (x_d - c) x m_d a_d.  The dummies' forces
+     * on one another are internal to the rigid body; fixed walls do not act
+     * on it.  Summed in ascending row order. */
+    if (p->body_free && out->scal) {
+        double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+        for (int64_t d = 0; d < n; ++d) {
+            if (kind[d] != 2 || src[d] < 0) continue;
+            double ad[3] = {0, 0, 0};
+            for (int64_t k = off[d]; k < off[d + 1]; ++k) {
+                int64_t i = ids[k];
+                if (kind[i] != 0) continue;
+                double r[3] = {0, 0, 0};
+                for (int a = 0; a < dim; ++a) r[a] = x[i * dim + a] - x[d * dim + a];
+                double q = sqrt(dist2(dim, x + d * dim, x + i * dim)) / h;
+                double Kq = orc_K(dim, h, q); /* grad_d W_di = K (x_i - x_d) */
+                for (int a = 0; a < dim; ++a) ad[a] -= (phiv[i] + phiv[d]) * Kq * r[a] * V[i];
+            }
+            double fd[3] = {0, 0, 0}, arm[3] = {0, 0, 0}, td[3];
+            for (int a = 0; a < dim; ++a) {
+                fd[a] = mass[d] * ad[a];
+                arm[a] = x[d * dim + a] - body->c[a];
+                F[a] += fd[a];
+            }
+            cross3(arm, fd, td);
+            for (int a = 0; a < 3; ++a) T[a] += td[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            out->scal[4 + a] = F[a];
+            out->scal[7 + a] = T[a];
+        }
+    }
+    free(off); free(ids); free(phiv); free(uv); free(V); free(src); free(xw); free(ndw); free(uww);
     return ORC_OK;
 }
 
@@ -981,31 +1102,90 @@ static void free_rates(orc_rates *r) {
     memset(r, 0, sizeof(*r));
 }
 
+/* Rates of the free body's state: dc/dt = v; dv/dt = F/M + G; dq/dt =
+ * (0, w) q / 2; dw/dt = I_w^-1 (T - w x I_w w) with I_w = R I_b R^T, the
+ * inertia tensor in the world frame (Euler's equations).  In 2D the body
+ * moves in the plane and turns about z only. */
+static void free_body_rates(const orc_params *p, const orc_body *b, const double F[3], const double T[3],
+                            const double G[3], orc_body *rate) {
+    int dim = p->dim;
+    const double *Ib = p->body_inertia;
+    double Bm[9] = {Ib[0], Ib[3], Ib[4], Ib[3], Ib[1], Ib[5], Ib[4], Ib[5], Ib[2]};
+    double R[9], RB[9], Iw[9];
+    quat_matrix(b->q, R);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += R[3 * i + k] * Bm[3 * k + j];
+            RB[3 * i + j] = acc;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += RB[3 * i + k] * R[3 * j + k];
+            Iw[3 * i + j] = acc;
+        }
+    double Lw[3], gyro[3], rhs[3];
+    for (int a = 0; a < 3; ++a) Lw[a] = Iw[3 * a] * b->w[0] + Iw[3 * a + 1] * b->w[1] + Iw[3 * a + 2] * b->w[2];
+    cross3(b->w, Lw, gyro);
+    for (int a = 0; a < 3; ++a) rhs[a] = T[a] - gyro[a];
+    for (int a = 0; a < 3; ++a) {
+        rate->c[a] = b->v[a];
+        rate->v[a] = F[a] / p->body_mass + G[a];
+    }
+    if (dim == 2) {
+        rate->c[2] = rate->v[2] = rate->w[0] = rate->w[1] = 0.0;
+        rate->w[2] = rhs[2] / Iw[8];
+    } else {
+        double Ii[9];
+        inverse_d(3, Iw, Ii);
+        for (int a = 0; a < 3; ++a) rate->w[a] = Ii[3 * a] * rhs[0] + Ii[3 * a + 1] * rhs[1] + Ii[3 * a + 2] * rhs[2];
+    }
+    /* (0, w) * q, Hamilton product */
+    const double *q = b->q, *w = b->w;
+    rate->q[0] = 0.5 * (-w[0] * q[1] - w[1] * q[2] - w[2] * q[3]);
+    rate->q[1] = 0.5 * (w[0] * q[0] + w[1] * q[3] - w[2] * q[2]);
+    rate->q[2] = 0.5 * (-w[0] * q[3] + w[1] * q[0] + w[2] * q[1]);
+    rate->q[3] = 0.5 * (w[0] * q[2] - w[1] * q[1] + w[2] * q[0]);
+}
+
+static void quat_normalise(double q[4]) {
+    double s = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int a = 0; a < 4; ++a) q[a] /= s;
+}
+
 /* SSP-RK2 (Sec. 2.3).  dt from U at t^n (dt_override > 0 replaces the
  * rule).  Stage 1 at t^n, stage 2 at t^n + dt (the body, kind 2, at its
  * positions of those times).  On return x, u, phi hold t^{n+nsteps} (dummy
- * rows untouched); *t advanced; *dt_last set. */
+ * rows untouched); *t advanced; *dt_last set.  A free body (body_free)
+ * advances with the same two stages, its force and torque taken at each
+ * right-hand side; its quaternion is renormalised after each stage. */
 int orc_step(const orc_params *p, int64_t n, double *x, double *u, double *phi, const double *mass,
              const uint8_t *kind, const double *nd, double *t, int32_t nsteps, double dt_override,
-             int nbr_mode, double *dt_last) {
+             int nbr_mode, double *dt_last, orc_body *body) {
     int dim = p->dim;
+    if (p->body_free && !body) return ORC_EINVAL;
     size_t nn = (size_t)(n > 0 ? n : 1);
     double *x0 = (double *)malloc(sizeof(double) * nn * dim);
     double *u0 = (double *)malloc(sizeof(double) * nn * dim);
     double *p0 = (double *)malloc(sizeof(double) * nn);
+    double scal[10];
     orc_rates r;
     int st = alloc_rates(&r, n, dim);
+    r.scal = scal;
     if (!x0 || !u0 || !p0 || st != ORC_OK) {
-        free(x0); free(u0); free(p0); free_rates(&r);
+        free(x0); free(u0); free(p0); r.scal = NULL; free_rates(&r);
         return ORC_ENOMEM;
     }
+    orc_body b0, b1, rt;
     for (int32_t s = 0; s < nsteps && st == ORC_OK; ++s) {
         double dt = dt_override > 0.0 ? dt_override : orc_dt(p, n, u, kind);
         memcpy(x0, x, sizeof(double) * nn * dim);
         memcpy(u0, u, sizeof(double) * nn * dim);
         memcpy(p0, phi, sizeof(double) * n);
+        double G[3];
         /* first stage */
-        st = orc_eval_rates(p, n, x, u, phi, mass, kind, nd, *t, nbr_mode, NULL, &r);
+        st = orc_eval_rates(p, n, x, u, phi, mass, kind, nd, *t, nbr_mode, NULL, &r, body);
         if (st != ORC_OK) break;
         for (int64_t i = 0; i < n; ++i) {
             if (kind[i] != 0) continue;
@@ -1015,8 +1195,21 @@ int orc_step(const orc_params *p, int64_t n, double *x, double *u, double *phi, 
                 x[i * dim + a] = x0[i * dim + a] + dt * (u0[i * dim + a] + r.dushift[i * dim + a]);
             }
         }
+        if (p->body_free) {
+            b0 = *body;
+            body_force(p, *t, G);
+            free_body_rates(p, &b0, scal + 4, scal + 7, G, &rt);
+            for (int a = 0; a < 3; ++a) {
+                b1.c[a] = b0.c[a] + dt * rt.c[a];
+                b1.v[a] = b0.v[a] + dt * rt.v[a];
+                b1.w[a] = b0.w[a] + dt * rt.w[a];
+            }
+            for (int a = 0; a < 4; ++a) b1.q[a] = b0.q[a] + dt * rt.q[a];
+            quat_normalise(b1.q);
+            *body = b1;
+        }
         /* second stage */
-        st = orc_eval_rates(p, n, x, u, phi, mass, kind, nd, *t + dt, nbr_mode, NULL, &r);
+        st = orc_eval_rates(p, n, x, u, phi, mass, kind, nd, *t + dt, nbr_mode, NULL, &r, body);
         if (st != ORC_OK) break;
         for (int64_t i = 0; i < n; ++i) {
             if (kind[i] != 0) continue;
@@ -1028,10 +1221,21 @@ int orc_step(const orc_params *p, int64_t n, double *x, double *u, double *phi, 
                                  0.5 * (x[i * dim + a] + dt * (u1 + r.dushift[i * dim + a]));
             }
         }
+        if (p->body_free) {
+            body_force(p, *t + dt, G);
+            free_body_rates(p, &b1, scal + 4, scal + 7, G, &rt);
+            for (int a = 0; a < 3; ++a) {
+                body->c[a] = 0.5 * b0.c[a] + 0.5 * (b1.c[a] + dt * rt.c[a]);
+                body->v[a] = 0.5 * b0.v[a] + 0.5 * (b1.v[a] + dt * rt.v[a]);
+                body->w[a] = 0.5 * b0.w[a] + 0.5 * (b1.w[a] + dt * rt.w[a]);
+            }
+            for (int a = 0; a < 4; ++a) body->q[a] = 0.5 * b0.q[a] + 0.5 * (b1.q[a] + dt * rt.q[a]);
+            quat_normalise(body->q);
+        }
         *t = *t + dt;
         if (dt_last) *dt_last = dt;
     }
-    free(x0); free(u0); free(p0); free_rates(&r);
+    free(x0); free(u0); free(p0); r.scal = NULL; free_rates(&r);
     return st;
 }
 

@@ -33,13 +33,13 @@ int main(int argc, char **argv) {
     fclose(in);
     orc_rates r;
     if (alloc_rates(&r, n, dim) != ORC_OK) return 4;
-    int st = orc_eval_rates(&p, n, x, u, phi, m, kind, nrm, t, 1, NULL, &r);
+    int st = orc_eval_rates(&p, n, x, u, phi, m, kind, nrm, t, 1, NULL, &r, NULL);
     if (st != ORC_OK) return 10 - st;
     FILE *out = fopen(argv[2], "wb");
     if (!out) return 2;
     if (!wr(out, r.acc, 8 * nv) || !wr(out, r.dphi, 8 * (size_t)n) || !wr(out, r.nnb, 4 * (size_t)n)) return 5;
     double dtl = 0.0;
-    st = orc_step(&p, n, x, u, phi, m, kind, nrm, &t, nsteps, 0.0, 1, &dtl);
+    st = orc_step(&p, n, x, u, phi, m, kind, nrm, &t, nsteps, 0.0, 1, &dtl, NULL);
     if (st != ORC_OK) return 20 - st;
     if (!wr(out, x, 8 * nv) || !wr(out, u, 8 * nv) || !wr(out, phi, 8 * (size_t)n)) return 5;
     fclose(out);

@@ -204,6 +204,23 @@ def dambreak3d(dx=0.01, tank=(3.22, 1.0, 1.0), column=(1.2, 1.0, 0.55), **kw):
                  desc=f"3D dam break, tank {tank}, column {column}, dx={dx}", **kw)
 
 
+def dambreak2d(dx=0.01, tank=(3.22, 1.0), column=(1.2, 0.55), **kw):
+    """2D dam break: the 3D case's vertical section, a column at rest against
+    the x = 0 wall of a closed tank (6,600 fluid at dx = 0.01)."""
+    kw.setdefault("c0", 30.0)
+    for k in ("delta_sph", "pst", "tic", "fs_project", "cont_uncorr"):
+        kw.setdefault(k, True)
+    kw.setdefault("fs_mode", "exact")
+    kw.setdefault("depth", column[1])
+    layers = 3
+    params = base_params(2, dx, domain_lo=[-layers * dx, -layers * dx, 0.0],
+                         domain_hi=[tank[0] + layers * dx, tank[1] + layers * dx, 0.0], **kw)
+    xf = _lattice([0, 0], [round(column[0] / dx), round(column[1] / dx)], dx)
+    xd, nd = _box_walls(2, dx, [round(tank[0] / dx), round(tank[1] / dx)], layers)
+    return _assemble(params, xf, xd, nd, column[1],
+                     {"name": "dambreak2d", "desc": f"2D dam break, tank {tank}, column {column}, dx={dx}"})
+
+
 def slosh_omega(length=1.0, depth=0.28, factor=1.2):
     """Forcing frequency for a period `factor` times the first natural sloshing
     period (linear theory: w1^2 = g k tanh(k d), k = pi / L)."""
