@@ -322,7 +322,7 @@ def _body_box(dim, lo, hi, dx, layers):
     pts, dlo, dhi, dmin, m = pts[keep], dlo[keep], dhi[keep], dmin[keep], m[keep]
     nrm = np.zeros_like(pts)
     near = dmin <= m[:, None] + 1e-9 * dx
-    nrm[near & (dlo < dhi)] = -1.0
+    nrm[near & (dlo <= dhi)] = -1.0  # a point midway between two faces takes the lower one
     nrm[near & (dhi < dlo)] = 1.0
     nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
     return pts, nrm
@@ -358,6 +358,31 @@ def with_body(case, lo, hi, motion, layers=3):
     meta.update({"n_fluid": int(((c["kind"] == 0)).sum()), "n_dummy": int((c["kind"] != 0).sum()),
                  "n_body": int(len(xb))})
     c["meta"] = meta
+    return c
+
+
+def with_free_body(case, lo, hi, density, v0=(0.0, 0.0, 0.0), w0=(0.0, 0.0, 0.0), layers=3):
+    """Copy of `case` with a solid box body [lo, hi] of kind-2 dummies that
+    moves under G(t) and the water's force and torque: mass density * volume
+    (area in 2D), the inertia tensor of the solid box about its centre, the
+    dummies given at the pose of the box, initial velocity v0 and angular
+    velocity w0 (world frame; in 2D only w0[2] is used).  Fluid particles
+    inside the box are removed."""
+    dim = case["params"]["dim"]
+    c = with_body(case, lo, hi, {"body_t": [], "body_a": [], "body_b": []}, layers=layers)
+    pd = c["params"]
+    for k in ("body_t", "body_a", "body_b"):
+        pd.pop(k, None)
+    ext = [float(b - a) for a, b in zip(lo[:dim], hi[:dim])] + [0.0] * (3 - dim)
+    vol = float(np.prod(ext[:dim]))
+    m = density * vol
+    a, b, cc = ext
+    inertia = [m * (b * b + cc * cc) / 12.0, m * (a * a + cc * cc) / 12.0, m * (a * a + b * b) / 12.0, 0.0, 0.0, 0.0]
+    centre = [0.5 * (float(lo[k]) + float(hi[k])) for k in range(dim)] + [0.0] * (3 - dim)
+    pd.update({"body_free": True, "body_mass": m, "body_inertia": inertia, "body_c0": centre})
+    c["body"] = {"c": list(centre), "q": [1.0, 0.0, 0.0, 0.0], "v": list(v0) + [0.0] * (3 - len(v0)),
+                 "w": list(w0) + [0.0] * (3 - len(w0))}
+    c["meta"]["desc"] = c["meta"].get("desc", "") + f"; free box body {lo}-{hi}, density {density}"
     return c
 
 
