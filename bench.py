@@ -101,7 +101,7 @@ def misclassification(sim, case, clf):
             "fs_exact": int(fs_e.sum()), "fs_learned": int(fs_l.sum())}
 
 
-def run_path(case, label, steps, warmup, clf=None):
+def run_path(case, label, steps, warmup, clf=None, after=None):
     import torch
     from paper_2608_22269_amd import Simulation
 
@@ -169,6 +169,8 @@ def run_path(case, label, steps, warmup, clf=None):
     if clf is not None:
         out["misclassification"] = misclassification(sim, case, clf)
         log(f"{label}: free-surface misclassification {out['misclassification']}")
+    if after is not None:
+        after(sim, out)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -509,6 +511,33 @@ def moving_body(dx, steps, warmup):
     return res
 
 
+def cylinder_entry_run(dx, cell, steps, warmup):
+    """The paper's cylinder water entry at its size (Sec. 4; dx = D/20 =
+    0.0025: 15.36M fluid + 2.37M dummies): a free solid cylinder (D = 0.05 m,
+    L = 0.2 m, density 1370) entering the water at 6.22 m/s, FP64 (the free
+    body's path), its force, torque and state at every right-hand side.  The
+    paper's figure for the same case (1000 steps in 270.31 s, FP32, one
+    RTX 3090) is context, not a target of the same precision."""
+    import workloads as wl
+    case = wl.cylinder_entry(3, dx=dx)
+    h = case["params"]["h"]
+    case = wl.with_params(case, cell_size=cell * h)
+    body0 = {k: list(map(float, v)) for k, v in case["body"].items()}
+
+    def after(sim, out):
+        st = sim.body_state()
+        out["body_end"] = {k: [float(a) for a in v] for k, v in st.items()}
+
+    res = {"workload": case["meta"]["desc"], "n_fluid": case["meta"]["n_fluid"],
+           "n_dummy": case["meta"]["n_dummy"], "n_body": case["meta"]["n_body"], "cell_size_over_h": cell,
+           "body_start": body0, "paper_ms_per_step": 270.31, "paper_particles": 17.53e6,
+           "paper_note": "1000 steps in 270.31 s on one RTX 3090, FP32 (Sec. 5, efficiency table)"}
+    res["fp64"] = run_path(case, "cylinder entry (fp64, free body)", steps, warmup, after=after)
+    res["particles"] = res["n_fluid"] + res["n_dummy"]
+    res["particle_steps_per_s"] = res["particles"] / (res["fp64"]["ms_per_step"] * 1e-3)
+    return res
+
+
 def _sig(v, n=4):
     """v rounded to n significant digits (non-floats pass through; non-finite
     floats become strings so that the line stays strict JSON)."""
@@ -615,6 +644,11 @@ def compact_line(d):
         line["moving_body"] = {"n_fluid": b["n_fluid"], "fp64_ms_per_step": _sig(b["fp64"]["ms_per_step"]),
                                "mixed_ms_per_step": _sig(b["mixed"]["ms_per_step"]),
                                "motion_cost_ms_per_step": _sig(b["motion_cost_ms_per_step"], 3)}
+    if d.get("cylinder_entry"):
+        c = d["cylinder_entry"]
+        line["cylinder_entry"] = {"n": c["particles"], "fp64_ms": _sig(c["fp64"]["ms_per_step"]),
+                                  "paper_ms_fp32_3090": c["paper_ms_per_step"],
+                                  "vz_end": _sig(c["fp64"].get("body_end", {}).get("v", [0, 0, 0])[2], 4)}
     if d.get("mlp_inference_17_5M"):
         m = d["mlp_inference_17_5M"]
         line["mlp_inference"] = {"rows": m["rows"], "ms_per_call": _sig(m["ms_per_call"]),
@@ -693,6 +727,8 @@ def main():
                     help="steps of the 2D Gaussian-bump spurious-velocity history (0: skip)")
     ap.add_argument("--body-dx", type=float, default=0.005,
                     help="particle spacing of the 3D moving-body run (3.82M fluid at 0.005; 0: skip)")
+    ap.add_argument("--cylinder-dx", type=float, default=0.0025,
+                    help="particle spacing of the cylinder water entry (the paper's D/20: 17.7M particles; 0: skip)")
     ap.add_argument("--mlp", action=argparse.BooleanOptionalAction, default=True,
                     help="standalone BF16 MLP inference over as many rows as the tank has fluid particles")
     ap.add_argument("--calib", action="store_true",
@@ -817,6 +853,8 @@ def main():
         }
     if args.body_dx > 0:
         d["moving_body"] = moving_body(args.body_dx, args.steps, args.warmup)
+    if args.cylinder_dx > 0:
+        d["cylinder_entry"] = cylinder_entry_run(args.cylinder_dx, args.cell, args.steps, args.warmup)
     if args.mlp:
         d["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:

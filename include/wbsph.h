@@ -133,6 +133,31 @@ typedef struct sph_params {
     double body_t[5];       /* breakpoints, strictly increasing                   */
     double body_a[4][3];
     double body_b[4][3];
+    /* A free rigid body made of the kind-2 dummies (the cylinder water entry
+     * of Sec. 4: the body falls under G(t) and the water's force), used when
+     * body_free != 0 (body_pieces must then be 0; precision SPH_FP64 only).
+     * The kind-2 rows are given in a reference pose whose centre is body_c0;
+     * a body state of centre c and unit quaternion q = (w, x, y, z) puts a
+     * dummy given at x_ref, n_ref at c + R(q)(x_ref - body_c0) with normal
+     * R(q) n_ref, and its wall velocity is v + omega x R(q)(x_ref - body_c0).
+     * Force on the body: each of its dummies with a mirror source takes the
+     * conservative-form acceleration of Eq. (sph) (the branch of Sec. 2.3)
+     * from its fluid neighbours, a_d = -sum_i (phi_i + phi_d) grad_d W_di
+     * V_i, with its mirrored potential; F = sum m_d a_d, torque about c =
+     * sum (x_d - c) x m_d a_d.  The state advances with the fluid's SSP-RK2
+     * stages: dc/dt = v, dv/dt = F/M + G(t), dq/dt = (0, omega) q / 2,
+     * domega/dt = I_w^-1 (T - omega x I_w omega), I_w = R I_body R^T; the
+     * quaternion is renormalised after each stage.  In 2D the body moves in
+     * the plane and turns about z: q = (cos, 0, 0, sin), omega = (0, 0, wz).
+     * The dummies are re-sorted at every right-hand side and
+     * SPH_F_KEEP_LISTS has no effect.                                        */
+    int32_t body_free;
+    int32_t body_pad2_;
+    double body_mass;        /* > 0                                                */
+    double body_inertia[6];  /* about the centre, body frame: xx yy zz xy xz yz;
+                                positive definite (2D: zz > 0)                    */
+    double body_c0[3];       /* centre of the reference pose                      */
+    double body_state0[13];  /* initial c[3], q[4] (unit), v[3], omega[3] (world) */
 } sph_params;
 
 typedef struct sph_ctx sph_ctx;
@@ -154,8 +179,8 @@ const char *sph_status_string(sph_status s);
  * x, u: n*dim doubles; phi: n doubles; mass: n doubles or NULL, in which case
  * m = rho0 exp(phi/C0^2) dx^dim (Sec. 2.2.1); kind: n bytes, 0 fluid, 1 fixed
  * dummy wall particle (Sec. 2.4), 2 dummy of the moving body (its position
- * of time body_t[0]); normal: n*dim doubles, the unit wall normal of each
- * dummy (fluid rows ignored).  inputs_on_device selects whether the
+ * of time body_t[0], or of the free body's reference pose); normal: n*dim
+ * doubles, the unit wall normal of each dummy (fluid rows ignored).  inputs_on_device selects whether the
  * six arrays are device (1) or host (0) pointers; they are copied and may be
  * released after the call.  workspace: a device buffer of ws_bytes >=
  * sph_workspace_bytes(), 256-byte aligned.  hip_stream: the stream all work
@@ -242,6 +267,14 @@ sph_status sph_fields(sph_ctx *ctx, int32_t field, void *out, int32_t out_on_dev
  * [13] for the last right-hand side that searched, [18] and [19] for the last
  * one that ran from kept lists (tests: kept candidates).  Synchronises. */
 sph_status sph_stats(sph_ctx *ctx, double out[20]);
+
+/* State of the free body (body_free) after the last right-hand side or step:
+ * out[0..2] centre c, [3..6] unit quaternion (w, x, y, z), [7..9] velocity,
+ * [10..12] angular velocity (world frame), [13..15] force and [16..18]
+ * torque about the centre of the water on the body at the last right-hand
+ * side (zero before any).  Host output; synchronises.  SPH_ESTATE without a
+ * free body. */
+sph_status sph_body_state(sph_ctx *ctx, double out[19]);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * each launch group while enabled: [0] pair pass with its own search, [1]

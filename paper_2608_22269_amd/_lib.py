@@ -49,6 +49,8 @@ class SphParams(C.Structure):
         ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3), ("cell_size", C.c_double),
         ("body_pieces", C.c_int32), ("body_pad_", C.c_int32), ("body_t", C.c_double * 5),
         ("body_a", (C.c_double * 3) * 4), ("body_b", (C.c_double * 3) * 4),
+        ("body_free", C.c_int32), ("body_pad2_", C.c_int32), ("body_mass", C.c_double),
+        ("body_inertia", C.c_double * 6), ("body_c0", C.c_double * 3), ("body_state0", C.c_double * 13),
     ]
 
 
@@ -87,6 +89,7 @@ def lib():
         "sph_set_time": (i32, [vp, C.c_double]),
         "sph_fields": (i32, [vp, i32, vp, i32]),
         "sph_stats": (i32, [vp, vp]),
+        "sph_body_state": (i32, [vp, vp]),
         "sph_neighbors": (i32, [vp, vp, vp, i64, C.POINTER(i64)]),
         "sph_profile": (i32, [vp, i32]),
         "sph_profile_read": (i32, [vp, vp]),
@@ -115,14 +118,15 @@ def exported_symbols():
     return [
         "sph_validate", "sph_workspace_bytes", "sph_status_string", "sph_init", "sph_destroy",
         "sph_last_error", "sph_build_cells", "sph_step", "sph_eval_rates", "sph_sync", "sph_set_time", "sph_fields",
-        "sph_stats", "sph_neighbors", "sph_profile", "sph_profile_read", "sph_set_classifier", "sph_mlp_workspace_bytes", "sph_mlp_create",
+        "sph_stats", "sph_body_state", "sph_neighbors", "sph_profile", "sph_profile_read", "sph_set_classifier", "sph_mlp_workspace_bytes", "sph_mlp_create",
         "sph_mlp_destroy", "sph_mlp_forward", "sph_mlp_loss_grad", "sph_mlp_adam", "sph_mlp_train_epoch",
         "sph_mlp_get_params", "sph_mlp_infer_bf16", "sph_mlp_forward_noalloc",
     ]
 
 
-def params_from_dict(pd: dict) -> SphParams:
-    """sph_params from the plain parameter dictionary of a workload."""
+def params_from_dict(pd: dict, body: dict | None = None) -> SphParams:
+    """sph_params from the plain parameter dictionary of a workload; body:
+    the free body's initial state {"c", "q", "v", "w"} (with body_free)."""
     p = SphParams()
     p.dim = int(pd["dim"])
     p.precision = {"fp64": SPH_FP64, "mixed": SPH_MIXED, "fp32": SPH_FP32}[pd.get("precision", "fp64")]
@@ -149,6 +153,21 @@ def params_from_dict(pd: dict) -> SphParams:
             for k, row in enumerate(list(pd[name])[:4]):
                 for c, v in enumerate(list(row)[:3]):
                     arr[k][c] = float(v)
+    if pd.get("body_free"):
+        if body is None:
+            raise ValueError("a free body needs its initial state")
+        p.body_free = 1
+        p.body_mass = float(pd["body_mass"])
+        for k, v in enumerate(list(pd["body_inertia"])[:6]):
+            p.body_inertia[k] = float(v)
+        for k, v in enumerate(list(pd["body_c0"])[:3]):
+            p.body_c0[k] = float(v)
+        st = [float(v) for v in (list(body["c"])[:3] + [0.0] * 3)[:3]]
+        st += [float(v) for v in body["q"]]
+        st += [float(v) for v in (list(body["v"]) + [0.0] * 3)[:3]]
+        st += [float(v) for v in (list(body["w"]) + [0.0] * 3)[:3]]
+        for k, v in enumerate(st):
+            p.body_state0[k] = v
     return p
 
 

@@ -60,8 +60,11 @@ struct sph_ctx {
   SortScratch ss;
   Dummies dm;
   Dummies dm2;  // moving body: the dummies' second buffer for their re-sort
-  bool has_body;
+  bool has_body;   // a prescribed or a free body
+  bool free_body;  // body_free
   Body body;
+  FreeBody fbody;
+  double *body_ft;  // free body: force and torque partials (6 per block of dummies)
   Rates r;
   uint32_t *cand, *fallback;
   float *cand_logit;
@@ -155,6 +158,33 @@ bool params_ok(const sph_params *p, std::string *why) {
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p->body_a[k][a]) || !std::isfinite(p->body_b[k][a])) return bad("non-finite body motion");
   }
+  if (p->body_free) {
+    if (p->body_pieces != 0) return bad("a free body excludes a prescribed motion (body_pieces must be 0)");
+    if (p->precision != SPH_FP64) return bad("the free body needs precision SPH_FP64");
+    if (!(p->body_mass > 0.0) || !std::isfinite(p->body_mass)) return bad("body_mass must be finite and > 0");
+    for (int k = 0; k < 6; ++k)
+      if (!std::isfinite(p->body_inertia[k])) return bad("non-finite body_inertia");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(p->body_c0[k])) return bad("non-finite body_c0");
+    for (int k = 0; k < 13; ++k)
+      if (!std::isfinite(p->body_state0[k])) return bad("non-finite body_state0");
+    const double *q = p->body_state0 + 3;
+    if (std::fabs(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] - 1.0) > 1e-12)
+      return bad("body_state0: the quaternion must have unit norm");
+    const double *I = p->body_inertia;
+    if (p->dim == 2) {
+      if (!(I[2] > 0.0)) return bad("body_inertia: zz must be > 0");
+      if (q[1] != 0.0 || q[2] != 0.0 || p->body_state0[9] != 0.0 || p->body_state0[10] != 0.0 ||
+          p->body_state0[11] != 0.0)
+        return bad("2D free body: q = (cos, 0, 0, sin), v_z = 0, omega = (0, 0, wz)");
+    } else {
+      // Sylvester's criterion on the packed xx yy zz xy xz yz tensor
+      const double m2 = I[0] * I[1] - I[3] * I[3];
+      const double m3 = I[0] * (I[1] * I[2] - I[5] * I[5]) - I[3] * (I[3] * I[2] - I[5] * I[4]) +
+                        I[4] * (I[3] * I[5] - I[1] * I[4]);
+      if (!(I[0] > 0.0) || !(m2 > 0.0) || !(m3 > 0.0)) return bad("body_inertia must be positive definite");
+    }
+  }
   return true;
 }
 
@@ -211,7 +241,7 @@ void derive(const sph_params *p, Phys &P, Grid &g) {
   // kept lists need 2h + skin inside it (a small margin keeps the cut away
   // from the rounding of cell indices)
   // (a moving body re-sorts the dummies at every right-hand side: no lists)
-  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u && p->body_pieces == 0;
+  const bool keep = (p->flags & SPH_F_KEEP_LISTS) != 0u && p->body_pieces == 0 && !p->body_free;
   P.skin_max = keep ? std::max(0.0, (double)g.reach * g.R - P.two_h - 1e-6 * g.R) : 0.0;
   // absolute part of the skin: far above the rounding of FP64 positions; on
   // the mixed path, above twice the rounding of the FP32 absolute positions
@@ -302,13 +332,15 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   c->ss.slot = cv.take<uint32_t>(nmax);
   c->ss.count = cv.take<uint32_t>(c->g.nkey + 1);
   c->ss.scan_tmp = cv.take<uint32_t>((int64_t)scan_tmp_words(std::max<int64_t>(c->g.nkey, n + 1)) + 1);
-  const bool body = c->p.body_pieces > 0;
+  const bool body = c->p.body_pieces > 0 || c->p.body_free;
+  const bool fbody = c->p.body_free != 0;
   for (Dummies *d : {&c->dm, &c->dm2}) {
     const bool on = d == &c->dm || body;
     for (int a = 0; a < 3; ++a) {
       d->x[a] = on && a < dim ? f64(nd) : nullptr;
       d->n[a] = on && a < dim ? f64(nd) : nullptr;
       d->x0[a] = body && a < dim ? f64(nd) : nullptr;
+      d->n0[a] = fbody && a < dim ? f64(nd) : nullptr;
     }
     d->m = on ? f64(nd) : nullptr;
     d->phi_in = on ? f64(nd) : nullptr;
@@ -316,6 +348,7 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
     d->src = on ? cv.take<int32_t>(nd) : nullptr;
     d->mov = body ? cv.take<uint8_t>(nd) : nullptr;
   }
+  c->body_ft = fbody ? f64(6 * (int64_t)grid_for(nd)) : nullptr;
   for (int a = 0; a < 3; ++a) {
     c->r.acc[a] = a < dim ? f64(nf) : nullptr;
     c->r.dus[a] = a < dim ? f64(nf) : nullptr;
@@ -344,7 +377,7 @@ size_t carve(sph_ctx *c, uintptr_t base, size_t cap) {
   c->clf.std = cv.take<float>(kNFeat);
   c->sc = cv.take<Scalars>(1);
   // staging: init copies of the inputs, dummy staging, field export, rank scans
-  int64_t per = 8 * (3 * dim + 2) + 1 + 8 * (2 * dim + 2) + 8 + (body ? 8 * dim + 1 : 0);
+  int64_t per = 8 * (3 * dim + 2) + 1 + 8 * (2 * dim + 2) + 8 + (body ? 8 * dim + 1 : 0) + (fbody ? 8 * dim : 0);
   c->stage_bytes = (size_t)n * (size_t)std::max<int64_t>(per + 16, 64 + 8) + ((size_t)16 << 20);
   c->stage = cv.take<unsigned char>((int64_t)c->stage_bytes);
   return cv.off + kAlign;
@@ -420,12 +453,14 @@ sph_status refresh(sph_ctx *c) {
 }
 
 // The moving body at the right-hand side's time: its dummies moved to x0 +
-// D(t_rhs), then all dummies re-sorted by (cell, original index) into the
+// D(t_rhs) (prescribed motion) or to the pose of the free body's current
+// state, then all dummies re-sorted by (cell, original index) into the
 // second buffer (the cell-start table of the dummies is rebuilt).
 sph_status move_body(sph_ctx *c) {
   if (c->nd == 0) return SPH_OK;
   ProfScope ps(c, 2);
-  hipError_t e = launch_body_move(c->body, c->dm, c->nd, c->dim, c->sc, c->s);
+  hipError_t e = c->free_body ? launch_free_body_place(c->dm, c->nd, c->dim, c->sc, c->s)
+                              : launch_body_move(c->body, c->dm, c->nd, c->dim, c->sc, c->s);
   if (e == hipSuccess)
     e = launch_sort_keys(c->g, c->dim, c->dm.x[0], c->dm.x[1], c->dm.x[2], nullptr, c->nd, c->dm.id, c->ss, c->cs_d,
                          c->perm, c->sc, c->s);
@@ -455,6 +490,12 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
       ProfScope ps(c, 1);
       e = launch_mirror_f64(Pw, c->g, c->dm, c->nd, c->rec0, c->rec1, c->rec0 + c->nf, c->rec1 + c->nf, c->cs_f,
                             (uint32_t)c->nf, c->sc, c->s, c->cur.id);
+      // the water's force and torque on the free body at this right-hand side
+      if (e == hipSuccess && c->free_body && c->nd > 0)
+        e = launch_body_force_f64(Pw, c->g, c->dm, c->nd, c->rec0, c->rec1, c->rec0 + c->nf, c->cs_f,
+                                  (uint32_t)c->nf, c->sc, c->body_ft, c->s);
+      if (e == hipSuccess && c->free_body)
+        e = launch_free_body_sum(c->body_ft, c->nd > 0 ? (int64_t)grid_for(c->nd) : 0, c->sc, c->s);
     }
     if (e == hipSuccess) {
       ProfScope ps(c, mode == kPairKept ? 5 : 0);
@@ -628,7 +669,10 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   c->mixed = p->precision != SPH_FP64;
   c->status = SPH_OK;
   c->has_clf = false;
-  c->has_body = p->body_pieces > 0;
+  c->has_body = p->body_pieces > 0 || p->body_free;
+  c->free_body = p->body_free != 0;
+  c->fbody.mass = p->body_mass;
+  for (int k = 0; k < 6; ++k) c->fbody.I[k] = p->body_inertia[k];
   std::memset(&c->body, 0, sizeof(c->body));
   c->body.pieces = p->body_pieces;
   for (int k = 0; k <= p->body_pieces; ++k) c->body.T[k] = p->body_t[k];
@@ -713,6 +757,7 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   dst.id = (uint32_t *)take(sizeof(uint32_t) * nd);
   dst.src = nullptr;
   for (int a = 0; a < 3; ++a) dst.x0[a] = c->has_body && a < dim ? (double *)take(sizeof(double) * nd) : nullptr;
+  for (int a = 0; a < 3; ++a) dst.n0[a] = c->free_body && a < dim ? (double *)take(sizeof(double) * nd) : nullptr;
   dst.mov = c->has_body ? (uint8_t *)take((size_t)nd) : nullptr;
   FluidF64 f0;
   std::memset(&f0, 0, sizeof(f0));
@@ -753,6 +798,11 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   // scalars and the brick order of the sort keys
   Scalars h;
   std::memset(&h, 0, sizeof(h));
+  if (c->free_body) {
+    h.fb_on = 1u;
+    for (int a = 0; a < 3; ++a) h.fb_c0[a] = p->body_c0[a];
+    for (int k = 0; k < 13; ++k) h.fb[k] = h.fb0[k] = p->body_state0[k];
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(c->sc, &h, sizeof(Scalars), hipMemcpyHostToDevice, s);
   const std::vector<uint32_t> ranks = tile_ranks(c->g);
   if (e == hipSuccess)
@@ -884,6 +934,7 @@ sph_status stage_update(sph_ctx *c, int stage) {
   }
   c->umax_fresh = true;
   c->recs_fresh = recs;
+  if (e == hipSuccess && c->free_body) e = launch_free_body_stage(c->fbody, c->P, c->sc, stage, c->s);
   if (e == hipSuccess && c->kent) e = launch_disp_add(c->sc, stage, c->s);
   if (e == hipSuccess && stage == 2) e = launch_advance_time(c->sc, c->s);
   return hip_check(c, e, stage == 1 ? "stage 1" : "stage 2");
@@ -946,6 +997,17 @@ sph_status sph_stats(sph_ctx *c, double out[20]) {
   out[17] = (double)(last_kept ? h.tests_s : h.tests);
   out[18] = (double)(last_kept ? h.pairs : h.pairs_k);
   out[19] = (double)(last_kept ? h.tests : h.tests_k);
+  return c->status != SPH_OK ? c->status : SPH_OK;
+}
+
+sph_status sph_body_state(sph_ctx *c, double out[19]) {
+  if (!c || !out) return SPH_EINVAL;
+  if (!c->free_body) return fail(c, SPH_ESTATE, "no free body");
+  Scalars h;
+  sph_status st = read_scalars(c, &h);
+  if (st != SPH_OK) return st;
+  for (int k = 0; k < 13; ++k) out[k] = h.fb[k];
+  for (int k = 0; k < 6; ++k) out[13 + k] = h.fbF[k];
   return c->status != SPH_OK ? c->status : SPH_OK;
 }
 

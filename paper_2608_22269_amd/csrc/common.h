@@ -140,6 +140,12 @@ struct Scalars {
   // last one that ran from kept lists (k), before the current one
   unsigned long long pairs_s, tests_s, pairs_k, tests_k;
   double body_x[3], body_u[3];  // moving body: displacement and velocity at t_rhs
+  // free body: on/off, centre of its reference pose, state (c, q, v, omega)
+  // at the current right-hand side, its copy of t^n (second stage), and the
+  // water's force and torque of the last right-hand side
+  uint32_t fb_on, fb_pad_;
+  double fb_c0[3];
+  double fb[13], fb0[13], fbF[6];
 };
 
 // Fluid state, FP64 path, sorted by (cell, original index).
@@ -179,6 +185,40 @@ __device__ __forceinline__ void body_force(const Phys &P, double t, double G[3])
   double w2 = P.fomega * P.fomega;
 #pragma unroll
   for (int a = 0; a < 3; ++a) G[a] = P.grav[a] + P.famp[a] * w2 * s;
+}
+
+// Rotation matrix (row-major) of the unit quaternion q = (w, x, y, z).
+// Rounded as written (no contraction): the free body's dummy positions then
+// do not depend on the compiler's choice of fused operations.
+__device__ __forceinline__ void quat_rotation(const double q[4], double R[9]) {
+#pragma clang fp contract(off)
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// R v for a row-major 3x3 R, rounded as written.
+__device__ __forceinline__ void mat3_apply(const double R[9], const double v[3], double out[3]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[a] = R[3 * a] * v[0] + R[3 * a + 1] * v[1] + R[3 * a + 2] * v[2];
+}
+
+// Velocity of the free body's material point at offset d from its centre,
+// v + omega x d (state layout c[3] q[4] v[3] omega[3]), rounded as written.
+__device__ __forceinline__ void free_body_point_velocity(const double fb[13], const double d[3], double U[3]) {
+#pragma clang fp contract(off)
+  const double *v = fb + 7, *w = fb + 10;
+  U[0] = v[0] + (w[1] * d[2] - w[2] * d[1]);
+  U[1] = v[1] + (w[2] * d[0] - w[0] * d[2]);
+  U[2] = v[2] + (w[0] * d[1] - w[1] * d[0]);
 }
 
 // Cell coordinate along one axis, Eq. (ixyz): floor((x - lo) / R) with an

@@ -439,6 +439,8 @@ __global__ void k_split(Phys P, int64_t n, const double *__restrict__ x, const d
       d.mov[k] = kind[i] == 2 ? 1 : 0;
       for (int a = 0; a < dim; ++a) d.x0[a][k] = x[i * dim + a];
     }
+    if (d.n0[0])
+      for (int a = 0; a < dim; ++a) d.n0[a][k] = nrm[i * dim + a];
   }
 }
 
@@ -467,6 +469,8 @@ __global__ void k_gather_dummies(const uint32_t *__restrict__ perm, int64_t nd, 
     dst.mov[k] = src.mov[o];
     for (int a = 0; a < dim; ++a) dst.x0[a][k] = src.x0[a][o];
   }
+  if (src.n0[0])
+    for (int a = 0; a < dim; ++a) dst.n0[a][k] = src.n0[a][o];
 }
 
 hipError_t launch_gather_dummies(const uint32_t *perm, int64_t nd, Dummies src, Dummies dst, int dim, hipStream_t s) {
@@ -515,6 +519,139 @@ __global__ void k_body_move(Body B, Dummies d, int64_t nd, int dim, Scalars *sc)
 hipError_t launch_body_move(const Body &B, const Dummies &d, int64_t nd, int dim, Scalars *sc, hipStream_t s) {
   if (!d.mov) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_body_move, dim3(grid_for(std::max<int64_t>(nd, 1))), dim3(kBlock), 0, s, B, d, nd, dim, sc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- free body
+
+__global__ void k_free_body_place(Dummies d, int64_t nd, int dim, Scalars *sc) {
+#pragma clang fp contract(off)
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nd || !d.mov[k]) return;
+  const double q[4] = {sc->fb[3], sc->fb[4], sc->fb[5], sc->fb[6]};
+  double R[9];
+  quat_rotation(q, R);
+  double d0[3] = {0.0, 0.0, 0.0}, n0[3] = {0.0, 0.0, 0.0}, dr[3], nr[3];
+  for (int a = 0; a < dim; ++a) {
+    d0[a] = d.x0[a][k] - sc->fb_c0[a];
+    n0[a] = d.n0[a][k];
+  }
+  mat3_apply(R, d0, dr);
+  mat3_apply(R, n0, nr);
+  for (int a = 0; a < dim; ++a) {
+    d.x[a][k] = sc->fb[a] + dr[a];
+    d.n[a][k] = nr[a];
+  }
+}
+
+hipError_t launch_free_body_place(const Dummies &d, int64_t nd, int dim, Scalars *sc, hipStream_t s) {
+  if (!d.mov || !d.n0[0]) return hipErrorInvalidValue;
+  if (nd == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_free_body_place, dim3(grid_for(nd)), dim3(kBlock), 0, s, d, nd, dim, sc);
+  return hipGetLastError();
+}
+
+// One block: thread t sums partials t, t + 1024, ... in order, then a fixed
+// tree over the block; the result depends only on the partials' order.
+constexpr int kBodySumThreads = 1024;
+__global__ void __launch_bounds__(kBodySumThreads) k_free_body_sum(const double *__restrict__ ft, int64_t np,
+                                                                    Scalars *sc) {
+  __shared__ double part[6][kBodySumThreads];
+  const int t = threadIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t k = t; k < np; k += kBodySumThreads)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += ft[(size_t)6 * k + c];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) part[c][t] = acc[c];
+  __syncthreads();
+  for (int w = kBodySumThreads / 2; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) part[c][t] += part[c][t + w];
+    __syncthreads();
+  }
+  if (t < 6) sc->fbF[t] = part[t][0];
+}
+
+hipError_t launch_free_body_sum(const double *ft, int64_t np, Scalars *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_free_body_sum, dim3(1), dim3(kBodySumThreads), 0, s, ft, np, sc);
+  return hipGetLastError();
+}
+
+// Rates of the free body's state y = (c, q, v, omega) under the force F and
+// torque T about the centre: dc/dt = v, dv/dt = F / M + G, dq/dt = (0, omega)
+// q / 2 (Hamilton product, omega in the world frame), domega/dt = I_w^-1 (T -
+// omega x I_w omega) with I_w = R I_body R^T (Euler's equations in the world
+// frame).  2D: motion in the plane, rotation about z only.
+__device__ void free_body_rates(const FreeBody &B, int dim, const double y[13], const double F[3],
+                                const double T[3], const double G[3], double r[13]) {
+  const double *q = y + 3, *v = y + 7, *w = y + 10;
+  double R[9];
+  quat_rotation(q, R);
+  // I_w = R I_body R^T
+  const double Ib[9] = {B.I[0], B.I[3], B.I[4], B.I[3], B.I[1], B.I[5], B.I[4], B.I[5], B.I[2]};
+  double RI[9], Iw[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) RI[3 * i + j] = R[3 * i] * Ib[j] + R[3 * i + 1] * Ib[3 + j] + R[3 * i + 2] * Ib[6 + j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Iw[3 * i + j] = RI[3 * i] * R[3 * j] + RI[3 * i + 1] * R[3 * j + 1] + RI[3 * i + 2] * R[3 * j + 2];
+  double Lw[3];
+  mat3_apply(Iw, w, Lw);
+  const double m[3] = {T[0] - (w[1] * Lw[2] - w[2] * Lw[1]), T[1] - (w[2] * Lw[0] - w[0] * Lw[2]),
+                       T[2] - (w[0] * Lw[1] - w[1] * Lw[0])};
+  for (int a = 0; a < 3; ++a) {
+    r[a] = v[a];
+    r[7 + a] = F[a] / B.mass + G[a];
+  }
+  if (dim == 2) {
+    r[2] = r[9] = 0.0;
+    r[10] = r[11] = 0.0;
+    r[12] = m[2] / Iw[8];
+  } else {
+    // I_w^-1 m by the adjugate: I_w is symmetric positive definite
+    const double c00 = Iw[4] * Iw[8] - Iw[5] * Iw[7], c01 = Iw[5] * Iw[6] - Iw[3] * Iw[8],
+                 c02 = Iw[3] * Iw[7] - Iw[4] * Iw[6];
+    const double c11 = Iw[0] * Iw[8] - Iw[2] * Iw[6], c12 = Iw[2] * Iw[3] - Iw[0] * Iw[5];
+    const double c22 = Iw[0] * Iw[4] - Iw[1] * Iw[3];
+    const double det = Iw[0] * c00 + Iw[1] * c01 + Iw[2] * c02;
+    // symmetric: the cofactor matrix is its own transpose
+    r[10] = (c00 * m[0] + c01 * m[1] + c02 * m[2]) / det;
+    r[11] = (c01 * m[0] + c11 * m[1] + c12 * m[2]) / det;
+    r[12] = (c02 * m[0] + c12 * m[1] + c22 * m[2]) / det;
+  }
+  // dq/dt = ((-omega . q_v), q_w omega + omega x q_v) / 2
+  r[3] = -0.5 * (w[0] * q[1] + w[1] * q[2] + w[2] * q[3]);
+  r[4] = 0.5 * (q[0] * w[0] + (w[1] * q[3] - w[2] * q[2]));
+  r[5] = 0.5 * (q[0] * w[1] + (w[2] * q[1] - w[0] * q[3]));
+  r[6] = 0.5 * (q[0] * w[2] + (w[0] * q[2] - w[1] * q[1]));
+}
+
+__global__ void k_free_body_stage(FreeBody B, Phys P, Scalars *sc, int stage) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double G[3], r[13], y[13];
+  body_force(P, sc->t_rhs, G);
+  for (int k = 0; k < 13; ++k) y[k] = sc->fb[k];
+  free_body_rates(B, P.dim, y, sc->fbF, sc->fbF + 3, G, r);
+  const double dt = sc->dt;
+  if (stage == 1) {
+    for (int k = 0; k < 13; ++k) {
+      sc->fb0[k] = y[k];
+      y[k] = y[k] + dt * r[k];
+    }
+  } else {
+    for (int k = 0; k < 13; ++k) y[k] = 0.5 * sc->fb0[k] + 0.5 * (y[k] + dt * r[k]);
+  }
+  const double qn = sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
+  for (int k = 3; k < 7; ++k) y[k] /= qn;
+  bool ok = true;
+  for (int k = 0; k < 13; ++k) ok = ok && isfinite(y[k]);
+  if (!ok) atomicOr(&sc->err, kErrNonFinite);
+  for (int k = 0; k < 13; ++k) sc->fb[k] = y[k];
+}
+
+hipError_t launch_free_body_stage(const FreeBody &B, const Phys &P, Scalars *sc, int stage, hipStream_t s) {
+  hipLaunchKernelGGL(k_free_body_stage, dim3(1), dim3(64), 0, s, B, P, sc, stage);
   return hipGetLastError();
 }
 

@@ -26,9 +26,18 @@ struct Dummies {
   uint32_t *id;
   int32_t *src;  // sorted fluid index of the mirror source, -1 if inactive
   // with a moving body only (else null): positions at the body's reference
-  // time and 1 for the body's dummies (kind 2)
+  // time (or pose) and 1 for the body's dummies (kind 2)
   double *x0[3];
   uint8_t *mov;
+  // with a free body only (else null): normals in the reference pose
+  double *n0[3];
+};
+
+// Constants of the free body: mass, inertia tensor about the centre in the
+// body frame (xx yy zz xy xz yz).
+struct FreeBody {
+  double mass;
+  double I[6];
 };
 
 // Prescribed motion of the body (Sec. 4, aircraft ditching): velocity a_k +
@@ -43,6 +52,12 @@ struct Body {
 hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const double4 *rec0,
                              const double4 *rec1, double4 *drec0, double4 *drec1, const uint32_t *cs_f,
                              uint32_t nf, const Scalars *sc, hipStream_t s, const uint32_t *fid);
+// Force and torque (F, then the torque about sc->fb's centre) of the water on
+// the free body's dummies after the mirror, one partial of 6 doubles per
+// block of kBlock dummy rows (part: 6 grid_for(nd) doubles).
+hipError_t launch_body_force_f64(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const double4 *rec0,
+                                 const double4 *rec1, const double4 *drec0, const uint32_t *cs_f, uint32_t nf,
+                                 const Scalars *sc, double *part, hipStream_t s);
 // pair pass modes: own search; own search keeping its candidate lists for the
 // step's second stage (kept lists kent, sized for kKeepChunks list fills of
 // kPairList entries per lane of the launch, and kcnt, one word of packed
@@ -118,5 +133,14 @@ hipError_t launch_gather_dummies(const uint32_t *perm, int64_t nd, Dummies src, 
 // Moves the body's dummies to their positions of time sc->t_rhs (x0 + D(t))
 // and stores D and the body velocity in sc->body_x / sc->body_u.
 hipError_t launch_body_move(const Body &B, const Dummies &d, int64_t nd, int dim, Scalars *sc, hipStream_t s);
+// Puts the free body's dummies at the pose of sc->fb: x = c + R (x0 - c0),
+// n = R n0.
+hipError_t launch_free_body_place(const Dummies &d, int64_t nd, int dim, Scalars *sc, hipStream_t s);
+// Sums np partials of 6 doubles (force, torque) into sc->fbF in a fixed
+// order (one block).
+hipError_t launch_free_body_sum(const double *ft, int64_t np, Scalars *sc, hipStream_t s);
+// SSP-RK2 stage of the free body's state from the force and torque of the
+// right-hand side just evaluated (stage 1 keeps the state of t^n in sc->fb0).
+hipError_t launch_free_body_stage(const FreeBody &B, const Phys &P, Scalars *sc, int stage, hipStream_t s);
 
 }  // namespace wb

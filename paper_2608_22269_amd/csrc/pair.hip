@@ -109,8 +109,19 @@ __global__ void __launch_bounds__(256) k_mirror_f64(Phys P, Grid g, Dummies d, i
   double nx = d.n[0][k], ny = d.n[1][k], nz = DIM == 3 ? d.n[2][k] : 0.0;
   double un;
   if (d.mov != nullptr && d.mov[k]) {
-    un = (f1.x - sc->body_u[0]) * nx + (f1.y - sc->body_u[1]) * ny;
-    if (DIM == 3) un += (f1.z - sc->body_u[2]) * nz;
+    double Uw[3] = {sc->body_u[0], sc->body_u[1], sc->body_u[2]};
+    if (sc->fb_on) {
+      // free body: v + omega x R (x0 - c0) at this dummy
+      double q[4] = {sc->fb[3], sc->fb[4], sc->fb[5], sc->fb[6]}, R[9];
+      quat_rotation(q, R);
+      const double d0[3] = {d.x0[0][k] - sc->fb_c0[0], d.x0[1][k] - sc->fb_c0[1],
+                            DIM == 3 ? d.x0[2][k] - sc->fb_c0[2] : 0.0};
+      double dr[3];
+      mat3_apply(R, d0, dr);
+      free_body_point_velocity(sc->fb, dr, Uw);
+    }
+    un = (f1.x - Uw[0]) * nx + (f1.y - Uw[1]) * ny;
+    if (DIM == 3) un += (f1.z - Uw[2]) * nz;
   } else {
     un = f1.x * nx + f1.y * ny + f1.z * nz;
   }
@@ -636,6 +647,90 @@ hipError_t launch_mirror_f64(const Phys &P, const Grid &g, const Dummies &d, int
   else
     hipLaunchKernelGGL(k_mirror_f64<3>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec0, rec1, drec0, drec1,
                        cs_f, nf, sc, fid);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------- free body force
+
+// Force and torque of the water on the free body: each of its dummies takes
+// the conservative-form acceleration of Eq. (sph) (the branch of Sec. 2.3)
+// that a dummy with mirrored potential phi_d gets from its fluid neighbours,
+// a_d = -sum_i (phi_i + phi_d) grad_d W_di V_i, times its mass, and its
+// moment about the body's centre.  Dummies without a mirror source (in no
+// fluid particle's support) and all other rows add nothing.  Each block sums
+// its rows by a fixed tree and writes one partial (6 doubles, F then the
+// torque) to part[6 blockIdx.x ..]: the sums depend only on the rows' order.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_body_force_f64(Phys P, Grid g, Dummies d, int64_t nd,
+                                                        const double4 *__restrict__ rec0,
+                                                        const double4 *__restrict__ rec1,
+                                                        const double4 *__restrict__ drec0,
+                                                        const uint32_t *__restrict__ cs_f, uint32_t nf,
+                                                        const Scalars *__restrict__ sc, double *__restrict__ part) {
+  __shared__ double red[6][256];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double f[3] = {0.0, 0.0, 0.0}, tq[3] = {0.0, 0.0, 0.0};
+  if (k < nd && d.mov[k] && d.src[k] >= 0) {
+    const double4 me = drec0[k];  // placed position and mirrored potential
+    RowWalker w;
+    walker_init<DIM>(w, g, me.x, me.y, me.z, P.win);
+    double a[3] = {0.0, 0.0, 0.0};
+    auto sum_run = [&](uint32_t lo, uint32_t hi) {
+      for (uint32_t j = lo; j < hi; ++j) {
+        const double4 b = rec0[j];
+        const double rx = b.x - me.x, ry = b.y - me.y, rz = DIM == 3 ? b.z - me.z : 0.0;
+        const double r2 = dist2_exact<DIM>(rx, ry, rz);
+        if (r2 > P.two_h2) continue;
+        const double t = fma(sqrt(r2), P.m_half_inv_h, 1.0);  // 1 - q/2
+        const double c = (b.w + me.w) * (P.kfac * t * t * t) * rec1[j].w;
+        a[0] -= c * rx;
+        a[1] -= c * ry;
+        if (DIM == 3) a[2] -= c * rz;
+      }
+    };
+    if (g.reach == 2) {
+      constexpr int NR = DIM == 3 ? 25 : 5;
+      uint32_t lo[NR], hi[NR];
+      walker_fluid_runs<DIM, NR>(w, g, cs_f, lo, hi);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sum_run(lo[r], hi[r]);
+    } else {
+      while (walker_next<DIM>(w, g, cs_f, cs_f, nf))
+        if (w.cur < nf) sum_run(w.cur, w.end);
+    }
+    const double m = d.m[k];
+    const double arm[3] = {me.x - sc->fb[0], me.y - sc->fb[1], DIM == 3 ? me.z - sc->fb[2] : 0.0};
+    for (int c = 0; c < 3; ++c) f[c] = m * a[c];
+    tq[0] = arm[1] * f[2] - arm[2] * f[1];
+    tq[1] = arm[2] * f[0] - arm[0] * f[2];
+    tq[2] = arm[0] * f[1] - arm[1] * f[0];
+  }
+  const int t = threadIdx.x;
+  for (int c = 0; c < 3; ++c) {
+    red[c][t] = f[c];
+    red[3 + c][t] = tq[c];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + w];
+    __syncthreads();
+  }
+  if (t < 6) part[(size_t)6 * blockIdx.x + t] = red[t][0];
+}
+
+hipError_t launch_body_force_f64(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const double4 *rec0,
+                                 const double4 *rec1, const double4 *drec0, const uint32_t *cs_f, uint32_t nf,
+                                 const Scalars *sc, double *part, hipStream_t s) {
+  if (nd == 0) return hipSuccess;
+  if (!d.mov || !part) return hipErrorInvalidValue;
+  static_assert(kBlock == 256, "the block tree of the body force assumes 256 threads");
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_body_force_f64<2>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec0, rec1, drec0,
+                       cs_f, nf, sc, part);
+  else
+    hipLaunchKernelGGL(k_body_force_f64<3>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec0, rec1, drec0,
+                       cs_f, nf, sc, part);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ class Simulation:
         pd.update(overrides)
         self.params = pd
         self.dim = int(pd["dim"])
-        self.p = L.params_from_dict(pd)
+        self.p = L.params_from_dict(pd, case.get("body"))
         lib = L.lib()
         _check(lib.sph_validate(C.byref(self.p)), "sph_validate")
         kind = np.ascontiguousarray(case["kind"], dtype=np.uint8)
@@ -141,6 +141,14 @@ class Simulation:
                 "n_singular", "pairs", "n_cand", "tests", "n_kept", "n_rebuilt", "pairs_search", "tests_search",
                 "pairs_kept", "tests_kept"]
         return {k: float(out[i]) for i, k in enumerate(keys)}
+
+    def body_state(self):
+        """The free body's state and the water's force and torque of the last
+        right-hand side: {"c", "q", "v", "w", "force", "torque"}."""
+        out = np.zeros(19)
+        _check(L.lib().sph_body_state(self.ctx, out.ctypes.data_as(C.c_void_p)), "sph_body_state", self.ctx)
+        return {"c": out[0:3].copy(), "q": out[3:7].copy(), "v": out[7:10].copy(), "w": out[10:13].copy(),
+                "force": out[13:16].copy(), "torque": out[16:19].copy()}
 
     def profile(self, enable=True):
         _check(L.lib().sph_profile(self.ctx, int(bool(enable))), "sph_profile", self.ctx)

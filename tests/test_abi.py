@@ -116,6 +116,64 @@ def test_body_motion_validation_and_workspace(L):
     assert lib.sph_workspace_bytes(C.byref(kept), nf, nd) == lib.sph_workspace_bytes(C.byref(plain), nf, nd)
 
 
+def _free_case():
+    c = wl.tank2d(dx=0.02, width=1.0, depth=0.6, wall_height=0.7)
+    return wl.with_free_body(c, (0.4, 0.2), (0.6, 0.32), 1500.0)
+
+
+def test_free_body_validation_and_workspace(L):
+    """The free body: FP64 only, no prescribed motion beside it, positive
+    mass, a positive definite inertia tensor, a unit quaternion, planar
+    motion in 2D; it adds the reference normals and the per-dummy force rows
+    to the moving body's workspace."""
+    lib = L.lib()
+    c = _free_case()
+    p = L.params_from_dict(c["params"], c["body"])
+    assert p.body_free == 1 and p.body_state0[3] == 1.0
+    assert lib.sph_validate(C.byref(p)) == L.SPH_OK
+    with pytest.raises(ValueError):
+        L.params_from_dict(c["params"])  # no initial state
+
+    def variant(fn):
+        q = L.params_from_dict(c["params"], c["body"])
+        fn(q)
+        return lib.sph_validate(C.byref(q))
+
+    bad = [
+        lambda q: setattr(q, "precision", L.SPH_MIXED),
+        lambda q: setattr(q, "precision", L.SPH_FP32),
+        lambda q: setattr(q, "body_pieces", 1),
+        lambda q: setattr(q, "body_mass", 0.0),
+        lambda q: setattr(q, "body_mass", float("inf")),
+        lambda q: q.body_inertia.__setitem__(2, 0.0),
+        lambda q: q.body_state0.__setitem__(3, 0.9),          # |q| != 1
+        lambda q: q.body_state0.__setitem__(12, float("nan")),
+        lambda q: q.body_c0.__setitem__(0, float("nan")),
+        lambda q: (q.body_state0.__setitem__(3, 0.6), q.body_state0.__setitem__(4, 0.8)),  # tilts out of plane
+        lambda q: q.body_state0.__setitem__(10, 0.5),         # omega_x in 2D
+    ]
+    for k, fn in enumerate(bad):
+        assert variant(fn) == L.SPH_EINVAL, k
+    # in-plane turn: accepted
+    assert variant(lambda q: (q.body_state0.__setitem__(3, 0.6), q.body_state0.__setitem__(6, 0.8))) == L.SPH_OK
+    # 3D: an indefinite tensor is refused, a rotated box accepted
+    c3 = wl.with_free_body(wl.box3d(0.04, (0.8, 0.6, 0.8), (0.8, 0.6, 0.6)), (0.28, 0.2, 0.24), (0.52, 0.4, 0.4),
+                           1500.0)
+    p3 = L.params_from_dict(c3["params"], c3["body"])
+    assert lib.sph_validate(C.byref(p3)) == L.SPH_OK
+    p3.body_inertia[3] = 2.0 * max(p3.body_inertia[0], p3.body_inertia[1])
+    assert lib.sph_validate(C.byref(p3)) == L.SPH_EINVAL
+    # workspace: the prescribed body's, plus reference normals (2 buffers x
+    # dim doubles), six force partials per block of 256 dummies and the
+    # normals' staging at init
+    nf, nd = int((c["kind"] == 0).sum()), int((c["kind"] != 0).sum())
+    moving = L.params_from_dict(dict({k: v for k, v in c["params"].items() if not k.startswith("body_")},
+                                     body_t=[0.0, 1.0], body_a=[[0.0, 0.0, 0.0]], body_b=[[0.0, 0.0, 0.0]]))
+    extra = lib.sph_workspace_bytes(C.byref(p), nf, nd) - lib.sph_workspace_bytes(C.byref(moving), nf, nd)
+    lo = nd * 2 * 8 * 2 + 6 * 8 * ((nd + 255) // 256)
+    assert lo <= extra <= lo + 8 * 2 * (nf + nd) + 16 * 256
+
+
 def test_single_precision_form_validates_with_kept_lists(L):
     """SPH_FP32 is a valid precision; its kept lists take the workspace of the
     mixed path's; an unknown precision is rejected."""

@@ -50,6 +50,8 @@ def stub_detail():
         "keep_across_steps": {"from_rest": _path(19.5), "moving": _path(22.1), "moving_within_step": _path(28.8)},
         "moving_body": {"n_fluid": 3820800, "fp64": _path(8.0), "mixed": _path(6.8), "motion_cost_ms_per_step": 0.24},
         "mlp_inference_17_5M": {"rows": 17500000, "ms_per_call": 1.52, "hbm_frac": 0.098},
+        "cylinder_entry": {"particles": 17728988, "paper_ms_per_step": 270.31,
+                           "fp64": dict(_path(31.5), body_end={"v": [1e-17, -2e-17, -6.2134567]})},
         "dambreak_detection": {"exact": {"ms_per_step": 2.13}, "learned": {"ms_per_step": 2.08,
                                                                           "misclassification": {"candidates": 21683,
                                                                                                 "misclassified": 15}}},
@@ -88,7 +90,7 @@ def test_line_is_compact_and_complete():
 
 def test_line_without_side_measurements():
     d = stub_detail()
-    for k in ("at_rest", "keep_across_steps", "moving_body", "mlp_inference_17_5M", "dambreak_detection",
+    for k in ("at_rest", "keep_across_steps", "moving_body", "cylinder_entry", "mlp_inference_17_5M", "dambreak_detection",
               "slosh_surface_detection",
               "dambreak_wall_pressure", "spurious_u_tank2d", "spurious_u_bump2d", "hydrostatic_l2_paper_cases",
               "cpu_baseline", "roofline_kept"):

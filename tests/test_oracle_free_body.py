@@ -208,6 +208,29 @@ def test_archimedes(orc, dim):
     assert np.abs(T).max() <= 1e-9 * want * 0.1
 
 
+def _immersed_cylinder(dim):
+    """A solid cylinder (D = 0.05 m; 3D: length 0.06 m along y) at rest in
+    hydrostatic water, centred on a node of the fluid's lattice."""
+    if dim == 2:
+        c = wl.tank2d(dx=0.005, width=0.4, depth=0.3, wall_height=0.35)
+        return wl.with_free_cylinder(c, (0.2, 0.15), 0.05, 1370.0)
+    c = wl.box3d(0.005, (0.2, 0.12, 0.2), (0.2, 0.12, 0.16))
+    return wl.with_free_cylinder(c, (0.1, 0.06, 0.08), 0.05, 1370.0, length=0.06)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_archimedes_cylinder(orc, dim):
+    """The curved body of the water-entry case: buoyancy rho0 g pi R^2 (L)
+    to 2%, no side force or torque beyond rounding (the scene is symmetric)."""
+    c = _immersed_cylinder(dim)
+    r = orc.eval_rates(c)
+    F, T = r["body_force"], r["body_torque"]
+    want = 1000.0 * 9.81 * math.pi * 0.025 ** 2 * (0.06 if dim == 3 else 1.0)
+    assert abs(F[dim - 1] / want - 1.0) <= 0.02, F
+    assert np.abs(F[:dim - 1]).max() <= 1e-9 * want
+    assert np.abs(T).max() <= 1e-9 * want * 0.025
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_force_and_torque_rotate_with_the_scene(orc, dim):
     c = wl.random_potential(wl.random_velocity(wl.jitter(_immersed(dim, tic=True), 0.1, 7), 0.1, 8), 0.5, 9)

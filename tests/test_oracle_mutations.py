@@ -47,6 +47,7 @@ BODY_CHECKS = {
     "slip_3d": lambda: fb.test_slip_relative_to_moving_wall(oracle, 3),
     "archimedes_2d": lambda: fb.test_archimedes(oracle, 2),
     "archimedes_3d": lambda: fb.test_archimedes(oracle, 3),
+    "archimedes_cylinder_2d": lambda: fb.test_archimedes_cylinder(oracle, 2),
     "covariance_3d": lambda: fb.test_force_and_torque_rotate_with_the_scene(oracle, 3),
     "reference_point_3d": lambda: fb.test_torque_reference_point(oracle, 3),
 }
