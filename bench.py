@@ -814,7 +814,7 @@ def main():
             out["ta_busy"] = {"frac": prof["ta_busy_frac"], "from": f"profiles/{key}_slosh3d_pmc.json"}
         return out
 
-    d["roofline"] = roofline(head, "pair_f64", "k_pair_f64<3,false,true,true> (first-stage search + pair pass)")
+    d["roofline"] = roofline(head, "pair_f64", "k_pair_f64<3,true,true> (first-stage search + pair pass)")
     d["data"] = f"synthetic: seeded lattice tank, tank-frame forcing; timed state: {state_desc}"
     d["config"] = {"workload": (f"3D sloshing tank 1.0x0.5x0.56 m, depth 0.28 m, dx={args.dx}: "
                                 f"{case['meta']['n_fluid']} fluid + {case['meta']['n_dummy']} dummies"),
@@ -823,15 +823,15 @@ def main():
                    "second_stage": "kept candidate lists" if args.keep_cell > 0 else "rebuild and search",
                    "parallelism": "single GPU"}
     if "kept_pass" in head:
-        d["roofline_kept"] = roofline(head, "pair_kept_f64", "k_pair_kept_f64<3,false,true> (second stage, kept "
+        d["roofline_kept"] = roofline(head, "pair_kept_f64", "k_pair_kept_f64<3,true> (second stage, kept "
                                       "lists)", kept=True)
     if "mixed" in d["paths"]:
         # non-packed FP32 issues at the FP64 rate on this chip: same peak
         d["roofline_mixed"] = roofline(d["paths"]["mixed"], "pair_mixed",
-                                       "k_pair_mixed<3,false,true,true,false> (first-stage pass, FP32 body + FP64 sums)")
+                                       "k_pair_mixed<3,true,true,false> (first-stage pass, FP32 body + FP64 sums)")
         if "kept_pass" in d["paths"]["mixed"]:
             d["roofline_kept_mixed"] = roofline(d["paths"]["mixed"], "pair_kept_mixed",
-                                                "k_pair_kept_mixed<3,false,true,false> (second stage from the kept "
+                                                "k_pair_kept_mixed<3,true,false> (second stage from the kept "
                                                 "lists)", kept=True)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(args.dx)

@@ -22,7 +22,7 @@ def _path(ms, learned=False):
 
 def _roof(ms):
     return {"bound": "alu", "achieved": 8.5, "peak": 78.6, "unit": "TFLOP/s", "frac": 0.108, "traffic": 1.68e10,
-            "kernel": "k_pair_f64<3,false,true,true> (first-stage search + pair pass)",
+            "kernel": "k_pair_f64<3,true,true> (first-stage search + pair pass)",
             "pair_pass_ms": ms, "pairs_per_launch": 1.395e9, "tests_per_launch": 3.28e9, "tflops_with_tests": 10.2,
             "source_sha": "0123456789abcdef", "valu_issue": {"frac": 0.54}, "ta_busy": {"frac": 0.68}}
 
