@@ -696,9 +696,10 @@ static int scan_region(const orc_params *p, int64_t i, const double *x, const do
 /* One evaluation of the semi-discrete system, Eq. (sph), at time t.  With
  * only != NULL the rates are computed for the fluid particles with only[i]
  * != 0 alone (the others are left zero), from neighbour lists of those
- * particles and of the dummies among their neighbours (cells mode).  Rows of
- * kind 2 (the moving body) hold the body at T_0; they take part at their
- * position of time t, x + D(t). */
+ * particles, of the dummies among their neighbours and, with a free body, of
+ * all of its dummies (cells mode).  Rows of kind 2 (the moving body) hold the
+ * body at T_0 (prescribed motion; they take part at x + D(t)) or in its
+ * reference pose (free body; placed from its state). */
 int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const double *u,
                    const double *phi, const double *mass, const uint8_t *kind, const double *nd_in,
                    double t, int nbr_mode, const uint8_t *only, orc_rates *out, const orc_body *body) {
@@ -752,6 +753,11 @@ int orc_eval_rates(const orc_params *p, int64_t n, const double *x_in, const dou
                 for (int64_t k = off[i]; k < off[i + 1]; ++k)
                     if (kind[ids[k]] != 0) rows[ids[k]] = 1;
             }
+            /* the free body's force and torque sum over all of its dummies:
+             * each needs its own list (mirror source and fluid neighbours) */
+            if (p->body_free)
+                for (int64_t i = 0; i < n; ++i)
+                    if (kind[i] == 2) rows[i] = 1;
             free(off);
             free(ids);
             off = NULL;

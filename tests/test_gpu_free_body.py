@@ -228,3 +228,40 @@ def test_body_state_needs_a_free_body(Sim):
         sim.body_state()
     assert e.value.code == L.SPH_ESTATE
     sim.eval_rates()  # the context stays usable
+
+
+def test_cylinder_entry_full_size_sampled(Sim):
+    """The bench's cylinder entry at the paper's size (15.36M fluid + 2.37M
+    dummies, R = h), the cylinder half submerged (centre at the still
+    surface, the water inside it removed) and entering at 6.22 m/s, at its
+    first right-hand side: the body's force and torque against the oracle's,
+    summed over all 13,736 of its dummies, and 1,500 sampled fluid rows next
+    to the cylinder plus 500 elsewhere, element by element at the parity
+    bar."""
+    from test_gpu_fullsize import _compare_rows
+    from test_gpu_parity import TOL
+    case = wl.cylinder_entry(3, dx=0.0025, gap=-0.025)
+    case = wl.with_params(case, cell_size=case["params"]["h"])
+    case["mass"] = oracle.mass_from_phi(case["params"], case["phi"])
+    rng = np.random.default_rng(41)
+    f = np.nonzero(case["kind"] == 0)[0]
+    c = np.asarray(case["body"]["c"])
+    xf = case["x"][f]
+    h = case["params"]["h"]
+    near = f[(np.abs(xf[:, 0] - c[0]) < 0.025 + 3 * h) & (np.abs(xf[:, 1] - c[1]) < 0.1 + 3 * h)
+             & (xf[:, 2] > c[2] - 0.025 - 3 * h)]
+    rows = np.unique(np.concatenate([rng.choice(near, 1500, replace=False), rng.choice(f, 500, replace=False)]))
+    sim = Sim(case)
+    sim.eval_rates()
+    ref = oracle.eval_rates(case, rows=rows)
+    nnb = _compare_rows(sim, case, ref, rows, TOL, TOL)
+    assert np.array_equal(nnb, ref["nnb"][rows])
+    st = sim.body_state()
+    F, T = ref["body_force"], ref["body_torque"]
+    print("force", st["force"], F, "torque", st["torque"], T)
+    # the hydrostatic part: the buoyancy of the submerged half, to 2%
+    assert abs(F[2] / (1000.0 * 9.81 * 0.5 * math.pi * 0.025 ** 2 * 0.2) - 1.0) <= 0.02, F
+    # the lateral components and the torque cancel by symmetry
+    assert np.abs(st["force"] - F).max() <= 1e-12 * abs(F[2])
+    assert np.abs(st["torque"] - T).max() <= 1e-12 * abs(F[2]) * 0.1
+    sim.close()
