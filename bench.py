@@ -264,12 +264,18 @@ def mlp_inference(n, reps=5):
 
 
 def state_of(sim, case):
-    """A case dict holding the simulation's current fluid state."""
+    """A case dict holding the simulation's current fluid state (and a free
+    body's state; its dummies stay in their reference pose)."""
     c = dict(case)
     c["x"], c["u"], c["phi"], c["mass"] = sim.field("x"), sim.field("u"), sim.field("phi"), sim.field("mass")
-    d = case["kind"] == 1
+    d = case["kind"] != 0
     c["u"][d] = case["u"][d]
     c["phi"][d] = case["phi"][d]
+    if case.get("body") is not None:
+        b = case["kind"] == 2
+        c["x"][b] = case["x"][b]
+        st = sim.body_state()
+        c["body"] = {k: [float(v) for v in st[k]] for k in ("c", "q", "v", "w")}
     c["t"] = sim.stats()["t"]
     return c
 
@@ -282,7 +288,6 @@ def dambreak_detection(spin, steps):
     0.45 m column, dx = 0.008 (mixed precision), after `spin` steps of the
     collapse: step time, detection time per step and misclassification on
     the same state."""
-    import torch
     import workloads as wl
     from paper_2608_22269_amd import Simulation
     clf = load_classifier()
@@ -294,6 +299,17 @@ def dambreak_detection(spin, steps):
     sim.close()
     out = {"workload": (f"3D dam break (held out) tank 2.4x0.7x0.9, column 0.7x0.7x0.45, dx=0.008, "
                         f"{case['meta']['n_fluid']} fluid, after {spin} steps (t = {state['t']:.3f} s)")}
+    out.update(detection_from_state(state, steps, "dam break", clf))
+    return out
+
+
+def detection_from_state(state, steps, label, clf):
+    """Step time and detection time with exact and learned detection from one
+    state, and the learned detector's misclassification on it."""
+    import torch
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    out = {}
     for mode in ("exact", "learned"):
         s2 = Simulation(wl.with_params(state, fs_mode=mode))
         if mode == "learned":
@@ -317,7 +333,28 @@ def dambreak_detection(spin, steps):
             r["misclassification"] = misclassification(s2, state, clf)
         s2.close()
         out[mode] = r
-        log(f"dam break {mode}: {r}")
+        log(f"{label} {mode}: {r}")
+    return out
+
+
+def cylinder_detection(dx, spin, steps):
+    """The learned detector on the cylinder water entry (a splash crown and
+    cavity no training snapshot holds; FP64, the free body): `spin` steps
+    with exact detection from the release, then exact against learned
+    detection from that state."""
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    clf = load_classifier()
+    case = wl.cylinder_entry(3, dx=dx)
+    case = wl.with_params(case, cell_size=case["params"]["h"])
+    sim = Simulation(case)
+    sim.step(spin)
+    state = state_of(sim, case)
+    sim.close()
+    out = {"workload": (f"cylinder entry dx={dx}, {case['meta']['n_fluid']} fluid, after {spin} steps "
+                        f"(t = {state['t'] * 1e3:.2f} ms, body centre {state['body']['c'][2]:.4f} m, "
+                        f"v_z {state['body']['v'][2]:.3f} m/s)")}
+    out.update(detection_from_state(state, steps, "cylinder entry", clf))
     return out
 
 
@@ -628,8 +665,7 @@ def compact_line(d):
             hist = r["step_t_l2_maxu"]
             below = [s for s, _, l2, _ in hist if l2 <= 1e-12]
             at = {int(s): _sig(l2, 2) for s, _, l2, _ in hist if int(s) in (100, 200)}
-            hs[shape] = {"l2_at": at, "last_step_below_1e-12": max(below) if below else 0,
-                         "stop": _short(r["error"], 40)}
+            hs[shape] = {"l2_at": at, "last_step_below_1e-12": max(below) if below else 0}
         hs["constants"] = d["hydrostatic_l2_paper_cases"].get("_constants")
         line["hydrostatic_paper_cases"] = hs
     if d.get("spurious_u_bump2d"):
@@ -653,6 +689,11 @@ def compact_line(d):
         m = d["mlp_inference_17_5M"]
         line["mlp_inference"] = {"rows": m["rows"], "ms_per_call": _sig(m["ms_per_call"]),
                                  "hbm_frac": _sig(m["hbm_frac"], 3)}
+    if d.get("cylinder_detection"):
+        r = d["cylinder_detection"]
+        m = r["learned"]["misclassification"]
+        line["cylinder_heldout_detection"] = {"cand": m["candidates"], "wrong": m["misclassified"],
+                                              "ms": [_sig(r["exact"]["ms_per_step"]), _sig(r["learned"]["ms_per_step"])]}
     if d.get("dambreak_detection"):
         r = d["dambreak_detection"]
         ln = r["learned"]
@@ -711,6 +752,9 @@ def main():
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
                          "mixed_learned: mixed precision with the trained classifier and exact fallback; "
                          "fp32: the single-precision form")
+    ap.add_argument("--cylinder-detect-spin", type=int, default=1000,
+                    help="steps of the cylinder entry before exact and learned detection are compared on its state "
+                         "(0: skip)")
     ap.add_argument("--dambreak-spin", type=int, default=5000,
                     help="steps of the held-out 3D dam break before the exact / learned detection comparison "
                          "(0: skip)")
@@ -763,7 +807,7 @@ def main():
     run_case = rest_case
     if args.state == "moving":
         run_case = wl.random_velocity(wl.jitter(rest_case, 0.05, seed=11), 0.05, seed=12)
-    state_desc = ("lattice jittered by 0.05 dx, velocities 0.05 m/s rms per component (seeded)"
+    state_desc = ("lattice jittered 0.05 dx, velocities 0.05 m/s rms per axis (seeded)"
                   if args.state == "moving" else "hydrostatic lattice at rest")
     d = {"steps": args.steps, "warmup": args.warmup, "paths": {}}
     clf = load_classifier()
@@ -859,6 +903,8 @@ def main():
         d["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:
         d["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)
+    if args.cylinder_detect_spin > 0 and args.cylinder_dx > 0:
+        d["cylinder_detection"] = cylinder_detection(args.cylinder_dx, args.cylinder_detect_spin, 20)
     if args.surface_steps > 0:
         d["slosh_surface_detection"] = slosh_surface_detection(args.dx, args.surface_steps)
     if args.probe_seconds > 0:

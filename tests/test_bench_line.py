@@ -50,6 +50,8 @@ def stub_detail():
         "keep_across_steps": {"from_rest": _path(19.5), "moving": _path(22.1), "moving_within_step": _path(28.8)},
         "moving_body": {"n_fluid": 3820800, "fp64": _path(8.0), "mixed": _path(6.8), "motion_cost_ms_per_step": 0.24},
         "mlp_inference_17_5M": {"rows": 17500000, "ms_per_call": 1.52, "hbm_frac": 0.098},
+        "cylinder_detection": {"exact": {"ms_per_step": 29.5}, "learned": {"ms_per_step": 29.2, "misclassification": {
+            "candidates": 93000, "misclassified": 12}}},
         "cylinder_entry": {"particles": 17728988, "paper_ms_per_step": 270.31,
                            "fp64": dict(_path(31.5), body_end={"v": [1e-17, -2e-17, -6.2134567]})},
         "dambreak_detection": {"exact": {"ms_per_step": 2.13}, "learned": {"ms_per_step": 2.08,
@@ -70,7 +72,7 @@ def stub_detail():
 def test_line_is_compact_and_complete():
     line = bench.compact_line(stub_detail())
     text = json.dumps(line, separators=(",", ":"))  # as bench.py prints it
-    assert len(text) < 3700, len(text)  # the driver keeps the tail of stdout
+    assert len(text) < 3900, len(text)  # the driver keeps the tail of stdout
     back = json.loads(text)
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
               "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
@@ -90,7 +92,8 @@ def test_line_is_compact_and_complete():
 
 def test_line_without_side_measurements():
     d = stub_detail()
-    for k in ("at_rest", "keep_across_steps", "moving_body", "cylinder_entry", "mlp_inference_17_5M", "dambreak_detection",
+    for k in ("at_rest", "keep_across_steps", "moving_body", "cylinder_entry", "cylinder_detection",
+              "mlp_inference_17_5M", "dambreak_detection",
               "slosh_surface_detection",
               "dambreak_wall_pressure", "spurious_u_tank2d", "spurious_u_bump2d", "hydrostatic_l2_paper_cases",
               "cpu_baseline", "roofline_kept"):
