@@ -551,8 +551,8 @@ def moving_body(dx, steps, warmup):
 def cylinder_entry_run(dx, cell, steps, warmup):
     """The paper's cylinder water entry at its size (Sec. 4; dx = D/20 =
     0.0025: 15.36M fluid + 2.37M dummies): a free solid cylinder (D = 0.05 m,
-    L = 0.2 m, density 1370) entering the water at 6.22 m/s, FP64 (the free
-    body's path), its force, torque and state at every right-hand side.  The
+    L = 0.2 m, density 1370) entering the water at 6.22 m/s, FP64 and mixed,
+    its force, torque and state at every right-hand side.  The
     paper's figure for the same case (1000 steps in 270.31 s, FP32, one
     RTX 3090) is context, not a target of the same precision."""
     import workloads as wl
@@ -570,6 +570,8 @@ def cylinder_entry_run(dx, cell, steps, warmup):
            "body_start": body0, "paper_ms_per_step": 270.31, "paper_particles": 17.53e6,
            "paper_note": "1000 steps in 270.31 s on one RTX 3090, FP32 (Sec. 5, efficiency table)"}
     res["fp64"] = run_path(case, "cylinder entry (fp64, free body)", steps, warmup, after=after)
+    res["mixed"] = run_path(wl.with_params(case, precision="mixed"), "cylinder entry (mixed, free body)", steps,
+                            warmup, after=after)
     res["particles"] = res["n_fluid"] + res["n_dummy"]
     res["particle_steps_per_s"] = res["particles"] / (res["fp64"]["ms_per_step"] * 1e-3)
     return res
@@ -683,6 +685,7 @@ def compact_line(d):
     if d.get("cylinder_entry"):
         c = d["cylinder_entry"]
         line["cylinder_entry"] = {"n": c["particles"], "fp64_ms": _sig(c["fp64"]["ms_per_step"]),
+                                  "mixed_ms": _sig(c["mixed"]["ms_per_step"]) if "mixed" in c else None,
                                   "paper_ms_fp32_3090": c["paper_ms_per_step"],
                                   "vz_end": _sig(c["fp64"].get("body_end", {}).get("v", [0, 0, 0])[2], 4)}
     if d.get("mlp_inference_17_5M"):

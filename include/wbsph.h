@@ -135,7 +135,8 @@ typedef struct sph_params {
     double body_b[4][3];
     /* A free rigid body made of the kind-2 dummies (the cylinder water entry
      * of Sec. 4: the body falls under G(t) and the water's force), used when
-     * body_free != 0 (body_pieces must then be 0; precision SPH_FP64 only).
+     * body_free != 0 (body_pieces must then be 0; every precision: the force
+     * is summed in FP64 from the records of the path).
      * The kind-2 rows are given in a reference pose whose centre is body_c0;
      * a body state of centre c and unit quaternion q = (w, x, y, z) puts a
      * dummy given at x_ref, n_ref at c + R(q)(x_ref - body_c0) with normal

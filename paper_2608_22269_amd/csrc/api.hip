@@ -160,7 +160,6 @@ bool params_ok(const sph_params *p, std::string *why) {
   }
   if (p->body_free) {
     if (p->body_pieces != 0) return bad("a free body excludes a prescribed motion (body_pieces must be 0)");
-    if (p->precision != SPH_FP64) return bad("the free body needs precision SPH_FP64");
     if (!(p->body_mass > 0.0) || !std::isfinite(p->body_mass)) return bad("body_mass must be finite and > 0");
     for (int k = 0; k < 6; ++k)
       if (!std::isfinite(p->body_inertia[k])) return bad("non-finite body_inertia");
@@ -506,6 +505,11 @@ sph_status rhs(sph_ctx *c, int stage, int mode = kPairSearch, double win_extra =
     if (e == hipSuccess) {
       ProfScope ps(c, 1);
       e = launch_mirror_mixed(Pw, c->g, c->dm, c->nd, c->mrec, c->cs_f, (uint32_t)c->nf, c->sc, c->s, c->mcur.id);
+      if (e == hipSuccess && c->free_body && c->nd > 0)
+        e = launch_body_force_mixed(Pw, c->g, c->dm, c->nd, c->mrec, c->cs_f, (uint32_t)c->nf, c->sc, c->body_ft,
+                                    c->s);
+      if (e == hipSuccess && c->free_body)
+        e = launch_free_body_sum(c->body_ft, c->nd > 0 ? (int64_t)grid_for(c->nd) : 0, c->sc, c->s);
     }
     if (e == hipSuccess) {
       ProfScope ps(c, mode == kPairKept ? 5 : 0);

@@ -24,6 +24,11 @@ hipError_t launch_reorder_mixed(const Phys &P, const Grid &g, const uint32_t *pe
 hipError_t launch_mirror_mixed(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const MixedRec &rec,
                                const uint32_t *cs_f, uint32_t nf, const Scalars *sc, hipStream_t s,
                                const uint32_t *fid);
+// The free body's force and torque partials from the mixed records (as
+// launch_body_force_f64).
+hipError_t launch_body_force_mixed(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const MixedRec &rec,
+                                   const uint32_t *cs_f, uint32_t nf, const Scalars *sc, double *part,
+                                   hipStream_t s);
 // modes and kept lists as for launch_pair_f64; abs32: the single-precision
 // form of the pair sums (SPH_FP32)
 hipError_t launch_pair_mixed(const Phys &P, const Grid &g, const MixedRec &rec, const uint32_t *cs_f,

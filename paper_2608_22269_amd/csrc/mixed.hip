@@ -257,10 +257,20 @@ __global__ void __launch_bounds__(256) k_mirror_mixed(Phys P, Grid g, Dummies d,
   for (int a = 0; a < DIM; ++a) gp += G[a] * (xs[a] - xfs[a]);
   const double phid = rec.phi[best] + gp;
   const float nx = (float)d.n[0][k], ny = (float)d.n[1][k], nz = DIM == 3 ? (float)d.n[2][k] : 0.f;
-  // slip, relative to the body's velocity for the moving body's dummies
+  // slip, relative to the body's velocity for the moving body's dummies (a
+  // free body: v + omega x R (x0 - c0) at this dummy, formed in FP64)
   const bool mv = d.mov != nullptr && d.mov[k];
-  const float wx = mv ? (float)sc->body_u[0] : 0.f, wy = mv ? (float)sc->body_u[1] : 0.f,
-              wz = mv && DIM == 3 ? (float)sc->body_u[2] : 0.f;
+  double Uw[3] = {sc->body_u[0], sc->body_u[1], sc->body_u[2]};
+  if (mv && sc->fb_on) {
+    double q[4] = {sc->fb[3], sc->fb[4], sc->fb[5], sc->fb[6]}, R[9];
+    quat_rotation(q, R);
+    const double d0[3] = {d.x0[0][k] - sc->fb_c0[0], d.x0[1][k] - sc->fb_c0[1],
+                          DIM == 3 ? d.x0[2][k] - sc->fb_c0[2] : 0.0};
+    double dr[3];
+    mat3_apply(R, d0, dr);
+    free_body_point_velocity(sc->fb, dr, Uw);
+  }
+  const float wx = mv ? (float)Uw[0] : 0.f, wy = mv ? (float)Uw[1] : 0.f, wz = mv && DIM == 3 ? (float)Uw[2] : 0.f;
   const float un = (f1.x - wx) * nx + (f1.y - wy) * ny + (f1.z - wz) * nz;
   const float V = (float)(d.m[k] / (P.rho0 * exp(phid * P.inv_c02)));
   rec.r1[o] = make_float4(f1.x - un * nx, f1.y - un * ny, DIM == 3 ? f1.z - un * nz : 0.f, V);
@@ -275,6 +285,86 @@ hipError_t launch_mirror_mixed(const Phys &P, const Grid &g, const Dummies &d, i
     hipLaunchKernelGGL(k_mirror_mixed<2>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec, cs_f, nf, sc, fid);
   else
     hipLaunchKernelGGL(k_mirror_mixed<3>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec, cs_f, nf, sc, fid);
+  return hipGetLastError();
+}
+
+// The water's force and torque on the free body's dummies from the mixed
+// records, in FP64 as on the FP64 path: fluid positions rebuilt exactly from
+// cell and FP32 offset, potentials in FP64, volumes from the FP32 records.
+// One partial of 6 doubles per block (force, then torque about the body's
+// centre), summed in a fixed tree.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_body_force_mixed(Phys P, Grid g, Dummies d, int64_t nd, MixedRec rec,
+                                                          const uint32_t *__restrict__ cs_f, uint32_t nf,
+                                                          const Scalars *__restrict__ sc, double *__restrict__ part) {
+  __shared__ double red[6][256];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double f[3] = {0.0, 0.0, 0.0}, tq[3] = {0.0, 0.0, 0.0};
+  if (k < nd && d.mov[k] && d.src[k] >= 0) {
+    const double xd = d.x[0][k], yd = d.x[1][k], zd = DIM == 3 ? d.x[2][k] : 0.0;
+    const double phid = rec.phi[nf + (uint32_t)k];
+    RowWalker w;
+    walker_init<DIM>(w, g, xd, yd, zd, P.win);
+    double a[3] = {0.0, 0.0, 0.0};
+    auto sum_run = [&](uint32_t lo, uint32_t hi) {
+      for (uint32_t j = lo; j < hi; ++j) {
+        const float4 r0 = rec.r0[j];
+        const uint32_t fc = __float_as_uint(r0.w);
+        const double rx = pos_of(g.lo[0], g.R, cell_x(fc), r0.x) - xd;
+        const double ry = pos_of(g.lo[1], g.R, cell_y(fc), r0.y) - yd;
+        const double rz = DIM == 3 ? pos_of(g.lo[2], g.R, cell_z(fc), r0.z) - zd : 0.0;
+        const double r2 = dist2_exact<DIM>(rx, ry, rz);
+        if (r2 > P.two_h2) continue;
+        const double t = fma(sqrt(r2), P.m_half_inv_h, 1.0);  // 1 - q/2
+        const double c = (rec.phi[j] + phid) * (P.kfac * t * t * t) * (double)rec.r1[j].w;
+        a[0] -= c * rx;
+        a[1] -= c * ry;
+        if (DIM == 3) a[2] -= c * rz;
+      }
+    };
+    if (g.reach == 2) {
+      constexpr int NR = DIM == 3 ? 25 : 5;
+      uint32_t lo[NR], hi[NR];
+      walker_fluid_runs<DIM, NR>(w, g, cs_f, lo, hi);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sum_run(lo[r], hi[r]);
+    } else {
+      while (walker_next<DIM>(w, g, cs_f, cs_f, nf))
+        if (w.cur < nf) sum_run(w.cur, w.end);
+    }
+    const double m = d.m[k];
+    const double arm[3] = {xd - sc->fb[0], yd - sc->fb[1], DIM == 3 ? zd - sc->fb[2] : 0.0};
+    for (int c = 0; c < 3; ++c) f[c] = m * a[c];
+    tq[0] = arm[1] * f[2] - arm[2] * f[1];
+    tq[1] = arm[2] * f[0] - arm[0] * f[2];
+    tq[2] = arm[0] * f[1] - arm[1] * f[0];
+  }
+  const int t = threadIdx.x;
+  for (int c = 0; c < 3; ++c) {
+    red[c][t] = f[c];
+    red[3 + c][t] = tq[c];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < 6; ++c) red[c][t] += red[c][t + w];
+    __syncthreads();
+  }
+  if (t < 6) part[(size_t)6 * blockIdx.x + t] = red[t][0];
+}
+
+hipError_t launch_body_force_mixed(const Phys &P, const Grid &g, const Dummies &d, int64_t nd, const MixedRec &rec,
+                                   const uint32_t *cs_f, uint32_t nf, const Scalars *sc, double *part,
+                                   hipStream_t s) {
+  if (nd == 0) return hipSuccess;
+  if (!d.mov || !part) return hipErrorInvalidValue;
+  static_assert(kBlock == 256, "the block tree of the body force assumes 256 threads");
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_body_force_mixed<2>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec, cs_f, nf, sc,
+                       part);
+  else
+    hipLaunchKernelGGL(k_body_force_mixed<3>, dim3(grid_for(nd)), dim3(kBlock), 0, s, P, g, d, nd, rec, cs_f, nf, sc,
+                       part);
   return hipGetLastError();
 }
 

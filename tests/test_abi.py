@@ -122,10 +122,10 @@ def _free_case():
 
 
 def test_free_body_validation_and_workspace(L):
-    """The free body: FP64 only, no prescribed motion beside it, positive
-    mass, a positive definite inertia tensor, a unit quaternion, planar
-    motion in 2D; it adds the reference normals and the per-dummy force rows
-    to the moving body's workspace."""
+    """The free body: any precision, no prescribed motion beside it,
+    positive mass, a positive definite inertia tensor, a unit quaternion,
+    planar motion in 2D; it adds the reference normals and the force
+    partials to the moving body's workspace."""
     lib = L.lib()
     c = _free_case()
     p = L.params_from_dict(c["params"], c["body"])
@@ -139,9 +139,9 @@ def test_free_body_validation_and_workspace(L):
         fn(q)
         return lib.sph_validate(C.byref(q))
 
+    for prec in (L.SPH_MIXED, L.SPH_FP32):
+        assert variant(lambda q: setattr(q, "precision", prec)) == L.SPH_OK
     bad = [
-        lambda q: setattr(q, "precision", L.SPH_MIXED),
-        lambda q: setattr(q, "precision", L.SPH_FP32),
         lambda q: setattr(q, "body_pieces", 1),
         lambda q: setattr(q, "body_mass", 0.0),
         lambda q: setattr(q, "body_mass", float("inf")),

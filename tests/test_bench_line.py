@@ -53,7 +53,8 @@ def stub_detail():
         "cylinder_detection": {"exact": {"ms_per_step": 29.5}, "learned": {"ms_per_step": 29.2, "misclassification": {
             "candidates": 93000, "misclassified": 12}}},
         "cylinder_entry": {"particles": 17728988, "paper_ms_per_step": 270.31,
-                           "fp64": dict(_path(31.5), body_end={"v": [1e-17, -2e-17, -6.2134567]})},
+                           "fp64": dict(_path(31.5), body_end={"v": [1e-17, -2e-17, -6.2134567]}),
+                           "mixed": _path(29.5)},
         "dambreak_detection": {"exact": {"ms_per_step": 2.13}, "learned": {"ms_per_step": 2.08,
                                                                           "misclassification": {"candidates": 21683,
                                                                                                 "misclassified": 15}}},

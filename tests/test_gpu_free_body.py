@@ -265,3 +265,31 @@ def test_cylinder_entry_full_size_sampled(Sim):
     assert np.abs(st["force"] - F).max() <= 1e-12 * abs(F[2])
     assert np.abs(st["torque"] - T).max() <= 1e-12 * abs(F[2]) * 0.1
     sim.close()
+
+
+@pytest.mark.parametrize("dim,nsteps", [(2, 40), (3, 8)])
+def test_mixed_free_body_tracks_fp64(Sim, dim, nsteps):
+    """The mixed path (cell + FP32 offset storage, FP32 pair terms, FP64 sums;
+    the body's force summed in FP64 from its records) against the FP64 path on
+    the cylinder entry: the body's state and the fluid after nsteps steps,
+    at the mixed path's bars (positions 1e-7 m, velocities and potentials
+    1e-4 of their maxima); the body's velocity to 1e-6 of its speed and its
+    force to 1e-5 (FP64 sums over records whose offsets carry the FP32
+    rounding, about 1e-7 of a cell)."""
+    case = _entry(dim)
+    sm = Sim(wl.with_params(case, precision="mixed"))
+    sd = Sim(case)
+    sm.step(nsteps)
+    sd.step(nsteps)
+    bm, bd = sm.body_state(), sd.body_state()
+    f = case["kind"] == 0
+    speed = np.abs(bd["v"]).max()
+    err = {"c": np.abs(bm["c"] - bd["c"]).max(), "v": np.abs(bm["v"] - bd["v"]).max() / speed,
+           "F": np.abs(bm["force"] - bd["force"]).max() / np.abs(bd["force"]).max(),
+           "x": np.abs(sm.field("x")[f] - sd.field("x")[f]).max(),
+           "u": np.abs(sm.field("u")[f] - sd.field("u")[f]).max() / np.abs(sd.field("u")[f]).max(),
+           "phi": np.abs(sm.field("phi")[f] - sd.field("phi")[f]).max() / np.abs(sd.field("phi")[f]).max()}
+    print(dim, nsteps, {k: f"{v:.2e}" for k, v in err.items()})
+    assert err["c"] <= 1e-7 and err["x"] <= 1e-7
+    assert err["u"] <= 1e-4 and err["phi"] <= 1e-4
+    assert err["v"] <= 1e-6 and err["F"] <= 1e-5
