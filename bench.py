@@ -358,6 +358,38 @@ def cylinder_detection(dx, spin, steps):
     return out
 
 
+def sloshing_after_spinup(dx, keep_cell, spin, steps, warmup):
+    """The sloshing tank's forced flow itself as the timed state: `spin` steps
+    from the hydrostatic start under the tank-frame forcing (FP64, lists kept
+    across steps with cells of 1.03 h, the fastest exact configuration), then
+    the headline configuration (cells of keep_cell h, one sort per step) and
+    mixed + learned timed from that state, with the learned detector's
+    misclassification on it."""
+    import workloads as wl
+    from paper_2608_22269_amd import Simulation
+    clf = load_classifier()
+    case = wl.slosh3d(dx=dx)
+    h = case["params"]["h"]
+    spin_case = wl.with_params(case, cell_size=1.03 * h, keep_lists=True, keep_across_steps=True)
+    sim = Simulation(spin_case)
+    done = 0
+    while done < spin:
+        k = min(1000, spin - done)
+        sim.step(k)
+        done += k
+        st = sim.stats()
+        log(f"spin-up: {done} steps, t = {st['t']:.4f} s, max |U| {st['umax']:.4f} m/s")
+    state = state_of(sim, case)
+    sim.close()
+    state = wl.with_params(state, cell_size=keep_cell * h, keep_lists=True)
+    out = {"workload": (f"sloshing tank dx={dx} after {spin} forced steps from rest (t = {state['t']:.4f} s, "
+                        f"T_f = {2 * math.pi / case['params']['forcing_omega']:.4f} s)")}
+    out["fp64"] = run_path(state, "fp64 after spin-up", steps, warmup)
+    out["mixed_learned"] = run_path(wl.with_params(state, precision="mixed", fs_mode="learned"),
+                                    "mixed_learned after spin-up", steps, warmup, clf=clf)
+    return out
+
+
 def slosh_surface_detection(dx, steps):
     """The learned detector on the full-size sloshing tank with a moved
     surface, a state no training snapshot holds: the first mode's shape
@@ -692,6 +724,11 @@ def compact_line(d):
         m = d["mlp_inference_17_5M"]
         line["mlp_inference"] = {"rows": m["rows"], "ms_per_call": _sig(m["ms_per_call"]),
                                  "hbm_frac": _sig(m["hbm_frac"], 3)}
+    if d.get("slosh_after_spinup"):
+        r = d["slosh_after_spinup"]
+        line["slosh_after_spinup_ms"] = {"fp64": _sig(r["fp64"]["ms_per_step"]),
+                                         "mixed_learned": _sig(r["mixed_learned"]["ms_per_step"]),
+                                         "wrong": r["mixed_learned"]["misclassification"]["misclassified"]}
     if d.get("cylinder_detection"):
         r = d["cylinder_detection"]
         m = r["learned"]["misclassification"]
@@ -755,6 +792,10 @@ def main():
                     help="fp64: FP64 path, exact detection; mixed: mixed precision, exact detection; "
                          "mixed_learned: mixed precision with the trained classifier and exact fallback; "
                          "fp32: the single-precision form")
+    ap.add_argument("--spinup-steps", type=int, default=0,
+                    help="forced steps of the sloshing tank before a second timing of fp64 and mixed + learned "
+                         "from that state (16760 reach T_f/4 at dx = 0.002; 0: skip; several minutes)")
+    ap.add_argument("--spinup-timed", type=int, default=200, help="timed steps after the spin-up (50 warm-up)")
     ap.add_argument("--cylinder-detect-spin", type=int, default=1000,
                     help="steps of the cylinder entry before exact and learned detection are compared on its state "
                          "(0: skip)")
@@ -906,6 +947,9 @@ def main():
         d["mlp_inference_17_5M"] = mlp_inference(case["meta"]["n_fluid"])
     if args.dambreak_spin > 0:
         d["dambreak_detection"] = dambreak_detection(args.dambreak_spin, 20)
+    if args.spinup_steps > 0:
+        d["slosh_after_spinup"] = sloshing_after_spinup(args.dx, args.keep_cell, args.spinup_steps,
+                                                        args.spinup_timed, 50)
     if args.cylinder_detect_spin > 0 and args.cylinder_dx > 0:
         d["cylinder_detection"] = cylinder_detection(args.cylinder_dx, args.cylinder_detect_spin, 20)
     if args.surface_steps > 0:
