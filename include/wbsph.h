@@ -93,6 +93,13 @@ typedef int32_t sph_status;
                              /* (a step then sorts only when they run out; a    */
                              /* particle that leaves the domain is reported at  */
                              /* the next sort)                                  */
+#define SPH_F_GRAPH 256u     /* sph_step runs pairs of steps as one HIP graph   */
+                             /* captured at its first use (the same kernels in  */
+                             /* the same order as without; recaptured after any */
+                             /* call that changes what a step launches: a right-*/
+                             /* hand side outside sph_step, a new classifier or */
+                             /* dt_override).  Excludes SPH_F_KEEP_LISTS, whose */
+                             /* reuse test reads the device between stages.     */
 
 typedef struct sph_params {
     int32_t dim;        /* 2 or 3; gravity usually along the last axis          */

@@ -28,6 +28,7 @@ SPH_FS_NONE, SPH_FS_EXACT, SPH_FS_LEARNED = 0, 1, 2
 SPH_F_DELTA, SPH_F_PST, SPH_F_TIC, SPH_F_FS_PROJECT, SPH_F_CONT_UNCORR, SPH_F_FEATURES = 1, 2, 4, 8, 16, 32
 SPH_F_KEEP_LISTS = 64
 SPH_F_KEEP_ACROSS_STEPS = 128
+SPH_F_GRAPH = 256
 
 FIELDS = {
     "x": 0, "u": 1, "phi": 2, "rho": 3, "p": 4, "dudt": 5, "dphidt": 6, "delta_u": 7, "lambda": 8,
@@ -136,7 +137,8 @@ def params_from_dict(pd: dict, body: dict | None = None) -> SphParams:
                | (SPH_F_CONT_UNCORR if pd.get("cont_uncorr") else 0)
                | (SPH_F_FEATURES if pd.get("features") else 0)
                | (SPH_F_KEEP_LISTS if pd.get("keep_lists") or pd.get("keep_across_steps") else 0)
-               | (SPH_F_KEEP_ACROSS_STEPS if pd.get("keep_across_steps") else 0))
+               | (SPH_F_KEEP_ACROSS_STEPS if pd.get("keep_across_steps") else 0)
+               | (SPH_F_GRAPH if pd.get("graph") else 0))
     for k in ("dx", "h", "c0", "rho0", "nu", "delta", "cfl", "pst_R", "pst_n", "lambda_tic", "lambda_fs_lo",
               "lambda_fs_hi", "lambda_singular", "forcing_omega", "cell_size"):
         setattr(p, k, float(pd.get(k, 0.0)))

@@ -65,6 +65,16 @@ struct sph_ctx {
   Body body;
   FreeBody fbody;
   double *body_ft;  // free body: force and torque partials (6 per block of dummies)
+  // SPH_F_GRAPH: two steps captured on a stream of the library's own and
+  // replayed on the caller's; valid while the buffers a step swaps are where
+  // they were at the capture (they return there every two steps)
+  hipStream_t cap_s;
+  hipGraphExec_t gexec;
+  bool g_ok;
+  double g_dt;
+  FluidF64 g_cur, g_alt;
+  FluidMixed g_mcur, g_malt;
+  Dummies g_dm, g_dm2;
   Rates r;
   uint32_t *cand, *fallback;
   float *cand_logit;
@@ -148,7 +158,9 @@ bool params_ok(const sph_params *p, std::string *why) {
   if (ncell > 2.0e9) return bad("too many cells");
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(p->gravity[a]) || !std::isfinite(p->forcing_amp[a])) return bad("non-finite body force");
-  if (p->flags & ~255u) return bad("unknown flag bits");
+  if (p->flags & ~511u) return bad("unknown flag bits");
+  if ((p->flags & SPH_F_GRAPH) && (p->flags & SPH_F_KEEP_LISTS))
+    return bad("SPH_F_GRAPH excludes SPH_F_KEEP_LISTS");
   if ((p->flags & SPH_F_KEEP_ACROSS_STEPS) && !(p->flags & SPH_F_KEEP_LISTS))
     return bad("SPH_F_KEEP_ACROSS_STEPS needs SPH_F_KEEP_LISTS");
   if (p->body_pieces < 0 || p->body_pieces > 4) return bad("body_pieces must be 0..4");
@@ -627,6 +639,8 @@ const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 void sph_destroy(sph_ctx *ctx) {
   if (!ctx) return;
+  if (ctx->g_ok) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->cap_s) (void)hipStreamDestroy(ctx->cap_s);
   for (auto ev : ctx->ev_a) (void)hipEventDestroy(ev);
   for (auto ev : ctx->ev_b) (void)hipEventDestroy(ev);
   delete ctx;
@@ -673,6 +687,9 @@ sph_status sph_init(const sph_params *p, int64_t n, const double *x, const doubl
   c->mixed = p->precision != SPH_FP64;
   c->status = SPH_OK;
   c->has_clf = false;
+  c->cap_s = nullptr;
+  c->g_ok = false;
+  c->g_dt = 0.0;
   c->has_body = p->body_pieces > 0 || p->body_free;
   c->free_body = p->body_free != 0;
   c->fbody.mass = p->body_mass;
@@ -944,20 +961,87 @@ sph_status stage_update(sph_ctx *c, int stage) {
   return hip_check(c, e, stage == 1 ? "stage 1" : "stage 2");
 }
 
+// One SSP-RK2 step, launched on c->s.
+sph_status one_step(sph_ctx *c, double dt_override) {
+  sph_status st = umax_of_current(c);
+  if (st == SPH_OK) st = hip_check(c, launch_dt(c->P, c->sc, dt_override, c->s), "time step");
+  if (st == SPH_OK) st = stage_rhs(c, 1);
+  if (st == SPH_OK) st = stage_update(c, 1);
+  if (st == SPH_OK) st = umax_of_current(c);
+  if (st == SPH_OK) st = stage_rhs(c, 2);
+  if (st == SPH_OK) st = stage_update(c, 2);
+  c->cells_current = false;
+  return st;
+}
+
+bool same_bytes(const void *a, const void *b, size_t n) { return std::memcmp(a, b, n) == 0; }
+
+// The buffers a step swaps sit where they sat at the capture.
+bool graph_matches(const sph_ctx *c, double dt_override) {
+  return c->g_ok && c->g_dt == dt_override && same_bytes(&c->cur, &c->g_cur, sizeof(FluidF64)) &&
+         same_bytes(&c->alt, &c->g_alt, sizeof(FluidF64)) && same_bytes(&c->mcur, &c->g_mcur, sizeof(FluidMixed)) &&
+         same_bytes(&c->malt, &c->g_malt, sizeof(FluidMixed)) && same_bytes(&c->dm, &c->g_dm, sizeof(Dummies)) &&
+         same_bytes(&c->dm2, &c->g_dm2, sizeof(Dummies));
+}
+
+void graph_drop(sph_ctx *c) {
+  if (c->g_ok) (void)hipGraphExecDestroy(c->gexec);
+  c->g_ok = false;
+}
+
+// Captures two steps on the library's own stream (nothing runs during the
+// capture; the host-side buffer swaps of the two steps bring every buffer
+// back to where it was).  The first step of a capture recomputes max |U|.
+sph_status graph_capture(sph_ctx *c, double dt_override) {
+  graph_drop(c);
+  if (!c->cap_s) {
+    if (hipStreamCreateWithFlags(&c->cap_s, hipStreamNonBlocking) != hipSuccess) {
+      c->cap_s = nullptr;
+      return fail(c, SPH_EHIP, "graph: stream creation failed");
+    }
+  }
+  c->umax_fresh = false;
+  c->g_cur = c->cur;
+  c->g_alt = c->alt;
+  c->g_mcur = c->mcur;
+  c->g_malt = c->malt;
+  c->g_dm = c->dm;
+  c->g_dm2 = c->dm2;
+  hipStream_t user = c->s;
+  hipError_t e = hipStreamBeginCapture(c->cap_s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_check(c, e, "graph: begin capture");
+  c->s = c->cap_s;
+  sph_status st = one_step(c, dt_override);
+  if (st == SPH_OK) st = one_step(c, dt_override);
+  c->s = user;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(c->cap_s, &graph);
+  if (st != SPH_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_check(c, e, "graph: capture");
+  if (!same_bytes(&c->cur, &c->g_cur, sizeof(FluidF64)) || !same_bytes(&c->dm, &c->g_dm, sizeof(Dummies))) {
+    (void)hipGraphExecDestroy(c->gexec);
+    return fail(c, SPH_EHIP, "graph: two steps did not bring the buffers back");
+  }
+  c->g_ok = true;
+  c->g_dt = dt_override;
+  return SPH_OK;
+}
+
 sph_status sph_step(sph_ctx *c, int32_t nsteps, double dt_override) {
   sph_status st = usable(c);
   if (st != SPH_OK) return st;
   if (nsteps < 0 || !std::isfinite(dt_override)) return fail(c, SPH_EINVAL, "bad nsteps or dt_override");
-  for (int32_t k = 0; k < nsteps && st == SPH_OK; ++k) {
-    st = umax_of_current(c);
-    if (st == SPH_OK) st = hip_check(c, launch_dt(c->P, c->sc, dt_override, c->s), "time step");
-    if (st == SPH_OK) st = stage_rhs(c, 1);
-    if (st == SPH_OK) st = stage_update(c, 1);
-    if (st == SPH_OK) st = umax_of_current(c);
-    if (st == SPH_OK) st = stage_rhs(c, 2);
-    if (st == SPH_OK) st = stage_update(c, 2);
-    c->cells_current = false;
+  if ((c->p.flags & SPH_F_GRAPH) && !c->profiling && nsteps >= 2) {
+    if (!graph_matches(c, dt_override)) st = graph_capture(c, dt_override);
+    for (; nsteps >= 2 && st == SPH_OK; nsteps -= 2)
+      st = hip_check(c, hipGraphLaunch(c->gexec, c->s), "graph launch");
   }
+  for (int32_t k = 0; k < nsteps && st == SPH_OK; ++k) st = one_step(c, dt_override);
   return st;
 }
 
@@ -1022,6 +1106,7 @@ sph_status sph_set_classifier(sph_ctx *c, const float *params, int64_t nparams, 
   if (!params || !mean || !std || nparams != kMlpParams || !(margin >= 0.0f))
     return fail(c, SPH_EINVAL, "classifier: bad parameters");
   if (c->p.fs_mode != SPH_FS_LEARNED) return fail(c, SPH_ESTATE, "classifier needs fs_mode SPH_FS_LEARNED");
+  graph_drop(c);  // the margin and the classifier's presence are launch arguments
   for (int k = 0; k < kNFeat; ++k)
     if (!(std[k] > 0.0f) || !std::isfinite(mean[k])) return fail(c, SPH_EINVAL, "classifier: bad mean/std");
   for (int64_t k = 0; k < nparams; ++k)

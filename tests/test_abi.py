@@ -50,7 +50,12 @@ def test_validate_and_workspace(L):
     q.cell_size = 0.5 * q.h  # reach 4 > 3
     assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
     q = L.params_from_dict(c["params"])
-    q.flags |= 256  # no such flag
+    q.flags |= 512  # no such flag
+    assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
+    q = L.params_from_dict(c["params"])
+    q.flags |= L.SPH_F_GRAPH
+    assert lib.sph_validate(C.byref(q)) == L.SPH_OK
+    q.flags |= L.SPH_F_KEEP_LISTS  # their reuse test reads the device between stages
     assert lib.sph_validate(C.byref(q)) == L.SPH_EINVAL
     q = L.params_from_dict(c["params"])
     q.flags |= L.SPH_F_KEEP_ACROSS_STEPS  # needs SPH_F_KEEP_LISTS
