@@ -36,7 +36,10 @@ def _cases():
     d3 = wl.random_velocity(wl.dambreak3d(dx=0.04), 0.05, 5)
     cyl = wl.cylinder_entry(2, dx=0.005, tank=(0.3,), depth=0.15, wall_height=0.2, ceiling=0.25)
     return [("tank2d", t2), ("dambreak3d-coarse", d3), ("tank2d-mixed", wl.with_params(t2, precision="mixed")),
-            ("cylinder-entry-2d", cyl), ("entry2d-prescribed", wl.entry2d(dx=0.02, **_flags_all()))]
+            ("tank2d-fp32", wl.with_params(t2, precision="fp32")),
+            ("dambreak3d-coarse-mixed", wl.with_params(d3, precision="mixed")),
+            ("cylinder-entry-2d", cyl), ("cylinder-entry-2d-mixed", wl.with_params(cyl, precision="mixed")),
+            ("entry2d-prescribed", wl.entry2d(dx=0.02, **_flags_all()))]
 
 
 CASES = _cases()
