@@ -55,6 +55,8 @@ def stub_detail():
         "cylinder_entry": {"particles": 17728988, "paper_ms_per_step": 270.31,
                            "fp64": dict(_path(31.5), body_end={"v": [1e-17, -2e-17, -6.2134567]}),
                            "mixed": _path(29.5)},
+        "dambreak_obstacle": {"particles": 6837984, "paper_ms_per_step": 79.40, "fp64": _path(11.3),
+                              "mixed": _path(10.4)},
         "dambreak_detection": {"exact": {"ms_per_step": 2.13}, "learned": {"ms_per_step": 2.08,
                                                                           "misclassification": {"candidates": 21683,
                                                                                                 "misclassified": 15}}},
@@ -93,7 +95,7 @@ def test_line_is_compact_and_complete():
 
 def test_line_without_side_measurements():
     d = stub_detail()
-    for k in ("at_rest", "keep_across_steps", "moving_body", "cylinder_entry", "cylinder_detection",
+    for k in ("at_rest", "keep_across_steps", "moving_body", "cylinder_entry", "cylinder_detection", "dambreak_obstacle",
               "mlp_inference_17_5M", "dambreak_detection",
               "slosh_surface_detection",
               "dambreak_wall_pressure", "spurious_u_tank2d", "spurious_u_bump2d", "hydrostatic_l2_paper_cases",

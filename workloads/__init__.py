@@ -204,6 +204,55 @@ def dambreak3d(dx=0.01, tank=(3.22, 1.0, 1.0), column=(1.2, 1.0, 0.55), **kw):
                  desc=f"3D dam break, tank {tank}, column {column}, dx={dx}", **kw)
 
 
+def _floor_obstacle(lo, hi, dx, layers):
+    """Dummy lattice points of a solid box [lo, hi] standing on the floor
+    z = 0 (corners on multiples of dx): the points within `layers` spacings of
+    its side and top faces, each with the outward normal of its nearest of
+    those faces (its bottom face rests on the floor and meets no water)."""
+    lo_ext = (lo[0], lo[1], -(layers + 1) * dx)
+    pts, nrm = _body_box(3, lo_ext, hi, dx, layers)
+    keep = pts[:, 2] > 0.0
+    return pts[keep], nrm[keep]
+
+
+def dambreak_obstacle3d(dx=0.161 / 30, tank=(3.22, 1.0, 2.0), column=(1.228, 1.0, 0.55),
+                        obstacle=((2.3955, 0.2985), (0.161, 0.403, 0.161)), layers=3, **kw):
+    """The paper's 3D dam break against an obstacle (Sec. 4): a water column
+    at rest against the x = 0 wall of a closed reservoir and a box obstacle
+    on the floor downstream, obstacle corner (x, y) and size (dx, dy, dz);
+    every length snapped to the lattice.  At the default spacing (the
+    obstacle 30 particles wide): 4.34M fluid."""
+    for k, v in (("c0", 30.0), ("delta_sph", True), ("pst", True), ("tic", True), ("fs_project", True),
+                 ("cont_uncorr", True), ("fs_mode", "exact")):
+        kw.setdefault(k, v)
+    snap = lambda v: round(v / dx) * dx  # noqa: E731
+    tank = tuple(snap(t) for t in tank)
+    column = tuple(snap(c) for c in column)
+    kw.setdefault("depth", column[2])
+    case = box3d(dx, tank, column, layers=layers, name="dambreak_obstacle3d", **kw)
+    (ox, oy), size = obstacle
+    lo = (snap(ox), snap(oy), 0.0)
+    hi = (lo[0] + snap(size[0]), lo[1] + snap(size[1]), snap(size[2]))
+    xo, no = _floor_obstacle(lo, hi, dx, layers)
+    x = case["x"]
+    inside = (case["kind"] == 0) & np.all((x > np.array(lo) - 0.25 * dx) & (x < np.array(hi) + 0.25 * dx), axis=1)
+    keep = ~inside
+    G = np.asarray(case["params"]["gravity"], dtype=np.float64)
+    H = case["meta"]["H"]
+    c = dict(case)
+    c["x"] = np.concatenate([x[keep], xo])
+    c["u"] = np.concatenate([case["u"][keep], np.zeros_like(xo)])
+    c["phi"] = np.concatenate([case["phi"][keep], xo @ G + H * float(np.linalg.norm(G))])
+    c["kind"] = np.concatenate([case["kind"][keep], np.ones(len(xo), np.uint8)])
+    c["normal"] = np.concatenate([case["normal"][keep], no])
+    meta = dict(case["meta"])
+    meta.update({"n_fluid": int((c["kind"] == 0).sum()), "n_dummy": int((c["kind"] != 0).sum()),
+                 "n_obstacle": int(len(xo)),
+                 "desc": f"3D dam break against an obstacle, tank {tank}, column {column}, obstacle {lo}-{hi}, dx={dx:.6g}"})
+    c["meta"] = meta
+    return c
+
+
 def dambreak2d(dx=0.01, tank=(3.22, 1.0), column=(1.2, 0.55), **kw):
     """2D dam break: the 3D case's vertical section, a column at rest against
     the x = 0 wall of a closed tank (6,600 fluid at dx = 0.01)."""
