@@ -604,6 +604,8 @@ def cylinder_entry_run(dx, cell, steps, warmup):
     res["fp64"] = run_path(case, "cylinder entry (fp64, free body)", steps, warmup, after=after)
     res["mixed"] = run_path(wl.with_params(case, precision="mixed"), "cylinder entry (mixed, free body)", steps,
                             warmup, after=after)
+    res["fp32"] = run_path(wl.with_params(case, precision="fp32"), "cylinder entry (single precision, free body)",
+                           steps, warmup, after=after)
     res["particles"] = res["n_fluid"] + res["n_dummy"]
     res["particle_steps_per_s"] = res["particles"] / (res["fp64"]["ms_per_step"] * 1e-3)
     return res
@@ -630,6 +632,8 @@ def dambreak_obstacle_run(dx, keep_cell, cell, steps, warmup):
            "paper_note": "1000 steps in 79.40 s on one RTX 3090, FP32 (Sec. 5, efficiency table)"}
     res["fp64"] = run_path(case, "dam break + obstacle (fp64)", steps, warmup)
     res["mixed"] = run_path(wl.with_params(case, precision="mixed"), "dam break + obstacle (mixed)", steps, warmup)
+    res["fp32"] = run_path(wl.with_params(case, precision="fp32"), "dam break + obstacle (single precision)", steps,
+                           warmup)
     res["particles"] = res["n_fluid"] + res["n_dummy"]
     return res
 
@@ -743,12 +747,14 @@ def compact_line(d):
         c = d["cylinder_entry"]
         line["cylinder_entry"] = {"n": c["particles"], "fp64_ms": _sig(c["fp64"]["ms_per_step"]),
                                   "mixed_ms": _sig(c["mixed"]["ms_per_step"]) if "mixed" in c else None,
+                                  "fp32_ms": _sig(c["fp32"]["ms_per_step"]) if "fp32" in c else None,
                                   "paper_ms_fp32_3090": c["paper_ms_per_step"],
                                   "vz_end": _sig(c["fp64"].get("body_end", {}).get("v", [0, 0, 0])[2], 4)}
     if d.get("dambreak_obstacle"):
         c = d["dambreak_obstacle"]
         line["dambreak_obstacle"] = {"n": c["particles"], "fp64_ms": _sig(c["fp64"]["ms_per_step"]),
                                      "mixed_ms": _sig(c["mixed"]["ms_per_step"]),
+                                     "fp32_ms": _sig(c["fp32"]["ms_per_step"]) if "fp32" in c else None,
                                      "paper_ms_fp32_3090": c["paper_ms_per_step"]}
     if d.get("mlp_inference_17_5M"):
         m = d["mlp_inference_17_5M"]

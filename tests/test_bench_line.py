@@ -54,9 +54,9 @@ def stub_detail():
             "candidates": 93000, "misclassified": 12}}},
         "cylinder_entry": {"particles": 17728988, "paper_ms_per_step": 270.31,
                            "fp64": dict(_path(31.5), body_end={"v": [1e-17, -2e-17, -6.2134567]}),
-                           "mixed": _path(29.5)},
+                           "mixed": _path(29.5), "fp32": _path(27.1)},
         "dambreak_obstacle": {"particles": 6837984, "paper_ms_per_step": 79.40, "fp64": _path(11.3),
-                              "mixed": _path(10.4)},
+                              "mixed": _path(10.4), "fp32": _path(9.9)},
         "dambreak_detection": {"exact": {"ms_per_step": 2.13}, "learned": {"ms_per_step": 2.08,
                                                                           "misclassification": {"candidates": 21683,
                                                                                                 "misclassified": 15}}},
