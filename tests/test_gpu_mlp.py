@@ -92,6 +92,29 @@ def test_bf16_mfma_inference(learn, n):
     assert np.abs(got - ref).max() <= 3e-2 * scale
 
 
+def test_bf16_inference_full_size_sampled(learn):
+    """The bench's call: the trained classifier over 17.5M rows (the 3D
+    sloshing tank's fluid count; a grid-stride launch of 4,096 blocks over
+    16-row tiles, the last tile ragged), features drawn on the host from the
+    training normalisation; 20,000 rows (the first and last 2,000 and 16,000
+    at random) against the oracle at the BF16 bar."""
+    import torch
+    from bench import load_classifier
+    clf = load_classifier()
+    n = 17_500_003
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((n, 16), dtype=np.float32)
+    X *= np.asarray(clf["std"], np.float32)
+    X += np.asarray(clf["mean"], np.float32)
+    got = learn.infer_bf16(clf["params"], clf["mean"], clf["std"], torch.from_numpy(X).cuda()).cpu().numpy()
+    rows = np.unique(np.concatenate([np.arange(2000), np.arange(n - 2000, n), rng.integers(0, n, 16000)]))
+    ref = omlp.forward(np.asarray(clf["params"], np.float64), X[rows], np.asarray(clf["mean"], np.float32),
+                       np.asarray(clf["std"], np.float32))
+    scale = max(1.0, np.abs(ref).max())
+    assert got.shape == (n,)
+    assert np.abs(got[rows] - ref).max() <= 3e-2 * scale
+
+
 def test_learned_mode_infinite_margin_equals_exact(learn):
     """Every candidate falls back to the exact test: flags identical."""
     from paper_2608_22269_amd import Simulation
