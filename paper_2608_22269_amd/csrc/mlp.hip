@@ -45,7 +45,8 @@ __device__ __forceinline__ float gelu_f(float z) {
 // activations).  Saturates correctly: e -> inf gives 0, e -> 0 gives z.
 __device__ __forceinline__ float gelu_fast(float z) {
   const float k = -2.0f * 0.7978845608028654f * 1.4426950408889634f;  // -2 sqrt(2/pi) log2(e)
-  const float e = __builtin_amdgcn_exp2f(k * z * fmaf(0.044715f, z * z, 1.0f));
+  const float kc = k * 0.044715f;                                       // folded into the cubic term
+  const float e = __builtin_amdgcn_exp2f(z * fmaf(kc, z * z, k));
   return z * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
