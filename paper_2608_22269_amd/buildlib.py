@@ -39,7 +39,25 @@ def build(jobs: int = 8) -> str:
     tmp = LIB + ".tmp"
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
     os.replace(tmp, LIB)
+    build_example()
     return LIB
+
+
+EXAMPLE = os.path.join(LIBDIR, "run_case")
+
+
+def build_example() -> str:
+    """The plain C caller of the library (examples/run_case.c), built with gcc
+    against the HIP runtime API and linked to libwbsph.so next to it."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = EXAMPLE + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+                    "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(rocm, "include"),
+                    os.path.join(HERE, "examples", "run_case.c"), "-o", tmp, "-L" + LIBDIR, "-lwbsph",
+                    "-L" + os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN",
+                    "-Wl,-rpath," + os.path.join(rocm, "lib")], check=True)
+    os.replace(tmp, EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":

@@ -229,3 +229,24 @@ def test_host_validation_before_any_launch(L):
 def test_status_strings(L):
     for code in range(-8, 1):
         assert L.status_string(code)
+
+
+def test_c_caller_rejects_bad_input(tmp_path):
+    """The plain C caller is built next to the library and refuses a
+    malformed case file (exit status 2) before it touches a GPU."""
+    import subprocess
+    from c_caller import EXAMPLE, write_case
+    assert os.path.exists(EXAMPLE), "run __graft_entry__.build() first"
+    r = subprocess.run([EXAMPLE], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage" in r.stderr
+    bad = tmp_path / "bad.case"
+    bad.write_bytes(b"WBSPHCS1" + b"\0" * 8)
+    r = subprocess.run([EXAMPLE, str(bad), str(tmp_path / "out")], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "sph_params" in r.stderr
+    good = tmp_path / "tank.case"
+    write_case(good, wl.tank2d(dx=0.05), 1)
+    with open(good, "r+b") as f:  # a truncated file is refused while reading
+        f.truncate(os.path.getsize(good) - 8)
+    r = subprocess.run([EXAMPLE, str(good), str(tmp_path / "out")], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "cannot read" in r.stderr
+
