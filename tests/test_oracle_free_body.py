@@ -29,7 +29,6 @@ import math
 import numpy as np
 import pytest
 
-import oracle
 import workloads as wl
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
