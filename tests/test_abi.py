@@ -226,6 +226,39 @@ def test_host_validation_before_any_launch(L):
     assert _init(L, c, ws=300) == L.SPH_EWORKSPACE
 
 
+def test_size_limits(L):
+    """The grid's limits (2047 x 2047 x 1023 cells, 2e9 cells with the
+    margin) and the particle limit (n < 2^31: 32-bit indices) are refused
+    on the host."""
+    lib = L.lib()
+    c = wl.box3d(0.02, (0.4, 0.3, 0.4), (0.4, 0.3, 0.2))
+    R = 2.0 * c["params"]["h"]
+
+    def with_cells(ncx, ncy, ncz):
+        q = L.params_from_dict(c["params"])
+        q.cell_size = R
+        for a, nc in enumerate((ncx, ncy, ncz)):
+            q.domain_lo[a] = 0.0
+            q.domain_hi[a] = (nc - 0.5) * R  # floor(span / R) + 1 = nc cells
+        return q
+
+    for a, nmax in enumerate((2047, 2047, 1023)):
+        cells = [12, 12, 12]
+        cells[a] = nmax
+        assert lib.sph_validate(C.byref(with_cells(*cells))) == L.SPH_OK, a
+        cells[a] = nmax + 1
+        assert lib.sph_validate(C.byref(with_cells(*cells))) == L.SPH_EINVAL, a
+    assert lib.sph_validate(C.byref(with_cells(2047, 2047, 400))) == L.SPH_OK
+    assert lib.sph_validate(C.byref(with_cells(2047, 2047, 600))) == L.SPH_EINVAL  # 2.6e9 cells
+    p = L.params_from_dict(c["params"])
+    assert lib.sph_workspace_bytes(C.byref(p), 2 ** 31 - 11, 10) > 0
+    assert lib.sph_workspace_bytes(C.byref(p), 2 ** 31 - 10, 10) == 0
+    ctx = C.c_void_p()
+    assert lib.sph_init(C.byref(p), 2 ** 31, None, None, None, None, None, None, 0, None, 0, None,
+                        C.byref(ctx)) == L.SPH_EINVAL
+    assert not ctx.value
+
+
 def test_status_strings(L):
     for code in range(-8, 1):
         assert L.status_string(code)
