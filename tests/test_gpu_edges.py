@@ -93,6 +93,58 @@ def test_water_without_walls_ragged_sizes(Sim, n):
     sim.close()
 
 
+def _two_blocks_at_the_limit(axis, precision, seed):
+    """A 3D domain with the largest cell count the library accepts along
+    `axis` (2047, 2047, 1023 cells of 2h; 14 on the others) and two jittered
+    3 x 3 x 3 water blocks, one in its first cells and one in its last."""
+    dx = 0.01
+    pd = wl.base_params(3, dx, delta_sph=True, pst=True, tic=True, fs_project=True, cont_uncorr=True,
+                        fs_mode="exact", precision=precision)
+    R = pd["cell_size"]
+    ncell = [14, 14, 14]
+    ncell[axis] = (2047, 2047, 1023)[axis]
+    pd["domain_lo"] = [0.0, 0.0, 0.0]
+    pd["domain_hi"] = [(nc - 0.5) * R for nc in ncell]
+    g = (np.stack(np.meshgrid(*[np.arange(3)] * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5) * dx
+    lo = np.full(3, 0.5 * R)
+    hi = np.full(3, 0.5 * R)
+    hi[axis] = pd["domain_hi"][axis] - 2.75 * dx  # the top layer 0.25 dx inside the last (half) cell
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([lo + g, hi + g]) + rng.normal(0.0, 0.05 * dx, (54, 3))
+    pd["depth"] = 3 * dx
+    phi = 9.81 * (x[:, 2].max() - x[:, 2])
+    return {"params": pd, "x": x, "u": rng.normal(0.0, 0.05, x.shape), "phi": phi, "kind": np.zeros(54, np.uint8),
+            "normal": np.zeros((54, 3)), "mass": None, "t": 0.0, "meta": {"name": "limit"}}
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_water_in_the_last_cells_of_the_largest_grid(Sim, axis):
+    """Cells at the largest index along each axis (the mixed path packs
+    them in 11, 11 and 10 bits): FP64 against the oracle at the parity bars
+    over one right-hand side and two steps; the mixed path's cells and
+    neighbour counts exact."""
+    case = _two_blocks_at_the_limit(axis, "fp64", 80 + axis)
+    c3, _ = oracle.cells(case["params"], case["x"])
+    assert c3[:, axis].max() == (2046, 2046, 1022)[axis]
+    sim = Sim(case)
+    sim.eval_rates()
+    assert np.array_equal(sim.field("cell"), c3)
+    ref = oracle.eval_rates(case)
+    print(axis, compare_rates(sim, case, ref))
+    sim.step(2)
+    out = oracle.step(case, 2)
+    L = max(case["params"]["domain_hi"])
+    assert np.abs(sim.field("x") - out["x"]).max() <= 1e-12 * L
+    assert np.abs(sim.field("u") - out["u"]).max() <= 1e-12 * np.abs(out["u"]).max()
+    sim.close()
+    mixed = _two_blocks_at_the_limit(axis, "mixed", 80 + axis)
+    sm = Sim(mixed)
+    sm.eval_rates()
+    assert np.array_equal(sm.field("cell"), c3)
+    assert np.array_equal(sm.field("nnb"), ref["nnb"])
+    sm.close()
+
+
 def test_coincident_particles_are_reported(Sim):
     """Two fluid particles at one position (r = 0 has no kernel gradient
     direction): the right-hand side flags it and the next synchronising call
