@@ -53,8 +53,11 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, double d) {
   s = t;
 }
 
-// Position along one axis reconstructed in FP64: lo + c R + (o - oc).
+// Position along one axis reconstructed in FP64: (lo + c R) + o, each
+// operation rounded as written (no contraction), as the storage conversion
+// and the field export form it.
 __device__ __forceinline__ double pos_of(double lo, double R, int c, float o) {
+#pragma clang fp contract(off)
   return lo + (double)c * R + (double)o;
 }
 
@@ -62,6 +65,9 @@ __device__ __forceinline__ double pos_of(double lo, double R, int c, float o) {
 
 template <int DIM>
 __global__ void k_to_mixed(Phys P, Grid g, FluidF64 src, int64_t n, FluidMixed dst, Scalars *sc) {
+  // the offset x - (lo + c R) rounded as written (no contraction): the stored
+  // state is then a plain function of the input
+#pragma clang fp contract(off)
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int c[3] = {0, 0, 0};
@@ -999,6 +1005,7 @@ hipError_t launch_stage_mixed(const Phys &P, const Grid &g, const FluidMixed &f,
 
 template <int DIM>
 __global__ void k_fields_mixed(Phys P, Grid g, FluidMixed f, int64_t n, int field, void *dst, uint32_t nout) {
+#pragma clang fp contract(off)
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const uint32_t id = f.id[k];

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from test_gpu_mixed import _own_state_case
+from test_gpu_mixed import _own_state_case, _with_mass
 from test_gpu_parity import _flags_all, compare_rates
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
@@ -105,6 +105,7 @@ def test_body_keep_lists_have_no_effect(Sim):
 
 @pytest.mark.parametrize("name,case", [CASES[1], CASES[3]], ids=[CASES[1][0], CASES[3][0]])
 def test_mixed_body_rates(Sim, name, case):
+    case = _with_mass(case)
     sim = Sim(wl.with_params(case, precision="mixed"))
     sim.eval_rates()
     ref = oracle.eval_rates(_own_state_case(sim, case))

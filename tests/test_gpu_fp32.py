@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from test_gpu_mixed import _own_state_case
+from test_gpu_mixed import _own_state_case, _with_mass
 from test_gpu_parity import _flags_all
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
@@ -58,6 +58,7 @@ def _bar(case):
 
 @pytest.mark.parametrize("name,case", CASES, ids=[c[0] for c in CASES])
 def test_fp32_rates_vs_oracle(Sim, name, case):
+    case = _with_mass(case)
     sim = Sim(wl.with_params(case, precision="fp32"))
     sim.eval_rates()
     ref = oracle.eval_rates(_own_state_case(sim, case))

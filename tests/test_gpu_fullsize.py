@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from test_gpu_mixed import _own_state_case
+from test_gpu_mixed import _own_state_case, _with_mass
 from test_gpu_parity import TOL, _rel, compare_rates
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
@@ -94,10 +94,11 @@ def test_fp64_sloshing_tank_full_size_sampled(Sim, slosh):
 
 def test_mixed_sloshing_tank_full_size_sampled(Sim, slosh):
     rows = _sample(slosh, seed=1)
-    sim = Sim(wl.with_params(slosh, precision="mixed"))
+    case = _with_mass(slosh)
+    sim = Sim(wl.with_params(case, precision="mixed"))
     sim.eval_rates()
-    ref = oracle.eval_rates(_own_state_case(sim, slosh), rows=rows)
-    nnb = _compare_rows(sim, slosh, ref, rows, 2e-5, 1e-5, fs_tie=1e-4, max_ties=len(rows) // 100)
+    ref = oracle.eval_rates(_own_state_case(sim, case), rows=rows)
+    nnb = _compare_rows(sim, case, ref, rows, 2e-5, 1e-5, fs_tie=1e-4, max_ties=len(rows) // 100)
     # FP32 candidate tests may move pairs within ~1e-7 m of 2h in or out
     assert np.abs(nnb.astype(np.int64) - ref["nnb"][rows]).max() <= 1
     sim.close()

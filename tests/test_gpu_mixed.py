@@ -35,21 +35,50 @@ def _mixed(case):
     return wl.with_params(case, precision="mixed")
 
 
-def _own_state_case(sim, case):
-    """The oracle's input: the mixed path's positions, velocities, potential
-    and masses as it stores them."""
+def _with_mass(case):
+    """The case with its masses given explicitly (the default
+    rho0 exp(phi / C0^2) dx^d, evaluated here), so that the stored FP32
+    masses are a function of the input alone."""
     c = dict(case)
-    c["x"] = sim.field("x")
-    c["u"] = sim.field("u")
-    c["phi"] = sim.field("phi")
-    c["mass"] = sim.field("mass")
-    # dummies: their inputs (a moving body's at its reference time; the
-    # oracle places it)
-    d = case["kind"] != 0
-    c["x"][d] = case["x"][d]
-    c["u"][d] = case["u"][d]
-    c["phi"][d] = case["phi"][d]
+    pd = case["params"]
+    c["mass"] = pd["rho0"] * np.exp(case["phi"] / pd["c0"] ** 2) * pd["dx"] ** pd["dim"]
     return c
+
+
+def _stored_state(case):
+    """The state the mixed and single-precision forms store for `case`,
+    formed here from its definition: per axis the cell c = floor((x - lo) / R)
+    and the FP32 offset (x - (lo + c R)), the position (lo + c R) + offset,
+    every operation rounded as written; FP32 velocity and mass; the FP64
+    potential.  Dummies keep their inputs (a moving body's at its reference
+    time; the oracle places it)."""
+    pd = case["params"]
+    dim = pd["dim"]
+    R = pd["cell_size"] if pd["cell_size"] > 0 else 2.0 * pd["h"]
+    lo = np.asarray(pd["domain_lo"][:dim], np.float64)
+    f = case["kind"] == 0
+    c = dict(case)
+    x = case["x"][f]
+    base = lo + np.floor((x - lo) / R) * R
+    c["x"] = case["x"].copy()
+    c["x"][f] = base + (x - base).astype(np.float32).astype(np.float64)
+    c["u"] = case["u"].copy()
+    c["u"][f] = case["u"][f].astype(np.float32).astype(np.float64)
+    c["mass"] = np.asarray(case["mass"], np.float64).copy()
+    c["mass"][f] = c["mass"][f].astype(np.float32).astype(np.float64)
+    return c
+
+
+def _own_state_case(sim, case):
+    """The oracle's input: the stored state of `case` formed on the CPU
+    (`_stored_state`), after checking that the GPU stored exactly that, bit
+    for bit.  `case` carries explicit masses (`_with_mass`)."""
+    assert case.get("mass") is not None, "give the masses explicitly (_with_mass)"
+    ref = _stored_state(case)
+    f = case["kind"] == 0
+    for k in ("x", "u", "phi", "mass"):
+        assert np.array_equal(sim.field(k)[f], ref[k][f]), k
+    return ref
 
 
 CASES = [
@@ -63,6 +92,7 @@ CASES = [
 
 @pytest.mark.parametrize("name,case", CASES, ids=[c[0] for c in CASES])
 def test_mixed_rates_vs_oracle(Sim, name, case):
+    case = _with_mass(case)
     sim = Sim(_mixed(case))
     sim.eval_rates()
     ref = oracle.eval_rates(_own_state_case(sim, case))
@@ -93,8 +123,9 @@ def test_mixed_linear_potential_is_exact(Sim, dim):
     case = _fluid_block(dim, 24 if dim == 2 else 10, 0.01, seed=31)
     case["mass"] = np.full(len(case["x"]), 1000.0 * 0.01 ** dim)
     case = _mixed(case)
+    x_m = _stored_state(case)["x"]  # positions the mixed storage represents exactly
     sim0 = Sim(case)
-    x_m = sim0.field("x")
+    assert np.array_equal(sim0.field("x"), x_m)
     sim0.close()
     rng = np.random.default_rng(32)
     c = rng.normal(size=dim) * 3.0
