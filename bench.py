@@ -860,7 +860,7 @@ def main():
                     help="standalone BF16 MLP inference over as many rows as the tank has fluid particles")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+    ap.add_argument("--detail", default="bench_detail.json",
                     help="file that receives the full record (histories, traces, per-kernel times)")
     args = ap.parse_args()
     if args.gpus != 1:

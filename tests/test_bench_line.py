@@ -68,7 +68,7 @@ def stub_detail():
         "spurious_u_bump2d": {f"{a}/{b}": {"max_u": long_hist, "error": None} for a in ("literal", "tic")
                               for b in ("fp64", "mixed")},
         "hydrostatic_l2_paper_cases": paper,
-        "detail_path": "gpurun_out/bench_detail.json",
+        "detail_path": "bench_detail.json",
     }
 
 
