@@ -1,6 +1,6 @@
 """Pins of the oracle's free rigid body (kind-2 dummies moving under G(t) and
-the water's force and torque; the cylinder water entry of Sec. 4 falls
-"under the balance of gravity force and interaction force with water").
+the water's force and torque; in the cylinder water entry of Sec. 4 the body's
+motion results from its weight and the force the water exerts on it).
 
 * free flight away from the water: the centre follows x0 + v0 t + G t^2 / 2
   and the velocity v0 + G t exactly (SSP-RK2 integrates a constant
