@@ -75,7 +75,7 @@ def stub_detail():
 def test_line_is_compact_and_complete():
     line = bench.compact_line(stub_detail())
     text = json.dumps(line, separators=(",", ":"))  # as bench.py prints it
-    assert len(text) < 3900, len(text)  # the driver keeps the tail of stdout
+    assert len(text) < 3900, len(text)  # a reader that keeps only the tail of stdout still holds all of it
     back = json.loads(text)
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
               "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
